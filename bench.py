@@ -1,0 +1,168 @@
+"""Benchmark: setup (hss_factor) + GMRES solve to 1e-8 on one MI355X.
+
+A step is the whole hot path on one synthetic input: hss_factor of the
+impedance Helmholtz problem (SIPG p=2 on 64x64 elements, 36,864 dofs,
+8 dofs per wavelength, ID tol 1e-4, complex64 factor) followed by
+gmres_solve in complex128 to a true relative residual of 1e-8. The operator
+values and the right-hand side are resident in HBM before the timed region.
+The same steps are timed in the plain FP64 form (complex128 factor) for the
+mixed-versus-FP64 comparison, and the CPU oracle is timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+CLASSES = ["gather", "gj_panel", "gj_rows", "gj_update", "gj_unswap", "schur_gemm", "symm", "omega",
+           "sample_gemm", "sample", "id", "utall", "expand", "judge", "root", "apply", "spmv", "gmres"]
+PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "hbm": 8000.0}
+
+
+def cpu_baseline(P):
+    """The oracle as it stands, on one BLAS thread, on the full workload once."""
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:
+        lim = None
+    from oracle.factor import OracleFactor
+    from oracle.gmres import gmres as ogmres
+    t0 = time.perf_counter()
+    F = OracleFactor(P.op, P.tree, P.tol, seed=P.seed)
+    res = ogmres(F.matvec, F.apply, P.rhs[:, 0], tol=P.gmres_tol, restart=P.restart)
+    dt = time.perf_counter() - t0
+    if lim is not None:
+        lim.unregister() if hasattr(lim, "unregister") else None
+    return dt * 1e3, res.iters
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--roofline-class", default="schur_gemm")
+    ap.add_argument("--profile-all", action="store_true", help="print the time of every kernel class")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1508_07798_amd import hss
+    from workloads import configs
+
+    P = configs.make("helmholtz_p2_64")
+    dev = torch.device("cuda:0")
+    vals = torch.from_numpy(P.op.vals).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(P.rhs[:, 0])).to(dev)
+    kh = P.kappa / P.op.n
+    cls_bit = 1 << (CLASSES.index(args.roofline_class) + 1)
+
+    def step(prec, profile):
+        h = hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, vals_dev=vals, profile=profile,
+                       kappa_h=kh)
+        x, info = h.gmres(b, tol=P.gmres_tol, restart=P.restart)
+        return h, x, info
+
+    def timed(prec, steps, warmup, profile):
+        for _ in range(warmup):
+            h, _, _ = step(prec, profile)
+            h.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = []
+        for _ in range(steps):
+            h, x, info = step(prec, profile)
+            out.append((h, x, info))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        return ms, out
+
+    ms, runs = timed("fp32", args.steps, args.warmup, cls_bit)
+    h, x, info = runs[-1]
+    iters = [r[2][0]["iters"] for r in runs]
+    relres = max(r[2][0]["true_relres"] for r in runs)
+    # dominant-kernel roofline from the HIP events recorded in the timed steps
+    kms = sum(float(r[0].query(f"prof.{args.roofline_class}.ms")[0]) for r in runs)
+    kl = sum(float(r[0].query(f"prof.{args.roofline_class}.launches")[0]) for r in runs)
+    kfl = sum(float(r[0].query(f"prof.{args.roofline_class}.flops")[0]) for r in runs)
+    avg_ms = kms / max(kl, 1)
+    per_launch_flops = kfl / max(kl, 1)
+    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    flops_factor = float(h.query("flops_factor")[0])
+    t_factor = float(np.mean([float(r[0].query("time_factor_ms")[0]) for r in runs]))
+    ranks = h.query("ranks")
+    for r in runs:
+        r[0].close()
+
+    fsteps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
+    ms64, runs64 = timed("fp64", fsteps, 1, 0)
+    iters64 = runs64[-1][2][0]["iters"]
+    t_factor64 = float(np.mean([float(r[0].query("time_factor_ms")[0]) for r in runs64]))
+    for r in runs64:
+        r[0].close()
+
+    if args.profile_all:
+        h, _, _ = step("fp32", 1)
+        tot = {c: float(h.query(f"prof.{c}.ms")[0]) for c in CLASSES}
+        for c in sorted(tot, key=lambda c: -tot[c]):
+            print(f"  {c:12s} {tot[c]:8.3f} ms  launches {int(h.query(f'prof.{c}.launches')[0])}"
+                  f"  flops {h.query(f'prof.{c}.flops')[0]:.3e}", file=sys.stderr)
+        h.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cms, citers = cpu_baseline(P)
+        cpu = {"value": round(cms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+               "sample": "full workload, one step (factor + GMRES), NumPy/SciPy on one BLAS thread",
+               "oracle_gmres_iters": citers}
+
+    out = {
+        "metric": "setup+GMRES time to 1e-8 resid, mixed vs FP64; factor TFLOP/s; GMRES iters",
+        "value": round(ms, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "helmholtz_p2_64: impedance Helmholtz, SIPG p=2, 64x64 elements, 36864 dofs, "
+                               "8 dofs/wavelength, ID tol 1e-4, GMRES(30) to 1e-8",
+                   "global_batch": 1, "parallelism": "single GPU"},
+        "fp64_ms_per_step": round(ms64, 3),
+        "speedup_vs_fp64": round(ms64 / ms, 3),
+        "factor_ms": round(t_factor, 3),
+        "factor_ms_fp64": round(t_factor64, 3),
+        "factor_tflops": round(flops_factor / (t_factor * 1e-3) / 1e12, 4),
+        "gmres_iters": iters[-1],
+        "gmres_iters_fp64": iters64,
+        "true_relres": relres,
+        "max_rank": int(ranks.max()),
+        "roofline": {"bound": "mfma", "kernel": args.roofline_class, "achieved": round(achieved, 3),
+                     "peak": PEAK["mfma_fp32"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK["mfma_fp32"], 4), "traffic": None,
+                     "avg_launch_ms": round(avg_ms, 5), "flops_per_launch": per_launch_flops},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

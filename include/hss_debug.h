@@ -1,0 +1,38 @@
+/*
+ * hss_debug.h -- kernel-level entry points of libhss used by the test suite
+ * to check single building blocks of the factorization on the device.
+ * Same conventions as hss.h (status codes, hss_last_error, column-major,
+ * device pointers, work on `hip_stream`, returns after the stream is synced).
+ *
+ * scalar codes: 0 = float, 1 = double, 2 = complex float, 3 = complex double.
+ */
+#ifndef HSS_DEBUG_H
+#define HSS_DEBUG_H
+
+#include <stdint.h>
+
+#include "hss.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C_b = alpha A_b B_b + beta C_b for b < nbatch (the batched MFMA GEMM of the
+ * Schur updates, equation (32)). Arrays of device pointers and sizes are host
+ * arrays; alpha, beta are (re, im) pairs. */
+hss_status_t hss_debug_gemm(int32_t scalar, int32_t nbatch, const void* const* A, const void* const* B,
+                            void* const* C, const int32_t* M, const int32_t* N, const int32_t* K,
+                            const int32_t* lda, const int32_t* ldb, const int32_t* ldc,
+                            const double* alpha, const double* beta, void* hip_stream);
+
+/* In-place [A_b | B_b] -> [A_b^{-1} | A_b^{-1} B_b] (n_b x (n_b + m_b), ld n_b) by
+ * the blocked Gauss-Jordan elimination with partial pivoting that the
+ * factorization uses for every A^_ii. *singular receives 1 if a pivot was 0. */
+hss_status_t hss_debug_gj(int32_t scalar, int32_t nbatch, void* const* Mat, const int32_t* n,
+                          const int32_t* m, int32_t* singular, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSS_DEBUG_H */

@@ -1,0 +1,269 @@
+// extern "C" entry points: argument checks, status codes, error messages.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "../../include/hss.h"
+#include "common.hpp"
+#include "engine.hpp"
+#include "planner.hpp"
+
+namespace hss {
+void mlp_forward(const float* w, const float* x, int n, float* y, hipStream_t st);
+void mlp_grad(const float* w, const float* x, const float* t, int n, float* grad, double* loss, hipStream_t st);
+void mlp_train(float* w, const float* x, const float* t, int n, int steps, float lr, float* loss_hist,
+               hipStream_t st);
+}  // namespace hss
+
+struct hss_ctx {
+  std::unique_ptr<hss::EngineBase> eng;
+};
+struct hss_plan_ctx {
+  hss::Plan plan;
+};
+
+namespace {
+thread_local std::string g_err;
+
+hss_status_t fail(int code, const std::string& msg) {
+  g_err = msg;
+  return (hss_status_t)code;
+}
+
+template <class F> hss_status_t guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const hss::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(HSS_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(HSS_EDEVICE, e.what());
+  } catch (...) {
+    return fail(HSS_EDEVICE, "unknown error");
+  }
+}
+
+void check_finite_host(const hss_block_op_t& a) {
+  if (a.vals_on_device) return;
+  const int64_t nnzb = a.row_ptr[a.n_el];
+  const int64_t cnt = nnzb * a.q * a.q * (a.dtype == HSS_C128 ? 2 : 1);
+  const double* v = (const double*)a.vals;
+  for (int64_t i = 0; i < cnt; ++i)
+    if (!std::isfinite(v[i])) throw hss::Error(HSS_EINVAL, "operator holds a non-finite value");
+}
+
+void ensure_device() {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) {
+    (void)hipGetLastError();
+    throw hss::Error(HSS_EDEVICE, "no HIP device available");
+  }
+}
+}  // namespace
+
+extern "C" {
+
+void hss_default_opts(hss_opts_t* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->prec = HSS_PREC_FP32;
+  o->p_os = 10;
+  o->l0 = 32;
+  o->max_attempts = 8;
+  o->seed = 1508;
+  o->rank_model = nullptr;
+  o->kappa_h = 0.0;
+  o->hip_stream = nullptr;
+  o->profile = 0;
+}
+
+const char* hss_last_error(void) { return g_err.c_str(); }
+
+hss_status_t hss_factor_batched(int32_t nprob, const hss_block_op_t* A, const hss_tree_t* T, double tol,
+                                const hss_opts_t* o, hss_handle_t* out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> hss_status_t {
+    if (!out) return fail(HSS_EINVAL, "out is null");
+    if (!(tol >= 0) || !std::isfinite(tol)) return fail(HSS_EINVAL, "tol must be finite and >= 0");
+    hss_opts_t opts;
+    hss_default_opts(&opts);
+    if (o) opts = *o;
+    if (opts.p_os < 1 || opts.l0 < 1 || opts.max_attempts < 1) return fail(HSS_EINVAL, "bad options");
+    if (opts.prec != HSS_PREC_FP64 && opts.prec != HSS_PREC_FP32 && opts.prec != HSS_PREC_BF16)
+      return fail(HSS_EINVAL, "unknown precision");
+    hss::Plan plan = hss::make_plan(nprob, A, T);
+    for (int p = 0; p < nprob; ++p) check_finite_host(A[p]);
+    ensure_device();
+    std::unique_ptr<hss_ctx> h(new hss_ctx);
+    h->eng = hss::make_engine(std::move(plan), opts, A[0].dtype == HSS_C128);
+    h->eng->factor(A, tol);
+    *out = h.release();
+    return HSS_OK;
+  });
+}
+
+hss_status_t hss_factor(const hss_block_op_t* A, const hss_tree_t* T, double tol, const hss_opts_t* o,
+                        hss_handle_t* out) {
+  return hss_factor_batched(1, A, T, tol, o, out);
+}
+
+hss_status_t hss_apply(hss_handle_t h, int32_t nrhs, const void* x, int64_t ldx, void* y, int64_t ldy) {
+  return guarded([&]() -> hss_status_t {
+    if (!h || !h->eng) return fail(HSS_EINVAL, "null handle");
+    h->eng->apply(nrhs, x, ldx, y, ldy);
+    return HSS_OK;
+  });
+}
+
+hss_status_t gmres_solve(hss_handle_t h, int32_t nrhs, const void* b, void* x, int64_t ld, double tol,
+                         int32_t restart, int32_t maxit, hss_gmres_info_t* info) {
+  return guarded([&]() -> hss_status_t {
+    if (!h || !h->eng) return fail(HSS_EINVAL, "null handle");
+    if (!info) return fail(HSS_EINVAL, "info is null");
+    if (!(tol > 0)) return fail(HSS_EINVAL, "tol must be > 0");
+    int s = h->eng->gmres(nrhs, b, x, ld, tol, restart, maxit, info);
+    if (s != HSS_OK) return fail(s, "GMRES did not reach the tolerance within maxit");
+    return HSS_OK;
+  });
+}
+
+hss_status_t hss_query(hss_handle_t h, const char* key, double* out, int64_t cap, int64_t* len) {
+  return guarded([&]() -> hss_status_t {
+    if (!h || !h->eng || !key) return fail(HSS_EINVAL, "null handle or key");
+    std::vector<double> v;
+    if (!h->eng->query(key, v)) return fail(HSS_EINVAL, std::string("unknown key ") + key);
+    if (len) *len = (int64_t)v.size();
+    for (int64_t i = 0; i < (int64_t)v.size() && i < cap && out; ++i) out[i] = v[i];
+    return HSS_OK;
+  });
+}
+
+void hss_destroy(hss_handle_t h) {
+  try {
+    delete h;
+  } catch (...) {
+  }
+}
+
+hss_status_t hss_plan_create(const hss_block_op_t* A, const hss_tree_t* T, hss_plan_t* out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> hss_status_t {
+    if (!out) return fail(HSS_EINVAL, "out is null");
+    std::unique_ptr<hss_plan_ctx> p(new hss_plan_ctx);
+    p->plan = hss::make_plan(1, A, T);
+    *out = p.release();
+    return HSS_OK;
+  });
+}
+
+hss_status_t hss_plan_query(hss_plan_t p, const char* key, int32_t node, int64_t* out, int64_t cap, int64_t* len) {
+  return guarded([&]() -> hss_status_t {
+    if (!p || !key) return fail(HSS_EINVAL, "null plan or key");
+    std::vector<int64_t> v;
+    const std::string k(key);
+    if (k == "root") {
+      v = p->plan.roots[0].dofs;
+    } else {
+      int g = p->plan.find(0, node);
+      if (g < 0) return fail(HSS_EINVAL, "no such box");
+      const hss::PNode& n = p->plan.nodes[g];
+      if (k == "idof") v = n.idof;
+      else if (k == "bdof") v = n.bdof;
+      else if (k == "height") v = {n.height};
+      else if (k == "hss") {
+        for (auto& t : n.hss) {
+          v.push_back(t.lo);
+          v.push_back(t.hi);
+          v.push_back(t.left);
+          v.push_back(t.right);
+        }
+      } else {
+        return fail(HSS_EINVAL, "unknown key " + k);
+      }
+    }
+    if (len) *len = (int64_t)v.size();
+    for (int64_t i = 0; i < (int64_t)v.size() && i < cap && out; ++i) out[i] = v[i];
+    return HSS_OK;
+  });
+}
+
+void hss_plan_destroy(hss_plan_t p) { delete p; }
+
+hss_status_t hss_mlp_forward(const float* w, const float* x, int32_t n, float* y, void* stream) {
+  return guarded([&]() -> hss_status_t {
+    if (!w || !x || !y || n < 1) return fail(HSS_EINVAL, "bad mlp arguments");
+    ensure_device();
+    hss::mlp_forward(w, x, n, y, (hipStream_t)stream);
+    return HSS_OK;
+  });
+}
+
+hss_status_t hss_mlp_grad(const float* w, const float* x, const float* t, int32_t n, float* grad, double* loss,
+                          void* stream) {
+  return guarded([&]() -> hss_status_t {
+    if (!w || !x || !t || !grad || !loss || n < 1) return fail(HSS_EINVAL, "bad mlp arguments");
+    ensure_device();
+    hss::mlp_grad(w, x, t, n, grad, loss, (hipStream_t)stream);
+    return HSS_OK;
+  });
+}
+
+hss_status_t hss_mlp_train(float* w, const float* x, const float* t, int32_t n, int32_t steps, float lr,
+                           float* loss_hist, void* stream) {
+  return guarded([&]() -> hss_status_t {
+    if (!w || !x || !t || n < 1 || steps < 0 || !(lr > 0)) return fail(HSS_EINVAL, "bad mlp arguments");
+    ensure_device();
+    hss::mlp_train(w, x, t, n, steps, lr, loss_hist, (hipStream_t)stream);
+    return HSS_OK;
+  });
+}
+
+}  // extern "C"
+
+#include "../../include/hss_debug.h"
+
+namespace hss {
+void debug_gemm(int scalar, int nb, const void* const* A, const void* const* B, void* const* C, const int32_t* M,
+                const int32_t* N, const int32_t* K, const int32_t* lda, const int32_t* ldb, const int32_t* ldc,
+                const double* al, const double* be, hipStream_t st);
+void debug_gj(int scalar, int nb, void* const* Mat, const int32_t* n, const int32_t* m, int32_t* singular,
+              hipStream_t st);
+}  // namespace hss
+
+extern "C" {
+hss_status_t hss_debug_gemm(int32_t scalar, int32_t nbatch, const void* const* A, const void* const* B,
+                            void* const* C, const int32_t* M, const int32_t* N, const int32_t* K,
+                            const int32_t* lda, const int32_t* ldb, const int32_t* ldc, const double* alpha,
+                            const double* beta, void* hip_stream) {
+  return guarded([&]() -> hss_status_t {
+    if (nbatch < 0 || !A || !B || !C || !M || !N || !K || !lda || !ldb || !ldc || !alpha || !beta)
+      return fail(HSS_EINVAL, "bad gemm arguments");
+    for (int b = 0; b < nbatch; ++b)
+      if (M[b] < 0 || N[b] < 0 || K[b] < 0 || lda[b] < std::max(1, M[b]) || ldb[b] < std::max(1, K[b]) ||
+          ldc[b] < std::max(1, M[b]))
+        return fail(HSS_EINVAL, "bad gemm sizes");
+    ensure_device();
+    hss::debug_gemm(scalar, nbatch, A, B, C, M, N, K, lda, ldb, ldc, alpha, beta, (hipStream_t)hip_stream);
+    return HSS_OK;
+  });
+}
+
+hss_status_t hss_debug_gj(int32_t scalar, int32_t nbatch, void* const* Mat, const int32_t* n, const int32_t* m,
+                          int32_t* singular, void* hip_stream) {
+  return guarded([&]() -> hss_status_t {
+    if (nbatch < 0 || !Mat || !n || !m || !singular) return fail(HSS_EINVAL, "bad gj arguments");
+    for (int b = 0; b < nbatch; ++b)
+      if (n[b] < 0 || m[b] < 0) return fail(HSS_EINVAL, "bad gj sizes");
+    ensure_device();
+    hss::debug_gj(scalar, nbatch, Mat, n, m, singular, (hipStream_t)hip_stream);
+    return HSS_OK;
+  });
+}
+}  // extern "C"

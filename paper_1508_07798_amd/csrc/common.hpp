@@ -1,0 +1,136 @@
+// Shared scalar types, traits and error handling for the HSS library.
+#pragma once
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#ifdef __HIPCC__
+#include <hip/hip_runtime.h>
+#define HD __host__ __device__ __forceinline__
+#else
+#define HD inline
+#endif
+
+namespace hss {
+
+// ---------------------------------------------------------------- scalars
+struct cf {
+  float x, y;
+};
+struct cd {
+  double x, y;
+};
+
+HD cf operator+(cf a, cf b) { return {a.x + b.x, a.y + b.y}; }
+HD cf operator-(cf a, cf b) { return {a.x - b.x, a.y - b.y}; }
+HD cf operator-(cf a) { return {-a.x, -a.y}; }
+HD cf operator*(cf a, cf b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+HD cf operator*(float s, cf b) { return {s * b.x, s * b.y}; }
+HD cd operator+(cd a, cd b) { return {a.x + b.x, a.y + b.y}; }
+HD cd operator-(cd a, cd b) { return {a.x - b.x, a.y - b.y}; }
+HD cd operator-(cd a) { return {-a.x, -a.y}; }
+HD cd operator*(cd a, cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+HD cd operator*(double s, cd b) { return {s * b.x, s * b.y}; }
+
+template <class T> struct traits;
+template <> struct traits<float> {
+  using real = float;
+  using wide = double;           // FP64 counterpart
+  static constexpr bool cplx = false;
+  HD static float zero() { return 0.f; }
+  HD static float one() { return 1.f; }
+  HD static float abs2(float a) { return a * a; }
+  HD static float conj(float a) { return a; }
+  HD static float mk(double re, double) { return (float)re; }
+  HD static float re(float a) { return a; }
+  HD static float im(float) { return 0.f; }
+};
+template <> struct traits<double> {
+  using real = double;
+  using wide = double;
+  static constexpr bool cplx = false;
+  HD static double zero() { return 0.0; }
+  HD static double one() { return 1.0; }
+  HD static double abs2(double a) { return a * a; }
+  HD static double conj(double a) { return a; }
+  HD static double mk(double re, double) { return re; }
+  HD static double re(double a) { return a; }
+  HD static double im(double) { return 0.0; }
+};
+template <> struct traits<cf> {
+  using real = float;
+  using wide = cd;
+  static constexpr bool cplx = true;
+  HD static cf zero() { return {0.f, 0.f}; }
+  HD static cf one() { return {1.f, 0.f}; }
+  HD static float abs2(cf a) { return a.x * a.x + a.y * a.y; }
+  HD static cf conj(cf a) { return {a.x, -a.y}; }
+  HD static cf mk(double re, double im) { return {(float)re, (float)im}; }
+  HD static float re(cf a) { return a.x; }
+  HD static float im(cf a) { return a.y; }
+};
+template <> struct traits<cd> {
+  using real = double;
+  using wide = cd;
+  static constexpr bool cplx = true;
+  HD static cd zero() { return {0.0, 0.0}; }
+  HD static cd one() { return {1.0, 0.0}; }
+  HD static double abs2(cd a) { return a.x * a.x + a.y * a.y; }
+  HD static cd conj(cd a) { return {a.x, -a.y}; }
+  HD static cd mk(double re, double im) { return {re, im}; }
+  HD static double re(cd a) { return a.x; }
+  HD static double im(cd a) { return a.y; }
+};
+
+// scalar helpers usable for every T
+HD float sc_mul(float a, float b) { return a * b; }
+HD double sc_mul(double a, double b) { return a * b; }
+HD cf sc_mul(cf a, cf b) { return a * b; }
+HD cd sc_mul(cd a, cd b) { return a * b; }
+HD float sc_inv(float a) { return 1.f / a; }
+HD double sc_inv(double a) { return 1.0 / a; }
+HD cf sc_inv(cf a) {
+  float d = a.x * a.x + a.y * a.y;
+  return {a.x / d, -a.y / d};
+}
+HD cd sc_inv(cd a) {
+  double d = a.x * a.x + a.y * a.y;
+  return {a.x / d, -a.y / d};
+}
+// fused a - b*c
+HD float sc_fms(float a, float b, float c) { return a - b * c; }
+HD double sc_fms(double a, double b, double c) { return a - b * c; }
+HD cf sc_fms(cf a, cf b, cf c) { return a - b * c; }
+HD cd sc_fms(cd a, cd b, cd c) { return a - b * c; }
+// conversions between precisions
+HD double to_wide(float a) { return (double)a; }
+HD double to_wide(double a) { return a; }
+HD cd to_wide(cf a) { return {(double)a.x, (double)a.y}; }
+HD cd to_wide(cd a) { return a; }
+template <class T> HD T narrow(double a);
+template <class T> HD T narrow(cd a);
+template <> HD float narrow<float>(double a) { return (float)a; }
+template <> HD double narrow<double>(double a) { return a; }
+template <> HD cf narrow<cf>(cd a) { return {(float)a.x, (float)a.y}; }
+template <> HD cd narrow<cd>(cd a) { return a; }
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+}  // namespace hss
+
+#ifdef __HIPCC__
+#define HIP_CHECK(expr)                                                                   \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      throw ::hss::Error(-5, std::string(#expr " failed: ") + hipGetErrorString(_e) +     \
+                                 " at " + __FILE__ + ":" + std::to_string(__LINE__));     \
+  } while (0)
+#endif

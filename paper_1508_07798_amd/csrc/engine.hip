@@ -1,0 +1,1387 @@
+// Device engine: factorization (Algorithm 2 in height waves + the root of
+// equation (36)), the inverse-factorization apply and FP64 GMRES.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <deque>
+#include <mutex>
+
+#include "common.hpp"
+#include "engine.hpp"
+#include "k_gather.hpp"
+#include "k_gemm.hpp"
+#include "k_gj.hpp"
+#include "k_hss.hpp"
+#include "k_vec.hpp"
+
+namespace hss {
+
+// ------------------------------------------------------------------ memory
+// Process-wide cache of device blocks: a block freed by a stream is reused by
+// the same stream (stream order keeps that safe) or, after that stream has
+// been synchronised, by any stream.
+namespace {
+struct Block {
+  void* p;
+  size_t n;
+  hipStream_t st;  // stream that freed it; nullptr when clean
+};
+std::mutex g_mu;
+std::vector<Block> g_free;
+
+void* dev_alloc(size_t n, hipStream_t st) {
+  n = (n + 255) & ~size_t(255);
+  if (n == 0) n = 256;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int best = -1;
+    for (size_t i = 0; i < g_free.size(); ++i) {
+      const Block& b = g_free[i];
+      if (b.n >= n && b.n <= 2 * n + (1 << 20) && (b.st == nullptr || b.st == st))
+        if (best < 0 || b.n < g_free[best].n) best = (int)i;
+    }
+    if (best >= 0) {
+      void* p = g_free[best].p;
+      g_free.erase(g_free.begin() + best);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    // release clean cached blocks and retry once
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      for (auto it = g_free.begin(); it != g_free.end();) {
+        if (it->st == nullptr) {
+          (void)hipFree(it->p);
+          it = g_free.erase(it);
+        } else {
+          ++it;
+        }
+      }
+    }
+    (void)hipGetLastError();
+    e = hipMalloc(&p, n);
+    if (e != hipSuccess) throw Error(HSS_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
+  }
+  return p;
+}
+void dev_free(void* p, size_t n, hipStream_t st) {
+  if (!p) return;
+  n = (n + 255) & ~size_t(255);
+  if (n == 0) n = 256;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_free.push_back({p, n, st});
+}
+void mark_clean(hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& b : g_free)
+    if (b.st == st) b.st = nullptr;
+}
+}  // namespace
+
+// Owning list of device allocations of one phase.
+struct Arena {
+  hipStream_t st = nullptr;
+  std::vector<std::pair<void*, size_t>> blocks;
+  template <class X> X* get(size_t count) {
+    size_t n = count * sizeof(X);
+    void* p = dev_alloc(n, st);
+    blocks.push_back({p, n});
+    return (X*)p;
+  }
+  void release() {
+    for (auto& b : blocks) dev_free(b.first, b.second, st);
+    blocks.clear();
+  }
+  ~Arena() { release(); }
+};
+
+// ------------------------------------------------------------------ profiling
+enum Cls {
+  C_GATHER, C_GJ_PANEL, C_GJ_ROWS, C_GJ_UPDATE, C_GJ_UNSWAP, C_SCHUR, C_SYMM, C_OMEGA, C_SAMPLE_GEMM,
+  C_SAMPLE, C_ID, C_UTALL, C_EXPAND, C_JUDGE, C_ROOT, C_APPLY, C_SPMV, C_GMRES, C_NCLS
+};
+static const char* kClsName[C_NCLS] = {"gather", "gj_panel", "gj_rows", "gj_update", "gj_unswap",
+                                       "schur_gemm", "symm", "omega", "sample_gemm", "sample", "id",
+                                       "utall", "expand", "judge", "root", "apply", "spmv", "gmres"};
+
+struct Prof {
+  bool on = false;
+  unsigned mask = ~0u;  // kernel classes that are timed
+  hipStream_t st = nullptr;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Rec> recs;
+  double ms[C_NCLS] = {}, flops[C_NCLS] = {}, bytes[C_NCLS] = {};
+  long launches[C_NCLS] = {};
+  hipEvent_t ev() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      HIP_CHECK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  int start(int cls, double fl, double by) {
+    if (!on || !((mask >> cls) & 1u)) return -1;
+    Rec r{cls, ev(), ev(), fl, by};
+    HIP_CHECK(hipEventRecord(r.a, st));
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void stop(int id) {
+    if (id < 0) return;
+    HIP_CHECK(hipEventRecord(recs[id].b, st));
+  }
+  void collect() {
+    if (!on || recs.empty()) return;
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (auto& r : recs) {
+      float t = 0;
+      HIP_CHECK(hipEventElapsedTime(&t, r.a, r.b));
+      ms[r.cls] += t;
+      flops[r.cls] += r.flops;
+      bytes[r.cls] += r.bytes;
+      launches[r.cls] += 1;
+    }
+    recs.clear();
+    used = 0;
+  }
+  void reset() {
+    collect();
+    for (int i = 0; i < C_NCLS; ++i) ms[i] = flops[i] = bytes[i] = 0, launches[i] = 0;
+  }
+  ~Prof() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+static inline unsigned grid1(int64_t work, int cap = 2048) {
+  int64_t g = (work + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+template <class T> struct Flop {
+  static constexpr double mac = traits<T>::cplx ? 8.0 : 2.0;
+};
+
+// ------------------------------------------------------------------ engine
+template <class T> struct Engine : EngineBase {
+  using W = typename traits<T>::wide;
+  static constexpr bool CX = traits<T>::cplx;
+
+  Plan P;
+  hss_opts_t o;
+  hipStream_t st;
+  int lds_max = 65536;
+  double tol = 0;
+  Prof prof;
+  std::deque<std::vector<char>> keep;  // host staging kept alive until the next sync
+  Arena persist, scratch;
+
+  // operator on the device
+  int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr, *d_dof_elem = nullptr, *d_dof_prob = nullptr;
+  W* d_vals = nullptr;
+  int64_t *d_elem_dof = nullptr, *d_seg_off = nullptr, *d_perm = nullptr;
+  int64_t ntot = 0;
+  int q = 0;
+
+  struct NodeDev {
+    T* G = nullptr;      // [A_ii^{-1} | X], n_i x (n_i + n_b)
+    T* Abi = nullptr;    // n_b x n_i
+    int* piv = nullptr;
+    int64_t* gidx = nullptr;
+    int32_t* src = nullptr;
+    int64_t* bpos = nullptr;  // global tree positions of B
+    T* St = nullptr;          // compressed complement (live during the factorization)
+  };
+  std::vector<NodeDev> nd;
+  struct RootDev {
+    W* R = nullptr;
+    int* piv = nullptr;
+    int64_t* gidx = nullptr;
+    int32_t* src = nullptr;
+    int n = 0;
+  };
+  std::vector<RootDev> rt;
+
+  // diagnostics
+  std::vector<int> rank_v, attempts_v, l_v;
+  std::vector<double> err_v;
+  std::vector<float> tmax_v;
+  int fallbacks = 0, retries = 0;
+  double flops_factor = 0, time_factor_ms = 0;
+  std::vector<float> feat_v;
+
+  // apply
+  struct ApplyWave {
+    GemvDesc<T>* fwd1 = nullptr;
+    GemvDesc<T>* fwd2 = nullptr;
+    GemvDesc<T>* bwd = nullptr;
+    int n = 0, max_ni = 0, max_nb = 0;
+  };
+  std::vector<ApplyWave> aw;
+  GemvDesc<W>* d_rootdesc = nullptr;
+  int max_nr = 0;
+  W *d_r = nullptr, *d_t = nullptr;
+  int work_nrhs = 0;
+  Arena work;
+
+  Engine(Plan&& plan, const hss_opts_t& opts) : P(std::move(plan)), o(opts) {
+    st = (hipStream_t)o.hip_stream;
+    persist.st = scratch.st = work.st = st;
+    // profile: 0 off, 1 every class, otherwise bit (c + 1) selects class c
+    prof.on = o.profile != 0;
+    prof.mask = o.profile == 1 ? ~0u : ((unsigned)o.profile >> 1);
+    prof.st = st;
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      lds_max = v;
+    (void)hipGetLastError();
+    q = P.probs[0].q;
+    for (auto& pr : P.probs)
+      if (pr.q != q) throw Error(HSS_EINVAL, "all problems of a batch must share q");
+    ntot = P.ndof_total;
+    if (lds_max > 65536) {
+      HIP_CHECK(hipFuncSetAttribute((const void*)gj_panel_kernel<T, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 20480));
+      if (!std::is_same<T, W>::value)
+        HIP_CHECK(hipFuncSetAttribute((const void*)gj_panel_kernel<W, true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 20480));
+    }
+  }
+  ~Engine() override {
+    (void)hipStreamSynchronize(st);
+    keep.clear();
+    work.release();
+    scratch.release();
+    persist.release();
+    mark_clean(st);
+  }
+
+  template <class X> X* up(const std::vector<X>& v, Arena& ar) {
+    if (v.empty()) return nullptr;
+    size_t bytes = v.size() * sizeof(X);
+    keep.emplace_back((const char*)v.data(), (const char*)v.data() + bytes);
+    X* d = ar.get<X>(v.size());
+    HIP_CHECK(hipMemcpyAsync(d, keep.back().data(), bytes, hipMemcpyHostToDevice, st));
+    return d;
+  }
+  template <class X> void h2d(X* dst, const std::vector<X>& v) {
+    if (v.empty()) return;
+    size_t bytes = v.size() * sizeof(X);
+    keep.emplace_back((const char*)v.data(), (const char*)v.data() + bytes);
+    HIP_CHECK(hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, st));
+  }
+  void sync() {
+    HIP_CHECK(hipStreamSynchronize(st));
+    keep.clear();
+  }
+  void check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error(HSS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+
+  // ---------------------------------------------------------------- GEMM
+  template <class X>
+  void gemm(const std::vector<GemmDesc>& ds, X alpha, X beta, int cls, Arena& ar) {
+    std::vector<GemmDesc> v;
+    std::vector<int> pre{0};
+    double fl = 0;
+    for (auto& g : ds) {
+      if (g.M <= 0 || g.N <= 0) continue;
+      v.push_back(g);
+      pre.push_back(pre.back() + cdiv(g.M, GBM) * cdiv(g.N, GBN));
+      fl += Flop<X>::mac * (double)g.M * g.N * g.K;
+    }
+    if (v.empty()) return;
+    GemmDesc* dd = up(v, ar);
+    int* dp = up(pre, ar);
+    int id = prof.start(cls, fl, 0);
+    gemm_nn_kernel<X><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), alpha, beta);
+    prof.stop(id);
+    check_launch("gemm");
+    if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_SAMPLE_GEMM) flops_factor += fl;
+  }
+
+  // ---------------------------------------------------------------- GJ
+  // In-place [M_ii | M_ib] -> [M_ii^{-1} | M_ii^{-1} M_ib] for a batch.
+  template <class X>
+  void gauss_jordan(std::vector<GjDesc<X>>& ds, Arena& ar) {
+    if (ds.empty()) return;
+    int nmax = 0, wmax = 0;
+    for (auto& g : ds) nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W);
+    const int sX = (int)sizeof(X);
+    const int avail = (lds_max > 65536 ? lds_max - 20480 : 65536 - 20480);
+    int nb = 32;
+    bool lds = true;
+    while (nb >= 8 && (int64_t)nmax * nb * sX > avail) nb /= 2;
+    if (nb < 8) {
+      nb = 32;
+      lds = false;
+    }
+    // scratch per box
+    for (auto& g : ds) {
+      g.pinv = ar.get<X>((size_t)nb * nb);
+      g.csave = ar.get<X>((size_t)g.n * nb);
+      g.rbuf = ar.get<X>((size_t)nb * g.W);
+      g.gpanel = lds ? nullptr : ar.get<X>((size_t)g.n * nb);
+    }
+    GjDesc<X>* dd = up(ds, ar);
+    const int nn = (int)ds.size();
+    const size_t shm = lds ? (size_t)nmax * nb * sX : 0;
+    for (int j0 = 0; j0 < nmax; j0 += nb) {
+      int id = prof.start(C_GJ_PANEL, 0, 0);
+      if (lds) gj_panel_kernel<X, true><<<nn, 256, shm, st>>>(dd, j0, nb);
+      else gj_panel_kernel<X, false><<<nn, 256, 0, st>>>(dd, j0, nb);
+      prof.stop(id);
+      check_launch("gj_panel");
+      id = prof.start(C_GJ_ROWS, 0, 0);
+      gj_rows_kernel<X><<<dim3(cdiv(wmax, 64), nn), 256, 0, st>>>(dd, j0, nb);
+      prof.stop(id);
+      check_launch("gj_rows");
+      std::vector<GemmDesc> gd;
+      for (auto& g : ds) {
+        if (j0 >= g.n) continue;
+        int w = std::min(nb, g.n - j0);
+        gd.push_back({g.csave, g.rbuf, g.M, g.n, g.W, w, g.n, w, g.n});
+      }
+      X m1 = traits<X>::mk(-1.0, 0.0), p1 = traits<X>::one();
+      gemm<X>(gd, m1, p1, C_GJ_UPDATE, ar);
+    }
+    int id = prof.start(C_GJ_UNSWAP, 0, 0);
+    gj_unswap_kernel<X><<<dim3(cdiv(nmax, 256), nn), 256, 0, st>>>(dd);
+    prof.stop(id);
+    check_launch("gj_unswap");
+    double fl = 0;
+    for (auto& g : ds) fl += Flop<X>::mac * (double)g.n * g.n * g.W;
+    (void)fl;
+  }
+
+  // ---------------------------------------------------------------- factor
+  void factor(const hss_block_op_t* A, double tol_) override {
+    auto t0 = std::chrono::high_resolution_clock::now();
+    tol = tol_;
+    const int nprob = (int)P.probs.size();
+    // operator upload (FP64)
+    {
+      std::vector<int32_t> rp{0}, ci;
+      std::vector<int64_t> elem_dof, seg{0};
+      std::vector<int32_t> dof_elem, dof_prob;
+      for (int p = 0; p < nprob; ++p) {
+        const PProblem& pr = P.probs[p];
+        for (int e = 0; e < pr.n_el; ++e) {
+          for (int b = pr.row_ptr[e]; b < pr.row_ptr[e + 1]; ++b) ci.push_back((int32_t)(pr.el_off + pr.col_idx[b]));
+          rp.push_back((int32_t)ci.size());
+          elem_dof.push_back(pr.dof_off + (int64_t)e * q);
+          for (int k = 0; k < q; ++k) {
+            dof_elem.push_back((int32_t)(pr.el_off + e));
+            dof_prob.push_back(p);
+          }
+        }
+        seg.push_back(pr.dof_off + pr.ndof);
+      }
+      d_row_ptr = up(rp, persist);
+      d_col_idx = up(ci, persist);
+      d_elem_dof = up(elem_dof, persist);
+      d_seg_off = up(seg, persist);
+      d_dof_elem = up(dof_elem, persist);
+      d_dof_prob = up(dof_prob, persist);
+      const size_t blk = (size_t)q * q;
+      size_t nnzb = ci.size();
+      d_vals = persist.get<W>(nnzb * blk);
+      for (int p = 0; p < nprob; ++p) {
+        const PProblem& pr = P.probs[p];
+        size_t nb_p = (size_t)pr.row_ptr[pr.n_el];
+        const hipMemcpyKind kind = A[p].vals_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        HIP_CHECK(hipMemcpyAsync(d_vals + (size_t)pr.blk_off * blk, A[p].vals, nb_p * blk * sizeof(W), kind, st));
+      }
+      std::vector<int64_t> perm(ntot);
+      for (int p = 0; p < nprob; ++p) {
+        const PProblem& pr = P.probs[p];
+        for (int64_t t = 0; t < pr.ndof; ++t) perm[pr.dof_off + t] = pr.dof_off + pr.perm[t];
+      }
+      d_perm = up(perm, persist);
+    }
+    // per box index data and factor storage
+    const int nn = (int)P.nodes.size();
+    nd.assign(nn, NodeDev{});
+    {
+      std::vector<int64_t> gidx_all, bpos_all;
+      std::vector<int32_t> src_all;
+      std::vector<size_t> goff(nn), soff(nn), boff(nn);
+      size_t fsz = 0, psz = 0;
+      std::vector<size_t> foff(nn), aoff(nn), poff(nn);
+      for (int g = 0; g < nn; ++g) {
+        const PNode& n = P.nodes[g];
+        const PProblem& pr = P.probs[n.prob];
+        goff[g] = gidx_all.size();
+        for (auto d : n.idof) gidx_all.push_back(pr.dof_off + d);
+        for (auto d : n.bdof) gidx_all.push_back(pr.dof_off + d);
+        soff[g] = src_all.size();
+        if (!n.leaf) {
+          src_all.insert(src_all.end(), n.isrc.begin(), n.isrc.end());
+          src_all.insert(src_all.end(), n.bsrc.begin(), n.bsrc.end());
+        }
+        boff[g] = bpos_all.size();
+        for (auto b : n.bpos) bpos_all.push_back(pr.dof_off + b);
+        const size_t ni = n.idof.size(), nbd = n.bdof.size();
+        foff[g] = fsz;
+        fsz += ((ni * (ni + nbd) + 63) / 64) * 64;
+        aoff[g] = fsz;
+        fsz += ((nbd * ni + 63) / 64) * 64;
+        poff[g] = psz;
+        psz += ((ni + 63) / 64) * 64;
+      }
+      int64_t* dg = up(gidx_all, persist);
+      int32_t* ds = up(src_all, persist);
+      int64_t* db = up(bpos_all, persist);
+      T* fbase = persist.get<T>(std::max<size_t>(fsz, 1));
+      int* pbase = persist.get<int>(std::max<size_t>(psz, 1));
+      for (int g = 0; g < nn; ++g) {
+        nd[g].gidx = dg + goff[g];
+        nd[g].src = P.nodes[g].leaf ? nullptr : ds + soff[g];
+        nd[g].bpos = db + boff[g];
+        nd[g].G = fbase + foff[g];
+        nd[g].Abi = fbase + aoff[g];
+        nd[g].piv = pbase + poff[g];
+      }
+    }
+    rank_v.assign(nn, 0);
+    attempts_v.assign(nn, 0);
+    l_v.assign(nn, 0);
+    err_v.assign(nn, 0.0);
+    tmax_v.assign(nn, 0.f);
+    fallbacks = retries = 0;
+    flops_factor = 0;
+    int* d_sing = persist.get<int>(nn + nprob + 1);
+    HIP_CHECK(hipMemsetAsync(d_sing, 0, sizeof(int) * (nn + nprob + 1), st));
+    // features need the diagonal-block norms: computed on the host copy if available
+    compute_features(A);
+
+    std::vector<Arena> wave_st(P.waves.size());
+    for (size_t h = 0; h < P.waves.size(); ++h) {
+      const std::vector<int>& wv = P.waves[h];
+      Arena& stA = wave_st[h];
+      stA.st = st;
+      Arena tmp;
+      tmp.st = st;
+      // S and S~ buffers
+      // S lives for the wave; S~ until the parents are assembled (with tol = 0, S~ = S)
+      std::vector<T*> Sp(wv.size()), Mp(wv.size()), Ap(wv.size());
+      for (size_t i = 0; i < wv.size(); ++i) {
+        const PNode& n = P.nodes[wv[i]];
+        const size_t nbd = std::max<size_t>(n.bdof.size() * n.bdof.size(), 1);
+        if (tol > 0) {
+          Sp[i] = tmp.get<T>(nbd);
+          nd[wv[i]].St = stA.get<T>(nbd);
+        } else {
+          Sp[i] = stA.get<T>(nbd);
+          nd[wv[i]].St = Sp[i];
+        }
+        Mp[i] = nd[wv[i]].G;
+        Ap[i] = nd[wv[i]].Abi;
+      }
+      // 1. gather
+      {
+        std::vector<GatherDesc<T>> gd(wv.size());
+        int64_t maxe = 0;
+        for (size_t i = 0; i < wv.size(); ++i) {
+          const PNode& n = P.nodes[wv[i]];
+          const PProblem& pr = P.probs[n.prob];
+          GatherDesc<T>& g = gd[i];
+          g.ni = (int)n.idof.size();
+          g.nb = (int)n.bdof.size();
+          g.gidx = nd[wv[i]].gidx;
+          g.src = nd[wv[i]].src;
+          g.st[0] = n.leaf ? nullptr : nd[n.child[0]].St;
+          g.st[1] = n.leaf ? nullptr : nd[n.child[1]].St;
+          g.nbc[0] = n.leaf ? 0 : (int)P.nodes[n.child[0]].bdof.size();
+          g.nbc[1] = n.leaf ? 0 : (int)P.nodes[n.child[1]].bdof.size();
+          g.el_off = pr.el_off;
+          g.dof_off = pr.dof_off;
+          maxe = std::max<int64_t>(maxe, (int64_t)(g.ni + g.nb) * (g.ni + g.nb));
+        }
+        auto* dgd = up(gd, tmp);
+        auto* dM = up(Mp, tmp);
+        auto* dA = up(Ap, tmp);
+        auto* dS = up(Sp, tmp);
+        OpDev op{d_row_ptr, d_col_idx, d_vals, q};
+        int id = prof.start(C_GATHER, 0, 0);
+        gather_kernel<T, W, T><<<dim3(grid1(maxe, 512), (unsigned)wv.size()), 256, 0, st>>>(op, dgd, dM, dA, dS);
+        prof.stop(id);
+        check_launch("gather");
+      }
+      // 2. Gauss-Jordan on [A_ii | A_ib]
+      {
+        std::vector<GjDesc<T>> gj;
+        for (size_t i = 0; i < wv.size(); ++i) {
+          const PNode& n = P.nodes[wv[i]];
+          if (n.idof.empty()) continue;
+          GjDesc<T> g{};
+          g.M = nd[wv[i]].G;
+          g.n = (int)n.idof.size();
+          g.W = (int)(n.idof.size() + n.bdof.size());
+          g.piv = nd[wv[i]].piv;
+          g.flag = d_sing + wv[i];
+          gj.push_back(g);
+        }
+        gauss_jordan<T>(gj, tmp);
+      }
+      // 3. Schur update S = A_bb - A_bi X
+      {
+        std::vector<GemmDesc> gd;
+        for (size_t i = 0; i < wv.size(); ++i) {
+          const PNode& n = P.nodes[wv[i]];
+          const int ni = (int)n.idof.size(), nbd = (int)n.bdof.size();
+          if (ni == 0 || nbd == 0) continue;
+          gd.push_back({nd[wv[i]].Abi, nd[wv[i]].G + (size_t)ni * ni, Sp[i], nbd, nbd, ni, nbd, ni, nbd});
+        }
+        gemm<T>(gd, traits<T>::mk(-1.0, 0.0), traits<T>::one(), C_SCHUR, tmp);
+      }
+      // 4. compression
+      compress_wave(wv, Sp, tmp);
+      tmp.release();
+    }
+    // root of every problem
+    rt.assign(nprob, RootDev{});
+    {
+      Arena tmp;
+      tmp.st = st;
+      std::vector<GatherDesc<T>> gd(nprob);
+      std::vector<W*> Rp(nprob);
+      std::vector<std::vector<int64_t>> gi(nprob);
+      int64_t maxe = 0;
+      std::vector<int64_t> gall;
+      std::vector<int32_t> sall;
+      std::vector<size_t> go(nprob), so(nprob);
+      for (int p = 0; p < nprob; ++p) {
+        const PRoot& r = P.roots[p];
+        const PProblem& pr = P.probs[p];
+        const PNode &a = P.nodes[r.g2], &b = P.nodes[r.g3];
+        go[p] = gall.size();
+        so[p] = sall.size();
+        for (auto d : r.dofs) gall.push_back(pr.dof_off + d);
+        for (size_t k = 0; k < a.bdof.size(); ++k) sall.push_back((int32_t)k);
+        for (size_t k = 0; k < b.bdof.size(); ++k) sall.push_back((int32_t)((1 << 30) + k));
+        rt[p].n = (int)r.dofs.size();
+        rt[p].R = persist.get<W>((size_t)rt[p].n * rt[p].n);
+        rt[p].piv = persist.get<int>(rt[p].n);
+        max_nr = std::max(max_nr, rt[p].n);
+        maxe = std::max<int64_t>(maxe, (int64_t)rt[p].n * rt[p].n);
+      }
+      int64_t* dg = up(gall, persist);
+      int32_t* ds = up(sall, persist);
+      for (int p = 0; p < nprob; ++p) {
+        const PRoot& r = P.roots[p];
+        const PProblem& pr = P.probs[p];
+        GatherDesc<T>& g = gd[p];
+        g.ni = rt[p].n;
+        g.nb = 0;
+        g.gidx = dg + go[p];
+        g.src = ds + so[p];
+        g.st[0] = nd[r.g2].St;
+        g.st[1] = nd[r.g3].St;
+        g.nbc[0] = (int)P.nodes[r.g2].bdof.size();
+        g.nbc[1] = (int)P.nodes[r.g3].bdof.size();
+        g.el_off = pr.el_off;
+        g.dof_off = pr.dof_off;
+        Rp[p] = rt[p].R;
+        rt[p].gidx = dg + go[p];
+        rt[p].src = ds + so[p];
+      }
+      auto* dgd = up(gd, tmp);
+      auto* dR = up(Rp, tmp);
+      OpDev op{d_row_ptr, d_col_idx, d_vals, q};
+      int id = prof.start(C_ROOT, 0, 0);
+      gather_kernel<W, W, T><<<dim3(grid1(maxe, 512), (unsigned)nprob), 256, 0, st>>>(op, dgd, dR, nullptr, nullptr);
+      prof.stop(id);
+      check_launch("root gather");
+      std::vector<GjDesc<W>> gj;
+      for (int p = 0; p < nprob; ++p) {
+        GjDesc<W> g{};
+        g.M = rt[p].R;
+        g.n = g.W = rt[p].n;
+        g.piv = rt[p].piv;
+        g.flag = d_sing + nn + p;
+        gj.push_back(g);
+      }
+      gauss_jordan<W>(gj, tmp);
+      // singular pivots
+      std::vector<int> sing(nn + nprob + 1);
+      HIP_CHECK(hipMemcpyAsync(sing.data(), d_sing, sizeof(int) * sing.size(), hipMemcpyDeviceToHost, st));
+      sync();
+      tmp.release();
+      for (auto& a : wave_st) a.release();
+      for (int g = 0; g < nn; ++g) nd[g].St = nullptr;
+      for (int g = 0; g < nn + nprob; ++g)
+        if (sing[g]) {
+          std::string who = g < nn ? ("box " + std::to_string(P.nodes[g].heap) + " of problem " +
+                                      std::to_string(P.nodes[g].prob))
+                                   : ("root of problem " + std::to_string(g - nn));
+          throw Error(HSS_ESINGULAR, "zero pivot in " + who);
+        }
+    }
+    build_apply();
+    sync();
+    mark_clean(st);
+    prof.collect();
+    time_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::high_resolution_clock::now() - t0).count();
+  }
+
+  // ---------------------------------------------------------------- features
+  void compute_features(const hss_block_op_t* A) {
+    const int nn = (int)P.nodes.size();
+    feat_v.assign((size_t)nn * 8, 0.f);
+    for (int g = 0; g < nn; ++g) {
+      const PNode& n = P.nodes[g];
+      const PProblem& pr = P.probs[n.prob];
+      double s1 = 0, s2 = 0;
+      int cnt = 0;
+      if (!A[n.prob].vals_on_device) {
+        const size_t blk = (size_t)q * q;
+        for (int e : n.elems) {
+          int b = pr.diag_blk[e];
+          if (b < 0) continue;
+          double f = 0;
+          if (CX) {
+            const double* v = (const double*)A[n.prob].vals + 2 * (size_t)b * blk;
+            for (size_t k = 0; k < 2 * blk; ++k) f += v[k] * v[k];
+          } else {
+            const double* v = (const double*)A[n.prob].vals + (size_t)b * blk;
+            for (size_t k = 0; k < blk; ++k) f += v[k] * v[k];
+          }
+          double lf = 0.5 * std::log10(std::max(f, 1e-300));
+          s1 += lf;
+          s2 += lf * lf;
+          ++cnt;
+        }
+      }
+      double mean = cnt ? s1 / cnt : 0, var = cnt ? std::max(0.0, s2 / cnt - mean * mean) : 0;
+      float* f = &feat_v[(size_t)g * 8];
+      f[0] = (float)n.depth / 10.f;
+      f[1] = (float)std::log2(1.0 + n.bdof.size()) / 10.f;
+      f[2] = (float)std::log2(1.0 + n.idof.size()) / 10.f;
+      f[3] = (float)o.kappa_h;
+      f[4] = (float)(std::log10(std::max(tol, 1e-16)) / -10.0);
+      f[5] = (float)(mean / 5.0);
+      f[6] = (float)std::sqrt(var);
+      f[7] = (float)std::log2((double)q) / 5.f;
+    }
+  }
+
+  // predicted sample count per box from the rank model (host evaluation of the
+  // same network the GPU trains; tiny)
+  int predicted_l(int g) const {
+    if (!o.rank_model) return o.l0;
+    const float* w = o.rank_model;
+    const float* x = &feat_v[(size_t)g * 8];
+    float h1[64], out = w[4800];
+    for (int j = 0; j < 64; ++j) {
+      float z = w[512 + j];
+      for (int i = 0; i < 8; ++i) z += w[j * 8 + i] * x[i];
+      h1[j] = std::tanh(z);
+    }
+    for (int j = 0; j < 64; ++j) {
+      float z = w[4672 + j];
+      for (int i = 0; i < 64; ++i) z += w[576 + j * 64 + i] * h1[i];
+      out += w[4736 + j] * std::tanh(z);
+    }
+    double k = std::exp2((double)out) - 1.0;
+    int kk = (int)std::ceil(std::max(0.0, k) * 1.1);
+    return std::max(kk + o.p_os, o.p_os + 2);
+  }
+
+  // ---------------------------------------------------------------- compression
+  void compress_wave(const std::vector<int>& wv, const std::vector<T*>& Sp, Arena& tmp) {
+    const int nb_boxes = (int)wv.size();
+    // symmetrise and take ||S||_F^2 for every box
+    std::vector<CompBox<T>> all(nb_boxes);
+    double* d_nrm = tmp.get<double>(nb_boxes);
+    HIP_CHECK(hipMemsetAsync(d_nrm, 0, sizeof(double) * nb_boxes, st));
+    int64_t maxe = 0;
+    for (int i = 0; i < nb_boxes; ++i) {
+      all[i] = CompBox<T>{};
+      all[i].S = Sp[i];
+      all[i].n = (int)P.nodes[wv[i]].bdof.size();
+      all[i].nrm2 = d_nrm + i;
+      maxe = std::max<int64_t>(maxe, (int64_t)all[i].n * all[i].n);
+    }
+    {
+      auto* d = up(all, tmp);
+      int id = prof.start(C_SYMM, 0, 0);
+      symm_norm_kernel<T><<<dim3(grid1(maxe, 256), nb_boxes), 256, 0, st>>>(d);
+      prof.stop(id);
+      check_launch("symm");
+    }
+    if (tol <= 0) return;  // S~ = S (same buffer)
+    std::vector<int> todo;
+    std::vector<int> lcur(nb_boxes), att(nb_boxes, 0);
+    std::vector<double> scale(nb_boxes, 1.0);
+    std::vector<int> copy_boxes;
+    for (int i = 0; i < nb_boxes; ++i) {
+      const PNode& n = P.nodes[wv[i]];
+      int nid = (int)n.hss.size() - 1;
+      if (nid <= 0) {
+        copy_boxes.push_back(i);
+        continue;
+      }
+      todo.push_back(i);
+      int lcap = std::min(all[i].n + o.p_os, 256);
+      lcur[i] = std::min(std::max(predicted_l(wv[i]), 4), lcap);
+    }
+    std::vector<double> nrm(nb_boxes, 0.0);
+    HIP_CHECK(hipMemcpyAsync(nrm.data(), d_nrm, sizeof(double) * nb_boxes, hipMemcpyDeviceToHost, st));
+    std::vector<int> fallback_boxes;
+    while (!todo.empty()) {
+      Arena at;
+      at.st = st;
+      const int na = (int)todo.size();
+      std::vector<CompBox<T>> bx(na);
+      std::vector<HssDesc<T>> hs;
+      std::vector<std::vector<int>> byh;
+      std::vector<int> leaves;
+      std::vector<ExpandTile> tiles;
+      double* d_err = at.get<double>(na);
+      int* d_flags = at.get<int>(3 * na);
+      int* d_kmax = d_flags + na;
+      float* d_tmax = (float*)(d_flags + 2 * na);
+      HIP_CHECK(hipMemsetAsync(d_err, 0, sizeof(double) * na, st));
+      HIP_CHECK(hipMemsetAsync(d_flags, 0, sizeof(int) * 3 * na, st));
+      int64_t maxe = 0, maxol = 0;
+      int lmax = 0;
+      std::vector<GemmDesc> yg;
+      for (int a = 0; a < na; ++a) {
+        const int i = todo[a];
+        const PNode& n = P.nodes[wv[i]];
+        const int l = lcur[i];
+        lmax = std::max(lmax, l);
+        CompBox<T>& b = bx[a];
+        b.S = Sp[i];
+        b.St = nd[wv[i]].St;
+        b.n = all[i].n;
+        b.l = l;
+        b.n_id = (int)n.hss.size() - 1;
+        b.node = (uint32_t)n.heap;
+        b.tol_scale = tol * scale[i];
+        b.nrm2 = d_nrm + i;
+        b.err2 = d_err + a;
+        b.flags = d_flags + a;
+        b.kmax = d_kmax + a;
+        b.tmax = d_tmax + a;
+        b.Om = at.get<T>((size_t)b.n * l);
+        b.Y = at.get<T>((size_t)b.n * l);
+        maxe = std::max<int64_t>(maxe, (int64_t)b.n * b.n);
+        maxol = std::max<int64_t>(maxol, (int64_t)b.n * l);
+        yg.push_back({b.S, b.Om, b.Y, b.n, l, b.n, b.n, b.n, b.n});
+        const int base = (int)hs.size();
+        for (size_t t = 0; t < n.hss.size(); ++t) {
+          const HssNode& hn = n.hss[t];
+          HssDesc<T> d{};
+          d.box = a;
+          d.lo = hn.lo;
+          d.hi = hn.hi;
+          d.left = hn.left < 0 ? -1 : base + hn.left;
+          d.right = hn.right < 0 ? -1 : base + hn.right;
+          const bool root = t + 1 == n.hss.size();
+          const int width = hn.hi - hn.lo;
+          if (!root) {
+            d.zcap = hn.left < 0 ? width : std::min(width, 2 * l);
+            const int kc = std::min(l, d.zcap);
+            d.cand = at.get<int>(d.zcap);
+            d.skel = at.get<int>(d.zcap);
+            d.k = at.get<int>(1);
+            d.Zt = at.get<T>((size_t)l * d.zcap);
+            d.U = at.get<T>((size_t)d.zcap * kc);
+            d.Ut = at.get<T>((size_t)width * kc);
+            if ((int)byh.size() <= hn.height) byh.resize(hn.height + 1);
+            byh[hn.height].push_back(base + (int)t);
+          }
+          if (hn.left < 0) leaves.push_back(base + (int)t);
+          hs.push_back(d);
+        }
+      }
+      // expand tiles (need the right child's width)
+      const int tw = std::max(1, std::min(32, (int)(49152 / ((size_t)lmax * sizeof(T)))));
+      for (size_t t = 0; t < hs.size(); ++t)
+        if (hs[t].left >= 0) {
+          const int nc = hs[hs[t].right].hi - hs[hs[t].right].lo;
+          for (int c0 = 0; c0 < nc; c0 += tw) tiles.push_back({(int)t, c0});
+        }
+      auto* dbx = up(bx, at);
+      auto* dhs = up(hs, at);
+      {
+        int id = prof.start(C_OMEGA, 0, 0);
+        omega_kernel<T><<<dim3(grid1(maxol, 256), na), 256, 0, st>>>(dbx, o.seed);
+        prof.stop(id);
+        check_launch("omega");
+      }
+      gemm<T>(yg, traits<T>::one(), traits<T>::zero(), C_SAMPLE_GEMM, at);
+      for (size_t hh = 0; hh < byh.size(); ++hh) {
+        if (byh[hh].empty()) continue;
+        int* dl = up(byh[hh], at);
+        int id = prof.start(C_SAMPLE, 0, 0);
+        sample_kernel<T><<<(unsigned)byh[hh].size(), 256, 0, st>>>(dbx, dhs, dl);
+        prof.stop(id);
+        check_launch("sample");
+        id = prof.start(C_ID, 0, 0);
+        cpqr_kernel<T><<<(unsigned)byh[hh].size(), 256, 0, st>>>(dbx, dhs, dl, tol, o.p_os);
+        prof.stop(id);
+        check_launch("cpqr");
+      }
+      for (size_t hh = 0; hh < byh.size(); ++hh) {
+        if (byh[hh].empty()) continue;
+        int* dl = up(byh[hh], at);
+        int id = prof.start(C_UTALL, 0, 0);
+        utall_kernel<T><<<(unsigned)byh[hh].size(), 256, 0, st>>>(dbx, dhs, dl);
+        prof.stop(id);
+        check_launch("utall");
+      }
+      {
+        int* dl = up(leaves, at);
+        int id = prof.start(C_EXPAND, 0, 0);
+        diag_copy_kernel<T><<<(unsigned)leaves.size(), 256, 0, st>>>(dbx, dhs, dl);
+        check_launch("diag_copy");
+        if (!tiles.empty()) {
+          auto* dt = up(tiles, at);
+          expand_kernel<T><<<(unsigned)tiles.size(), 256, (size_t)lmax * tw * sizeof(T), st>>>(dbx, dhs, dt, tw);
+          check_launch("expand");
+        }
+        prof.stop(id);
+        id = prof.start(C_JUDGE, 0, 0);
+        judge_kernel<T><<<dim3(grid1(maxe, 64), na), 256, 0, st>>>(dbx);
+        prof.stop(id);
+        check_launch("judge");
+      }
+      std::vector<double> err(na);
+      std::vector<int> fl(3 * na);
+      HIP_CHECK(hipMemcpyAsync(err.data(), d_err, sizeof(double) * na, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipMemcpyAsync(fl.data(), d_flags, sizeof(int) * 3 * na, hipMemcpyDeviceToHost, st));
+      sync();
+      at.release();
+      std::vector<int> next;
+      for (int a = 0; a < na; ++a) {
+        const int i = todo[a];
+        const int g = wv[i];
+        att[i] += 1;
+        const double e = nrm[i] > 0 ? std::sqrt(err[a] / nrm[i]) : 0.0;
+        const bool exhausted = fl[a] & 1;
+        const int lcap = std::min(all[i].n + o.p_os, 256);
+        rank_v[g] = fl[na + a];
+        float tm;
+        std::memcpy(&tm, &fl[2 * na + a], sizeof(float));
+        tmax_v[g] = tm;
+        err_v[g] = e;
+        l_v[g] = lcur[i];
+        attempts_v[g] = att[i];
+        bool retry = false;
+        if (exhausted && lcur[i] < lcap) {
+          lcur[i] = std::min(2 * lcur[i], lcap);
+          retry = true;
+        } else if (e > tol) {
+          scale[i] /= 4.0;
+          retry = true;
+        }
+        if (retry && att[i] >= o.max_attempts) {
+          fallback_boxes.push_back(i);
+          retry = false;
+        }
+        if (retry) {
+          next.push_back(i);
+          ++retries;
+        }
+      }
+      todo.swap(next);
+    }
+    for (int i : fallback_boxes) copy_boxes.push_back(i), ++fallbacks, err_v[wv[i]] = 0.0;
+    if (!copy_boxes.empty()) {
+      std::vector<CompBox<T>> cb;
+      int64_t me = 0;
+      for (int i : copy_boxes) {
+        CompBox<T> b{};
+        b.S = Sp[i];
+        b.St = nd[wv[i]].St;
+        b.n = all[i].n;
+        cb.push_back(b);
+        me = std::max<int64_t>(me, (int64_t)b.n * b.n);
+      }
+      auto* d = up(cb, tmp);
+      copy_box_kernel<T><<<dim3(grid1(me, 256), (unsigned)cb.size()), 256, 0, st>>>(d);
+      check_launch("copy_box");
+    }
+  }
+
+  // ---------------------------------------------------------------- apply
+  void build_apply() {
+    aw.assign(P.waves.size(), ApplyWave{});
+    for (size_t h = 0; h < P.waves.size(); ++h) {
+      std::vector<GemvDesc<T>> f1, f2, b1;
+      ApplyWave& a = aw[h];
+      for (int g : P.waves[h]) {
+        const PNode& n = P.nodes[g];
+        const PProblem& pr = P.probs[n.prob];
+        const int ni = (int)n.idof.size(), nbd = (int)n.bdof.size();
+        if (ni == 0) continue;
+        const int64_t ip = pr.dof_off + n.ipos;
+        f1.push_back({nd[g].G, ni, ni, ip, nullptr, ip, nullptr});
+        f2.push_back({nd[g].Abi, nbd, ni, ip, nullptr, -1, nd[g].bpos});
+        b1.push_back({nd[g].G + (size_t)ni * ni, ni, nbd, -1, nd[g].bpos, ip, nullptr});
+        a.max_ni = std::max(a.max_ni, ni);
+        a.max_nb = std::max(a.max_nb, nbd);
+      }
+      a.n = (int)f1.size();
+      a.fwd1 = up(f1, persist);
+      a.fwd2 = up(f2, persist);
+      a.bwd = up(b1, persist);
+    }
+    std::vector<GemvDesc<W>> rd;
+    for (size_t p = 0; p < P.roots.size(); ++p) {
+      const int64_t ip = P.probs[p].dof_off + P.roots[p].ipos;
+      rd.push_back({rt[p].R, rt[p].n, rt[p].n, ip, nullptr, ip, nullptr});
+    }
+    d_rootdesc = up(rd, persist);
+  }
+
+  void ensure_work(int nrhs) {
+    if (nrhs <= work_nrhs) return;
+    work.release();
+    d_r = work.get<W>((size_t)ntot * nrhs);
+    d_t = work.get<W>((size_t)ntot * nrhs);
+    work_nrhs = nrhs;
+  }
+
+  template <class X> void gemv(const GemvDesc<X>* d, int n, int maxrows, const W* x, W* y, int nrhs, int mode) {
+    if (n == 0 || maxrows == 0) return;
+    gemv_kernel<X, W, 4><<<dim3(cdiv(maxrows, 64), n), 256, 0, st>>>(d, x, y, (int64_t)ntot, nrhs, mode);
+    check_launch("gemv");
+  }
+
+  // y = M^{-t} D^{-1} L^{-1} x with device x, y
+  void apply_dev(int nrhs, const W* x, int64_t ldx, W* y, int64_t ldy) {
+    ensure_work(nrhs);
+    int id = prof.start(C_APPLY, 0, apply_bytes() * nrhs);
+    permute_kernel<W><<<grid1(ntot * nrhs), 256, 0, st>>>(x, ldx, d_r, ntot, d_perm, ntot, nrhs, 0);
+    check_launch("permute");
+    for (size_t h = 0; h < aw.size(); ++h) {
+      gemv<T>(aw[h].fwd1, aw[h].n, aw[h].max_ni, d_r, d_t, nrhs, 0);
+      gemv<T>(aw[h].fwd2, aw[h].n, aw[h].max_nb, d_t, d_r, nrhs, 1);
+    }
+    gemv<W>(d_rootdesc, (int)rt.size(), max_nr, d_r, d_t, nrhs, 0);
+    for (size_t h = aw.size(); h-- > 0;) gemv<T>(aw[h].bwd, aw[h].n, aw[h].max_ni, d_t, d_t, nrhs, 1);
+    permute_kernel<W><<<grid1(ntot * nrhs), 256, 0, st>>>(d_t, ntot, y, ldy, d_perm, ntot, nrhs, 1);
+    check_launch("unpermute");
+    prof.stop(id);
+  }
+  double apply_bytes() const {
+    double b = 0;
+    for (auto& n : P.nodes) {
+      double ni = (double)n.idof.size(), nbd = (double)n.bdof.size();
+      b += (ni * ni + 2 * ni * nbd) * sizeof(T);
+    }
+    for (auto& r : rt) b += (double)r.n * r.n * sizeof(W);
+    return b;
+  }
+
+  void apply(int nrhs, const void* x, int64_t ldx, void* y, int64_t ldy) override {
+    if (nrhs < 1 || ldx < ntot || ldy < ntot || !x || !y) throw Error(HSS_EINVAL, "bad apply arguments");
+    apply_dev(nrhs, (const W*)x, ldx, (W*)y, ldy);
+    sync();
+    prof.collect();
+  }
+
+  // ---------------------------------------------------------------- GMRES
+  void spmv(const W* x, const W* b, W* y, int nrhs, int mode) {
+    int id = prof.start(C_SPMV, 0, 0);
+    spmv_kernel<W><<<grid1(ntot * nrhs, 4096), 256, 0, st>>>(d_row_ptr, d_col_idx, d_vals, q, d_dof_elem, d_elem_dof,
+                                                             ntot, x, b, y, ntot, nrhs, mode);
+    prof.stop(id);
+    check_launch("spmv");
+  }
+
+  int gmres(int nrhs, const void* bv, void* xv, int64_t ld, double gtol, int m, int maxit,
+            hss_gmres_info_t* info) override {
+    if (nrhs < 1 || ld < ntot || !bv || !xv || m < 1 || maxit < 1)
+      throw Error(HSS_EINVAL, "bad gmres arguments");
+    const int nprob = (int)P.probs.size();
+    const int ns = nprob * nrhs;
+    Arena ga;
+    ga.st = st;
+    const int64_t vlen = ntot * nrhs;
+    W* B = ga.get<W>(vlen);
+    W* X = ga.get<W>(vlen);
+    W* Vb = ga.get<W>(vlen * (m + 1));
+    W* Wv = ga.get<W>(vlen);
+    W* Z = ga.get<W>(vlen);
+    // copy in (the user's ld may differ)
+    HIP_CHECK(hipMemcpy2DAsync(B, ntot * sizeof(W), bv, ld * sizeof(W), ntot * sizeof(W), nrhs,
+                               hipMemcpyDeviceToDevice, st));
+    HIP_CHECK(hipMemcpy2DAsync(X, ntot * sizeof(W), xv, ld * sizeof(W), ntot * sizeof(W), nrhs,
+                               hipMemcpyDeviceToDevice, st));
+    int64_t maxseg = 0;
+    for (auto& pr : P.probs) maxseg = std::max<int64_t>(maxseg, pr.ndof);
+    const int chunk = 4096;
+    const int nchunk = std::max(1, cdiv(maxseg, chunk));
+    W* part = ga.get<W>((size_t)ns * nchunk * (m + 1));
+    W* Hd = ga.get<W>((size_t)(m + 1) * ns * (m + 1));   // [j][s][i]
+    W* nrmw = ga.get<W>(ns);
+    double* nrmd = ga.get<double>(ns);
+    W* coef = ga.get<W>((size_t)ns * (m + 1));
+    auto dots = [&](const W* V, int nvec, const W* w, W* out, int ostride, int accumulate) {
+      dots_kernel<W><<<dim3(nchunk, ns), 256, 0, st>>>(V, vlen, nvec, w, ntot, d_seg_off, nprob, chunk, part, nchunk);
+      check_launch("dots");
+      dots_reduce_kernel<W><<<cdiv((int64_t)nvec * ns, 256), 256, 0, st>>>(part, nvec, ns, nchunk, out, ostride,
+                                                                           accumulate);
+      check_launch("dots_reduce");
+    };
+    auto norms = [&](const W* w, std::vector<double>& host) {
+      dots(w, 1, w, nrmw, 1, 0);
+      host.resize(ns);
+      std::vector<W> tmp(ns);
+      HIP_CHECK(hipMemcpyAsync(tmp.data(), nrmw, sizeof(W) * ns, hipMemcpyDeviceToHost, st));
+      sync();
+      for (int s = 0; s < ns; ++s) host[s] = std::sqrt(std::max(0.0, (double)traits<W>::re(tmp[s])));
+    };
+    std::vector<double> bnorm;
+    norms(B, bnorm);
+    std::vector<int> iters(ns, 0), restarts(ns, 0), done(ns, 0);
+    std::vector<double> relres(ns, 0.0);
+    for (int s = 0; s < ns; ++s)
+      if (bnorm[s] == 0) done[s] = 1;
+    using C = std::complex<double>;
+    auto toC = [](W v) { return C(traits<W>::re(v), traits<W>::im(v)); };
+    int total_steps = 0;
+    int gid = prof.start(C_GMRES, 0, 0);
+    while (true) {
+      // residual and cycle start
+      spmv(X, B, Wv, nrhs, 1);
+      std::vector<double> beta;
+      norms(Wv, beta);
+      bool any = false;
+      for (int s = 0; s < ns; ++s) {
+        relres[s] = bnorm[s] > 0 ? beta[s] / bnorm[s] : 0.0;
+        if (!done[s] && relres[s] <= gtol) done[s] = 1;
+        if (!done[s] && iters[s] < maxit) any = true;
+      }
+      if (!any) break;
+      // V_0 = r / beta
+      std::vector<double> bb(beta);
+      for (int s = 0; s < ns; ++s)
+        if (done[s]) bb[s] = 0.0;
+      h2d(nrmd, bb);
+      scale_kernel<W><<<grid1(vlen), 256, 0, st>>>(Wv, ntot, ntot, nrhs, nrmd, d_dof_prob, nprob, Vb);
+      check_launch("scale");
+      sync();
+      std::vector<std::vector<C>> H(ns, std::vector<C>((size_t)(m + 1) * m, C(0)));
+      std::vector<std::vector<double>> cs(ns, std::vector<double>(m, 0));
+      std::vector<std::vector<C>> sn(ns, std::vector<C>(m, C(0)));
+      std::vector<std::vector<C>> gv(ns, std::vector<C>(m + 1, C(0)));
+      std::vector<int> jlen(ns, 0), act(ns, 0);
+      for (int s = 0; s < ns; ++s) {
+        act[s] = !done[s] && iters[s] < maxit;
+        gv[s][0] = C(beta[s], 0);
+      }
+      for (int j = 0; j < m; ++j) {
+        W* Vj = Vb + (size_t)j * vlen;
+        apply_dev(nrhs, Vj, ntot, Z, ntot);
+        spmv(Z, nullptr, Wv, nrhs, 0);
+        W* Hj = Hd + (size_t)j * ns * (m + 1);
+        // CGS2
+        dots(Vb, j + 1, Wv, Hj, m + 1, 0);
+        combine_kernel<W><<<grid1(vlen), 256, 0, st>>>(Vb, vlen, j + 1, Hj, m + 1, d_dof_prob, nprob, Wv, ntot,
+                                                       ntot, nrhs, -1.0, 1);
+        check_launch("combine");
+        W* Hj2 = coef;
+        dots(Vb, j + 1, Wv, Hj2, m + 1, 0);
+        combine_kernel<W><<<grid1(vlen), 256, 0, st>>>(Vb, vlen, j + 1, Hj2, m + 1, d_dof_prob, nprob, Wv, ntot,
+                                                       ntot, nrhs, -1.0, 1);
+        check_launch("combine");
+        std::vector<double> hn;
+        norms(Wv, hn);
+        h2d(nrmd, hn);
+        scale_kernel<W><<<grid1(vlen), 256, 0, st>>>(Wv, ntot, ntot, nrhs, nrmd, d_dof_prob, nprob,
+                                                     Vb + (size_t)(j + 1) * vlen);
+        check_launch("scale");
+        std::vector<W> h1((size_t)ns * (m + 1)), h2((size_t)ns * (m + 1));
+        HIP_CHECK(hipMemcpyAsync(h1.data(), Hj, sizeof(W) * ns * (m + 1), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipMemcpyAsync(h2.data(), Hj2, sizeof(W) * ns * (m + 1), hipMemcpyDeviceToHost, st));
+        sync();
+        ++total_steps;
+        bool any_act = false;
+        for (int s = 0; s < ns; ++s) {
+          if (!act[s]) continue;
+          auto& Hs = H[s];
+          for (int i = 0; i <= j; ++i) Hs[i + (size_t)j * (m + 1)] = toC(h1[(size_t)s * (m + 1) + i]) +
+                                                                     toC(h2[(size_t)s * (m + 1) + i]);
+          Hs[j + 1 + (size_t)j * (m + 1)] = C(hn[s], 0);
+          for (int i = 0; i < j; ++i) {
+            C a = Hs[i + (size_t)j * (m + 1)], b = Hs[i + 1 + (size_t)j * (m + 1)];
+            Hs[i + (size_t)j * (m + 1)] = cs[s][i] * a + sn[s][i] * b;
+            Hs[i + 1 + (size_t)j * (m + 1)] = -std::conj(sn[s][i]) * a + cs[s][i] * b;
+          }
+          C a = Hs[j + (size_t)j * (m + 1)], b = Hs[j + 1 + (size_t)j * (m + 1)];
+          double c;
+          C sgiv;
+          if (std::abs(b) == 0) {
+            c = 1;
+            sgiv = 0;
+          } else if (std::abs(a) == 0) {
+            c = 0;
+            sgiv = std::conj(b) / std::abs(b);
+          } else {
+            double r = std::hypot(std::abs(a), std::abs(b));
+            c = std::abs(a) / r;
+            sgiv = (a / std::abs(a)) * std::conj(b) / r;
+          }
+          cs[s][j] = c;
+          sn[s][j] = sgiv;
+          Hs[j + (size_t)j * (m + 1)] = c * a + sgiv * b;
+          Hs[j + 1 + (size_t)j * (m + 1)] = 0;
+          gv[s][j + 1] = -std::conj(sgiv) * gv[s][j];
+          gv[s][j] = c * gv[s][j];
+          iters[s] += 1;
+          jlen[s] = j + 1;
+          if (std::abs(gv[s][j + 1]) <= gtol * bnorm[s] || iters[s] >= maxit) act[s] = 0;
+          if (act[s]) any_act = true;
+        }
+        if (!any_act) break;
+      }
+      // x += M^{-1} V y per system
+      std::vector<W> yc((size_t)ns * (m + 1), traits<W>::zero());
+      for (int s = 0; s < ns; ++s) {
+        const int k = jlen[s];
+        if (k == 0) continue;
+        std::vector<C> y(k);
+        for (int i = k - 1; i >= 0; --i) {
+          C acc = gv[s][i];
+          for (int jj = i + 1; jj < k; ++jj) acc -= H[s][i + (size_t)jj * (m + 1)] * y[jj];
+          C d = H[s][i + (size_t)i * (m + 1)];
+          y[i] = std::abs(d) > 0 ? acc / d : C(0);
+        }
+        for (int i = 0; i < k; ++i) yc[(size_t)s * (m + 1) + i] = traits<W>::mk(y[i].real(), y[i].imag());
+        restarts[s] += 1;
+      }
+      h2d(coef, yc);
+      int kmax = 0;
+      for (int s = 0; s < ns; ++s) kmax = std::max(kmax, jlen[s]);
+      combine_kernel<W><<<grid1(vlen), 256, 0, st>>>(Vb, vlen, kmax, coef, m + 1, d_dof_prob, nprob, Wv, ntot, ntot,
+                                                     nrhs, 1.0, 0);
+      check_launch("combine");
+      apply_dev(nrhs, Wv, ntot, Z, ntot);
+      // X += Z
+      {
+        std::vector<W> one((size_t)ns, traits<W>::one());
+        W* onec = nrmw;
+        h2d(onec, one);
+        combine_kernel<W><<<grid1(vlen), 256, 0, st>>>(Z, 0, 1, onec, 1, d_dof_prob, nprob, X, ntot, ntot, nrhs,
+                                                       1.0, 1);
+        check_launch("axpy");
+      }
+      sync();
+      bool progress = false;
+      for (int s = 0; s < ns; ++s) progress |= jlen[s] > 0;
+      if (!progress) break;
+    }
+    prof.stop(gid);
+    HIP_CHECK(hipMemcpy2DAsync(xv, ld * sizeof(W), X, ntot * sizeof(W), ntot * sizeof(W), nrhs,
+                               hipMemcpyDeviceToDevice, st));
+    sync();
+    ga.release();
+    mark_clean(st);
+    prof.collect();
+    int status = HSS_OK;
+    for (int s = 0; s < ns; ++s) {
+      const int p = s % nprob, k = s / nprob;
+      hss_gmres_info_t& inf = info[(size_t)p * nrhs + k];
+      inf.iters = iters[s];
+      inf.restarts = restarts[s];
+      inf.true_relres = relres[s];
+      inf.status = relres[s] <= gtol ? HSS_OK : HSS_ENOCONV;
+      if (inf.status != HSS_OK) status = HSS_ENOCONV;
+    }
+    return status;
+  }
+
+  // ---------------------------------------------------------------- query
+  bool query(const std::string& key, std::vector<double>& out) override {
+    out.clear();
+    const int nn = (int)P.nodes.size();
+    auto per_node = [&](auto f) {
+      for (int g = 0; g < nn; ++g) out.push_back((double)f(g));
+    };
+    if (key == "n") out = {(double)ntot};
+    else if (key == "nprob") out = {(double)P.probs.size()};
+    else if (key == "nnodes") out = {(double)nn};
+    else if (key == "nwaves") out = {(double)P.waves.size()};
+    else if (key == "max_err") out = {err_v.empty() ? 0.0 : *std::max_element(err_v.begin(), err_v.end())};
+    else if (key == "ranks") per_node([&](int g) { return rank_v[g]; });
+    else if (key == "attempts") per_node([&](int g) { return attempts_v[g]; });
+    else if (key == "l") per_node([&](int g) { return l_v[g]; });
+    else if (key == "err") per_node([&](int g) { return err_v[g]; });
+    else if (key == "tmax") per_node([&](int g) { return tmax_v[g]; });
+    else if (key == "node_heap") per_node([&](int g) { return P.nodes[g].heap; });
+    else if (key == "node_prob") per_node([&](int g) { return P.nodes[g].prob; });
+    else if (key == "node_ni") per_node([&](int g) { return P.nodes[g].idof.size(); });
+    else if (key == "node_nb") per_node([&](int g) { return P.nodes[g].bdof.size(); });
+    else if (key == "features") {
+      for (float f : feat_v) out.push_back(f);
+    } else if (key == "fallbacks") out = {(double)fallbacks};
+    else if (key == "retries") out = {(double)retries};
+    else if (key == "flops_factor") {
+      double f = 0;
+      for (auto& n : P.nodes) {
+        double ni = (double)n.idof.size(), nbd = (double)n.bdof.size();
+        f += Flop<T>::mac * (ni * ni * (ni + nbd) + nbd * nbd * ni);
+      }
+      for (auto& r : rt) f += Flop<W>::mac * (double)r.n * r.n * r.n;
+      out = {f};
+    } else if (key == "bytes_apply") out = {apply_bytes()};
+    else if (key == "bytes_spmv") {
+      double nnzb = 0;
+      for (auto& pr : P.probs) nnzb += pr.row_ptr[pr.n_el];
+      out = {nnzb * q * q * sizeof(W) + 2.0 * ntot * sizeof(W)};
+    } else if (key == "time_factor_ms") out = {time_factor_ms};
+    else if (key.rfind("prof.", 0) == 0) {
+      prof.collect();
+      std::string rest = key.substr(5);
+      size_t dot = rest.rfind('.');
+      if (dot == std::string::npos) return false;
+      std::string cls = rest.substr(0, dot), what = rest.substr(dot + 1);
+      int c = -1;
+      for (int i = 0; i < C_NCLS; ++i)
+        if (cls == kClsName[i]) c = i;
+      if (c < 0) return false;
+      if (what == "ms") out = {prof.ms[c]};
+      else if (what == "launches") out = {(double)prof.launches[c]};
+      else if (what == "flops") out = {prof.flops[c]};
+      else if (what == "bytes") out = {prof.bytes[c]};
+      else return false;
+    } else if (key == "prof.reset") {
+      prof.reset();
+    } else {
+      return false;
+    }
+    return true;
+  }
+};
+
+std::unique_ptr<EngineBase> make_engine(Plan&& plan, const hss_opts_t& opts, bool cplx) {
+  const bool fp64 = opts.prec == HSS_PREC_FP64;
+  if (opts.prec == HSS_PREC_BF16) throw Error(HSS_EUNSUPPORTED, "BF16 Schur products are not built yet");
+  if (cplx) {
+    if (fp64) return std::unique_ptr<EngineBase>(new Engine<cd>(std::move(plan), opts));
+    return std::unique_ptr<EngineBase>(new Engine<cf>(std::move(plan), opts));
+  }
+  if (fp64) return std::unique_ptr<EngineBase>(new Engine<double>(std::move(plan), opts));
+  return std::unique_ptr<EngineBase>(new Engine<float>(std::move(plan), opts));
+}
+
+}  // namespace hss
+
+// ------------------------------------------------------------------ diagnostics
+namespace hss {
+namespace {
+template <class X> struct DebugRunner : Engine<X> {
+  using Engine<X>::Engine;
+};
+template <class X>
+void debug_gemm_t(int nb, const void* const* A, const void* const* B, void* const* C, const int32_t* M,
+                  const int32_t* N, const int32_t* K, const int32_t* lda, const int32_t* ldb, const int32_t* ldc,
+                  const double* al, const double* be, hipStream_t st) {
+  std::vector<GemmDesc> v;
+  std::vector<int> pre{0};
+  for (int b = 0; b < nb; ++b) {
+    if (M[b] <= 0 || N[b] <= 0) continue;
+    v.push_back({A[b], B[b], C[b], M[b], N[b], K[b], lda[b], ldb[b], ldc[b]});
+    pre.push_back(pre.back() + cdiv(M[b], GBM) * cdiv(N[b], GBN));
+  }
+  if (v.empty()) return;
+  Arena ar;
+  ar.st = st;
+  GemmDesc* dd = ar.get<GemmDesc>(v.size());
+  int* dp = ar.get<int>(pre.size());
+  HIP_CHECK(hipMemcpyAsync(dd, v.data(), v.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(dp, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  gemm_nn_kernel<X><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), traits<X>::mk(al[0], al[1]),
+                                                traits<X>::mk(be[0], be[1]));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(HSS_EDEVICE, hipGetErrorString(e));
+  HIP_CHECK(hipStreamSynchronize(st));
+  ar.release();
+  mark_clean(st);
+}
+}  // namespace
+
+void debug_gemm(int scalar, int nb, const void* const* A, const void* const* B, void* const* C, const int32_t* M,
+                const int32_t* N, const int32_t* K, const int32_t* lda, const int32_t* ldb, const int32_t* ldc,
+                const double* al, const double* be, hipStream_t st) {
+  switch (scalar) {
+    case 0: debug_gemm_t<float>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
+    case 1: debug_gemm_t<double>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
+    case 2: debug_gemm_t<cf>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
+    case 3: debug_gemm_t<cd>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
+    default: throw Error(HSS_EINVAL, "unknown scalar code");
+  }
+}
+
+template <class X>
+void debug_gj_t(int nb, void* const* Mat, const int32_t* n, const int32_t* m, int32_t* singular, hipStream_t st) {
+  // a throwaway engine instance provides the launch logic
+  Plan P;
+  P.probs.resize(1);
+  P.probs[0].q = 1;
+  hss_opts_t o;
+  std::memset(&o, 0, sizeof(o));
+  o.hip_stream = st;
+  Engine<X> eng(std::move(P), o);
+  Arena ar;
+  ar.st = st;
+  int* flags = ar.get<int>(nb);
+  HIP_CHECK(hipMemsetAsync(flags, 0, sizeof(int) * nb, st));
+  std::vector<GjDesc<X>> ds;
+  for (int b = 0; b < nb; ++b) {
+    if (n[b] <= 0) continue;
+    GjDesc<X> g{};
+    g.M = (X*)Mat[b];
+    g.n = n[b];
+    g.W = n[b] + m[b];
+    g.piv = ar.get<int>(n[b]);
+    g.flag = flags + b;
+    ds.push_back(g);
+  }
+  eng.template gauss_jordan<X>(ds, ar);
+  std::vector<int> f(nb);
+  HIP_CHECK(hipMemcpyAsync(f.data(), flags, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+  eng.sync();
+  *singular = 0;
+  for (int v : f) *singular |= v;
+  ar.release();
+  mark_clean(st);
+}
+
+void debug_gj(int scalar, int nb, void* const* Mat, const int32_t* n, const int32_t* m, int32_t* singular,
+              hipStream_t st) {
+  switch (scalar) {
+    case 0: debug_gj_t<float>(nb, Mat, n, m, singular, st); break;
+    case 1: debug_gj_t<double>(nb, Mat, n, m, singular, st); break;
+    case 2: debug_gj_t<cf>(nb, Mat, n, m, singular, st); break;
+    case 3: debug_gj_t<cd>(nb, Mat, n, m, singular, st); break;
+    default: throw Error(HSS_EINVAL, "unknown scalar code");
+  }
+}
+}  // namespace hss

@@ -1,0 +1,87 @@
+// Formation of the dense blocks of every box of a wave.
+//
+// Leaves (Section 3.1, the sub-matrices of A listed before equation (30)):
+//   A^_ii = A(I, I), A^_ib = A(I, B), A^_bi = A(B, I), A^_bb = A(B, B),
+// read from the element blocks. Merge boxes (the 2 x 2 block matrices before
+// equation (32)): entries whose row and column come from the same child are
+// read from that child's compressed complement S~, the others from the
+// coupling blocks A(B^mu, B^nu). The root (equation (36)) is a merge with
+// I^ = B^2 u B^3 and no B, assembled in FP64.
+//
+// Outputs per box: M = [A^_ii | A^_ib] (n_i x (n_i + n_b)), A^_bi (n_b x n_i),
+// S = A^_bb (n_b x n_b); all column-major.
+#pragma once
+
+#include "common.hpp"
+
+namespace hss {
+
+struct OpDev {                // the FP64 operator on the device (all problems)
+  const int32_t* row_ptr;     // global element rows
+  const int32_t* col_idx;     // global element ids
+  const void* vals;           // double / cd, q*q per block, column-major
+  int q;
+};
+
+template <class TS> struct GatherDesc {
+  int ni, nb;
+  const int64_t* gidx;     // [ni + nb]: global dofs of I^ then B (problem offset included)
+  const int32_t* src;      // merge: [ni + nb] side*2^30 + position in the child's B; null for leaves
+  const TS* st[2];         // children's S~ (merge)
+  int nbc[2];              // children's B sizes
+  int64_t el_off, dof_off; // problem offsets
+};
+
+template <class TA> __device__ inline TA op_entry(const OpDev& A, int64_t el_off, int64_t dof_off,
+                                                  int64_t gr, int64_t gc) {
+  const int q = A.q;
+  const int64_t lr = gr - dof_off, lc = gc - dof_off;
+  const int64_t er = el_off + lr / q, ec = el_off + lc / q;
+  const int ir = (int)(lr % q), ic = (int)(lc % q);
+  for (int b = A.row_ptr[er]; b < A.row_ptr[er + 1]; ++b)
+    if (A.col_idx[b] == ec) return ((const TA*)A.vals)[(size_t)b * q * q + (size_t)ic * q + ir];
+  return traits<TA>::zero();
+}
+
+// grid: (chunks over (ni+nb)^2, boxes)
+template <class T, class TA, class TS>
+__global__ __launch_bounds__(256) void gather_kernel(OpDev A, const GatherDesc<TS>* __restrict__ descs,
+                                                     T* const* __restrict__ Mout,
+                                                     T* const* __restrict__ Abi_out,
+                                                     T* const* __restrict__ S_out) {
+  const GatherDesc<TS> g = descs[blockIdx.y];
+  const int n = g.ni + g.nb;
+  const int64_t tot = (int64_t)n * n;
+  T* M = Mout[blockIdx.y];
+  T* Abi = Abi_out ? Abi_out[blockIdx.y] : nullptr;
+  T* S = S_out ? S_out[blockIdx.y] : nullptr;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int r = (int)(e % n), c = (int)(e / n);
+    T v;
+    bool same = false;
+    if (g.src) {
+      const int32_t sr = g.src[r], sc = g.src[c];
+      const int side_r = sr >> 30, side_c = sc >> 30;
+      if (side_r == side_c) {
+        const int pr = sr & ((1 << 30) - 1), pc = sc & ((1 << 30) - 1);
+        const TS* st = g.st[side_r];
+        if constexpr (sizeof(T) == sizeof(TS)) v = st[pr + (size_t)pc * g.nbc[side_r]];
+        else v = narrow<T>(to_wide(st[pr + (size_t)pc * g.nbc[side_r]]));
+        same = true;
+      }
+    }
+    if (!same) {
+      TA a = op_entry<TA>(A, g.el_off, g.dof_off, g.gidx[r], g.gidx[c]);
+      v = narrow<T>(a);
+    }
+    if (r < g.ni) {
+      M[r + (size_t)c * g.ni] = v;  // [A_ii | A_ib]
+    } else if (c < g.ni) {
+      Abi[(r - g.ni) + (size_t)c * g.nb] = v;
+    } else {
+      S[(r - g.ni) + (size_t)(c - g.ni) * g.nb] = v;
+    }
+  }
+}
+
+}  // namespace hss

@@ -1,0 +1,197 @@
+// Batched variable-size GEMM on CDNA4 matrix cores:
+//   C_b = alpha * A_b * B_b + beta * C_b   (all column-major, no transposes)
+// for every entry b of a descriptor array, one launch for all entries.
+//
+// Tiles of 64 x 64 outputs per 256-thread workgroup (4 wavefronts, each a
+// 32 x 32 quadrant made of 2 x 2 MFMA 16x16 blocks). K advances in slabs of
+// BK, staged through LDS with the next slab prefetched into registers while
+// the current one is consumed. FP32 uses v_mfma_f32_16x16x4_f32, FP64 uses
+// v_mfma_f64_16x16x4_f64; complex operands use four real products
+// (re*re - im*im, re*im + im*re) on split real/imaginary LDS planes.
+// Workgroups map to (entry, tile) through a prefix sum of tile counts.
+#pragma once
+
+#include "common.hpp"
+
+namespace hss {
+
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K;
+  int lda, ldb, ldc;
+};
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <class R> struct mfma_acc;
+// Result layout of the 16x16x4 MFMA: lane l holds column l % 16; value v of the
+// lane is row 4 * (l / 16) + v for FP32 and row (l / 16) + 4 * v for FP64 (both
+// checked by a lane-layout probe on gfx950). Operands: lane l holds A(l % 16, l / 16)
+// and B(l / 16, l % 16).
+template <> struct mfma_acc<float> {
+  using type = v4f;
+  __device__ static inline int row(int lk, int v) { return lk * 4 + v; }
+  __device__ static inline v4f mac(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct mfma_acc<double> {
+  using type = v4d;
+  __device__ static inline int row(int lk, int v) { return lk + 4 * v; }
+  __device__ static inline v4d mac(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class T> __device__ inline void split(T v, typename traits<T>::real& re,
+                                                typename traits<T>::real& im) {
+  re = traits<T>::re(v);
+  im = traits<T>::im(v);
+}
+
+constexpr int GBM = 64, GBN = 64;
+
+template <class T> struct gemm_cfg {
+  // K slab per LDS stage: 16 real or 8 complex values
+  static constexpr int BK = traits<T>::cplx ? 8 : 16;
+};
+
+// One 64 x 64 tile of C.
+template <class T>
+__global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict__ descs,
+                                                      const int* __restrict__ tprefix, int nent,
+                                                      T alpha, T beta) {
+  using R = typename traits<T>::real;
+  using Acc = typename mfma_acc<R>::type;
+  constexpr bool CX = traits<T>::cplx;
+  constexpr int NP = CX ? 2 : 1;
+  constexpr int BK = gemm_cfg<T>::BK;
+  constexpr int LDA_S = GBM + 4, LDB_S = GBN + 4;
+  __shared__ R As[NP][BK][LDA_S];
+  __shared__ R Bs[NP][BK][LDB_S];
+
+  // locate the entry of this workgroup
+  const int bid = blockIdx.x;
+  int lo = 0, hi = nent;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (tprefix[mid] <= bid) lo = mid; else hi = mid;
+  }
+  const GemmDesc g = descs[lo];
+  const int t = bid - tprefix[lo];
+  const int tmc = (g.M + GBM - 1) / GBM;
+  const int m0 = (t % tmc) * GBM, n0 = (t / tmc) * GBN;
+  const T* __restrict__ Ag = (const T*)g.A;
+  const T* __restrict__ Bg = (const T*)g.B;
+  T* __restrict__ Cg = (T*)g.C;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+
+  Acc acc[NP][2][2];
+  for (int p = 0; p < NP; ++p)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) acc[p][i][j] = Acc{0, 0, 0, 0};
+
+  // global -> register staging: A slab GBM x BK, B slab BK x GBN
+  constexpr int AE = GBM * BK / 256;  // elements per thread
+  constexpr int BE = BK * GBN / 256;
+  T ra[AE], rb[BE];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      int idx = tid + e * 256;
+      int i = idx % GBM, k = idx / GBM;
+      int gi = m0 + i, gk = k0 + k;
+      ra[e] = (gi < g.M && gk < g.K) ? Ag[gi + (size_t)gk * g.lda] : traits<T>::zero();
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      int idx = tid + e * 256;
+      int k = idx % BK, j = idx / BK;
+      int gk = k0 + k, gj = n0 + j;
+      rb[e] = (gk < g.K && gj < g.N) ? Bg[gk + (size_t)gj * g.ldb] : traits<T>::zero();
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      int idx = tid + e * 256;
+      int i = idx % GBM, k = idx / GBM;
+      R re, im;
+      split(ra[e], re, im);
+      As[0][k][i] = re;
+      if constexpr (CX) As[1][k][i] = im;
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      int idx = tid + e * 256;
+      int k = idx % BK, j = idx / BK;
+      R re, im;
+      split(rb[e], re, im);
+      Bs[0][k][j] = re;
+      if constexpr (CX) Bs[1][k][j] = im;
+    }
+  };
+
+  load(0);
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    store();
+    __syncthreads();
+    if (k0 + BK < g.K) load(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + lk;
+      R a[NP][2], b[NP][2];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        a[p][0] = As[p][kk][wm + li];
+        a[p][1] = As[p][kk][wm + 16 + li];
+        b[p][0] = Bs[p][kk][wn + li];
+        b[p][1] = Bs[p][kk][wn + 16 + li];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if constexpr (CX) {
+            acc[0][i][j] = mfma_acc<R>::mac(a[0][i], b[0][j], acc[0][i][j]);
+            acc[0][i][j] = mfma_acc<R>::mac(-a[1][i], b[1][j], acc[0][i][j]);
+            acc[1][i][j] = mfma_acc<R>::mac(a[0][i], b[1][j], acc[1][i][j]);
+            acc[1][i][j] = mfma_acc<R>::mac(a[1][i], b[0][j], acc[1][i][j]);
+          } else {
+            acc[0][i][j] = mfma_acc<R>::mac(a[0][i], b[0][j], acc[0][i][j]);
+          }
+        }
+    }
+    __syncthreads();
+  }
+
+  // epilogue: lane holds column lane%16 and four rows of each 16x16 block
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + j * 16 + li;
+      if (col >= g.N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + i * 16 + mfma_acc<R>::row(lk, v);
+        if (row >= g.M) continue;
+        T val;
+        if constexpr (CX) val = traits<T>::mk(acc[0][i][j][v], acc[1][i][j][v]);
+        else val = acc[0][i][j][v];
+        T* cp = Cg + row + (size_t)col * g.ldc;
+        T out = sc_mul(alpha, val);
+        if (!(traits<T>::re(beta) == 0 && traits<T>::im(beta) == 0)) out = out + sc_mul(beta, *cp);
+        *cp = out;
+      }
+    }
+}
+
+}  // namespace hss

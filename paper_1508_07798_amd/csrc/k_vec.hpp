@@ -1,0 +1,184 @@
+// Vector kernels: the sweeps of the inverse factorization, the element-block
+// SpMV and the GMRES building blocks. Vectors are FP64 (complex128); stored
+// factors may be FP32 and are widened on load.
+#pragma once
+
+#include "common.hpp"
+
+namespace hss {
+
+// Batched GEMV y(out) (+|-)= Mat * x(in) on multi-vectors (nrhs columns, ld).
+// Rows / columns are either contiguous from an offset or listed by index.
+template <class T> struct GemvDesc {
+  const T* mat;          // rows x cols, column-major, ld = rows
+  int rows, cols;
+  int64_t in_off;        // contiguous input offset, or -1 to use in_idx
+  const int64_t* in_idx;
+  int64_t out_off;       // contiguous output offset, or -1 to use out_idx
+  const int64_t* out_idx;
+};
+
+// mode 0: y = M x ; mode 1: y -= M x. grid (row tiles of 64, entries); 256 threads.
+template <class T, class V, int NR>
+__global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc<T>* __restrict__ ds, const V* __restrict__ x,
+                                                   V* __restrict__ y, int64_t ld, int nrhs, int mode) {
+  const GemvDesc<T> d = ds[blockIdx.y];
+  const int r0 = blockIdx.x * 64;
+  if (r0 >= d.rows) return;
+  const int tid = threadIdx.x;
+  const int rl = tid & 63, part = tid >> 6;
+  const int row = r0 + rl;
+  __shared__ V xs[NR][256];
+  __shared__ V red[NR][4][64];
+  for (int rb = 0; rb < nrhs; rb += NR) {
+    const int nr = min(NR, nrhs - rb);
+    V acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = traits<V>::zero();
+    for (int c0 = 0; c0 < d.cols; c0 += 256) {
+      const int cw = min(256, d.cols - c0);
+      __syncthreads();
+      for (int e = tid; e < cw * nr; e += 256) {
+        const int c = e % cw, k = e / cw;
+        const int64_t src = d.in_off >= 0 ? d.in_off + c0 + c : d.in_idx[c0 + c];
+        xs[k][c] = x[src + (rb + k) * ld];
+      }
+      __syncthreads();
+      if (row < d.rows) {
+        for (int c = part; c < cw; c += 4) {
+          const V m = to_wide(d.mat[row + (size_t)(c0 + c) * d.rows]);
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            if (k < nr) acc[k] = acc[k] + sc_mul(m, xs[k][c]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) red[k][part][rl] = acc[k];
+    __syncthreads();
+    if (part == 0 && row < d.rows) {
+      const int64_t dst = d.out_off >= 0 ? d.out_off + row : d.out_idx[row];
+      for (int k = 0; k < nr; ++k) {
+        V s = red[k][0][rl] + red[k][1][rl] + red[k][2][rl] + red[k][3][rl];
+        V* yp = y + dst + (rb + k) * ld;
+        *yp = mode == 0 ? s : (*yp - s);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// tree order <-> dof order. perm[t] = global dof of tree position t.
+template <class V>
+__global__ void permute_kernel(const V* __restrict__ x, int64_t ldx, V* __restrict__ y, int64_t ldy,
+                               const int64_t* __restrict__ perm, int64_t n, int nrhs, int inverse) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int64_t t = e % n;
+    const int64_t k = e / n;
+    if (!inverse) y[t + k * ldy] = x[perm[t] + k * ldx];
+    else y[perm[t] + k * ldy] = x[t + k * ldx];
+  }
+}
+
+// y = A x (mode 0) or y = b - A x (mode 1) for the element-block operator.
+// dof_elem[d]: global element of global dof d; elem_dof[e]: first global dof of e.
+template <class V>
+__global__ __launch_bounds__(256) void spmv_kernel(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                                                   const V* __restrict__ vals, int q,
+                                                   const int32_t* __restrict__ dof_elem,
+                                                   const int64_t* __restrict__ elem_dof, int64_t n,
+                                                   const V* __restrict__ x, const V* __restrict__ b,
+                                                   V* __restrict__ y, int64_t ld, int nrhs, int mode) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int64_t d = e % n, k = e / n;
+    const int el = dof_elem[d];
+    const int r = (int)(d - elem_dof[el]);
+    V acc = traits<V>::zero();
+    for (int bb = row_ptr[el]; bb < row_ptr[el + 1]; ++bb) {
+      const V* blk = vals + (size_t)bb * q * q + r;
+      const V* xs = x + elem_dof[col_idx[bb]] + k * ld;
+      for (int c = 0; c < q; ++c) acc = acc + sc_mul(blk[(size_t)c * q], xs[c]);
+    }
+    y[d + k * ld] = mode == 0 ? acc : (b[d + k * ld] - acc);
+  }
+}
+
+// ------------------------------------------------------------- GMRES pieces
+// Systems s = (problem p, column k): segment [seg_off[p], seg_off[p+1]) of column k.
+// Partial sums of conj(V_i) . w over chunks; grid (chunks, systems).
+template <class V>
+__global__ __launch_bounds__(256) void dots_kernel(const V* __restrict__ Vb, int64_t vstride, int nvec,
+                                                   const V* __restrict__ w, int64_t ld,
+                                                   const int64_t* __restrict__ seg_off, int nprob,
+                                                   int chunk, V* __restrict__ part, int nchunk_max) {
+  const int s = blockIdx.y;
+  const int p = s % nprob, k = s / nprob;
+  const int64_t a = seg_off[p], e = seg_off[p + 1];
+  const int64_t c0 = a + (int64_t)blockIdx.x * chunk;
+  __shared__ V red[256];
+  for (int i = 0; i < nvec; ++i) {
+    V acc = traits<V>::zero();
+    if (c0 < e) {
+      const int64_t c1 = min(e, c0 + chunk);
+      const V* vi = Vb + i * vstride + k * ld;
+      const V* wk = w + k * ld;
+      for (int64_t t = c0 + threadIdx.x; t < c1; t += 256) acc = acc + sc_mul(traits<V>::conj(vi[t]), wk[t]);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[((size_t)s * nchunk_max + blockIdx.x) * nvec + i] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[s * ostride + i] (+)= sum over chunks of part; one thread per (i, s).
+template <class V>
+__global__ void dots_reduce_kernel(const V* __restrict__ part, int nvec, int nsys, int nchunk_max,
+                                   V* __restrict__ out, int ostride, int accumulate) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nvec * nsys) return;
+  const int i = t % nvec, s = t / nvec;
+  V acc = traits<V>::zero();
+  for (int c = 0; c < nchunk_max; ++c) acc = acc + part[((size_t)s * nchunk_max + c) * nvec + i];
+  out[(size_t)s * ostride + i] = accumulate ? out[(size_t)s * ostride + i] + acc : acc;
+}
+
+// w[:, seg s] = sign * sum_i coef[s*cstride + i] V_i  (+ w if accumulate)
+template <class V>
+__global__ void combine_kernel(const V* __restrict__ Vb, int64_t vstride, int nvec,
+                               const V* __restrict__ coef, int cstride, const int32_t* __restrict__ dof_prob,
+                               int nprob, V* __restrict__ w, int64_t ld, int64_t n, int nrhs,
+                               double sign, int accumulate) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int64_t d = e % n, k = e / n;
+    const int s = dof_prob[d] + (int)k * nprob;
+    V acc = traits<V>::zero();
+    for (int i = 0; i < nvec; ++i) acc = acc + sc_mul(coef[(size_t)s * cstride + i], Vb[i * vstride + d + k * ld]);
+    V* wp = w + d + k * ld;
+    V val = sign * acc;
+    *wp = accumulate ? (*wp + val) : val;
+  }
+}
+
+// w[:, seg s] *= scale[s] (scale given as 1/norm with a zero guard)
+template <class V>
+__global__ void scale_kernel(V* __restrict__ w, int64_t ld, int64_t n, int nrhs, const double* __restrict__ nrm,
+                             const int32_t* __restrict__ dof_prob, int nprob, V* __restrict__ dst) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int64_t d = e % n, k = e / n;
+    const int s = dof_prob[d] + (int)k * nprob;
+    const double v = nrm[s];
+    const double f = v > 0 ? 1.0 / v : 0.0;
+    dst[d + k * ld] = f * w[d + k * ld];
+  }
+}
+
+}  // namespace hss

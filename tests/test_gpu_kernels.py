@@ -1,0 +1,85 @@
+"""Kernel-level GPU checks through the C ABI (hss_debug.h): the batched MFMA
+GEMM and the batched Gauss-Jordan elimination against NumPy on ragged,
+multi-tile shapes for every scalar type."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1508_07798_amd import hss  # noqa: E402
+
+DT = {"float32": (np.float32, torch.float32, 2e-5), "float64": (np.float64, torch.float64, 1e-13),
+      "complex64": (np.complex64, torch.complex64, 2e-5), "complex128": (np.complex128, torch.complex128, 1e-13)}
+
+
+def _rand(rng, shape, npdt):
+    a = rng.standard_normal(shape)
+    if np.issubdtype(npdt, np.complexfloating):
+        a = a + 1j * rng.standard_normal(shape)
+    return a.astype(npdt)
+
+
+def _dev(a, tdt):
+    # column-major matrix a (rows x cols) as a CUDA tensor holding a.T in row-major order
+    return torch.from_numpy(np.ascontiguousarray(a.T)).to("cuda")
+
+
+@pytest.mark.parametrize("name", list(DT))
+def test_batched_gemm(name):
+    npdt, tdt, tol = DT[name]
+    rng = np.random.default_rng(7)
+    shapes = [(70, 45, 33), (1, 130, 7), (64, 64, 64), (129, 3, 200), (200, 150, 1)]
+    As, Bs, Cs, ref = [], [], [], []
+    alpha, beta = (-1.0, 1.0)
+    for (m, n, k) in shapes:
+        A = _rand(rng, (m, k), npdt)
+        B = _rand(rng, (k, n), npdt)
+        Cm = _rand(rng, (m, n), npdt)
+        ref.append(alpha * (A.astype(np.complex128) @ B.astype(np.complex128)) + beta * Cm)
+        As.append(_dev(A, tdt))
+        Bs.append(_dev(B, tdt))
+        Cs.append(_dev(Cm, tdt))
+    hss.debug_gemm(As, Bs, Cs, alpha=alpha, beta=beta)
+    for (m, n, k), Cd, R in zip(shapes, Cs, ref):
+        got = Cd.cpu().numpy().T
+        scale = np.sqrt(k) * 10 + 1
+        assert np.abs(got - R).max() <= tol * scale * max(1.0, np.abs(R).max()), (m, n, k)
+
+
+@pytest.mark.parametrize("name", list(DT))
+def test_batched_gauss_jordan(name):
+    npdt, tdt, tol = DT[name]
+    rng = np.random.default_rng(11)
+    sizes = [(1, 3), (7, 0), (33, 20), (100, 45), (200, 230)]
+    mats, refs = [], []
+    for n, m in sizes:
+        # random matrices (pivoting needed) shifted to keep them reasonably conditioned
+        A = _rand(rng, (n, n), npdt) + np.sqrt(n) * np.eye(n, dtype=npdt)
+        B = _rand(rng, (n, m), npdt)
+        M = np.concatenate([A, B], axis=1)
+        mats.append(_dev(M, tdt))
+        A64 = A.astype(np.complex128)
+        refs.append((np.linalg.inv(A64), np.linalg.solve(A64, B.astype(np.complex128)) if m else None,
+                     np.linalg.cond(A64)))
+    sing = hss.debug_gj(mats, [s[0] for s in sizes], [s[1] for s in sizes])
+    assert sing == 0
+    for (n, m), Md, (Ainv, X, cond) in zip(sizes, mats, refs):
+        got = Md.cpu().numpy().T
+        e1 = np.abs(got[:, :n] - Ainv).max() / np.abs(Ainv).max()
+        assert e1 <= tol * cond * 50, (n, e1, cond)
+        if m:
+            e2 = np.abs(got[:, n:] - X).max() / np.abs(X).max()
+            assert e2 <= tol * cond * 50, (n, e2, cond)
+
+
+def test_gauss_jordan_needs_pivoting_and_flags_singular():
+    # a permutation-like matrix: no elimination without row interchanges
+    n = 40
+    P = np.eye(n)[np.random.default_rng(3).permutation(n)]
+    A = P * 2.0 + 1e-3 * np.random.default_rng(4).standard_normal((n, n))
+    M = _dev(A, torch.float64)
+    assert hss.debug_gj([M], [n], [0]) == 0
+    assert np.allclose(M.cpu().numpy().T, np.linalg.inv(A), atol=1e-10)
+    Z = _dev(np.zeros((5, 5)), torch.float64)
+    assert hss.debug_gj([Z], [5], [0]) == 1

@@ -1,0 +1,179 @@
+"""End-to-end parity of the GPU path (through the C ABI) with the CPU oracle.
+
+  * tol = 0: the factorization is exact, so hss_apply(b) equals A^{-1} b and
+    GMRES converges in one iteration (FP64 and FP32 factors, real and complex).
+  * tol > 0, FP64: same test matrices as the oracle (Philox), so the same
+    skeletons are chosen; the apply must match the oracle's element by element.
+  * tol > 0, FP32 / complex64: every box's measured compression error is
+    <= tol, GMRES reaches the target true residual and its iteration count is
+    within +-1 of the oracle's (golden counts from tests/golden/oracle_runs.json,
+    written by a script that calls only the oracle).
+  * batched problems and several right-hand sides give the same results as
+    separate single solves.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle.factor import OracleFactor  # noqa: E402
+from oracle.gmres import gmres as ogmres  # noqa: E402
+from paper_1508_07798_amd import hss  # noqa: E402
+from workloads import configs, partition, sipg  # noqa: E402
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_runs.json")))
+DEV = "cuda"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _relres(op, b, x):
+    return np.linalg.norm(b - op.to_scipy() @ x) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("pde,p,prec", [("poisson", 1, "fp64"), ("helmholtz", 2, "fp64"),
+                                        ("poisson", 2, "fp32"), ("helmholtz", 2, "fp32")])
+def test_exact_factorization(pde, p, prec):
+    n = 12
+    op = sipg.assemble(n, p, pde, kappa=14.0)
+    tree = partition.build_tree(n, n, 16)
+    print(f"exact: {pde} p={p} {prec}", flush=True)
+    h = hss.factor(op, tree, 0.0, prec=prec)
+    rng = np.random.default_rng(0)
+    b = rng.standard_normal(op.ndof) + (1j * rng.standard_normal(op.ndof) if op.is_complex else 0)
+    x = h.apply(_t(b)).cpu().numpy()
+    D = op.to_dense()
+    xr = np.linalg.solve(D, b)
+    cond = np.linalg.cond(D)
+    eps = 1e-16 if prec == "fp64" else 6e-8
+    assert np.linalg.norm(x - xr) <= 50 * eps * cond * np.linalg.norm(xr)
+    if prec == "fp64":
+        _, info = h.gmres(_t(b), tol=1e-10)
+        assert info[0]["iters"] == 1 and info[0]["true_relres"] <= 1e-10
+    h.close()
+
+
+def test_poisson16_fp64_matches_oracle_elementwise():
+    P = configs.make("poisson_p1_16")
+    h = hss.factor(P.op, P.tree, P.tol, prec="fp64", seed=P.seed)
+    F = OracleFactor(P.op, P.tree, P.tol, seed=P.seed)
+    heap = h.query("node_heap").astype(int)
+    ranks = dict(zip(heap, h.query("ranks").astype(int)))
+    assert ranks == F.ranks()
+    errs = h.query("err")
+    assert errs.max() <= P.tol
+    for s, e in zip(heap, errs):
+        assert abs(e - F.nodes[s].log.result.err) <= 1e-6 * P.tol
+    b = P.rhs[:, 0]
+    y = h.apply(_t(b)).cpu().numpy()
+    yr = F.apply(b)
+    assert np.linalg.norm(y - yr) <= 1e-10 * np.linalg.norm(yr)
+    x, info = h.gmres(_t(b), tol=P.gmres_tol)
+    g = GOLD["poisson_p1_16@16"]
+    assert abs(info[0]["iters"] - g["iters"]) <= 1
+    assert _relres(P.op, b, x.cpu().numpy()) <= P.gmres_tol
+    h.close()
+
+
+@pytest.mark.parametrize("name,n,prec", [("helmholtz_p2_64", 16, "fp32"), ("helmholtz_p2_64", 32, "fp32"),
+                                         ("helmholtz_p2_64", 32, "fp64")])
+def test_helmholtz_reduced(name, n, prec):
+    P = configs.make(name, n=n)
+    print(f"helmholtz n={n} {prec}", flush=True)
+    h = hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed)
+    assert h.query("max_err")[0] <= P.tol
+    assert h.query("fallbacks")[0] == 0
+    b = P.rhs[:, 0]
+    x, info = h.gmres(_t(b), tol=P.gmres_tol)
+    g = GOLD[f"{name}@{n}"]
+    assert abs(info[0]["iters"] - g["iters"]) <= 1, (info, g["iters"])
+    assert _relres(P.op, b, x.cpu().numpy()) <= P.gmres_tol
+    # ranks close to the oracle's (identical test matrices)
+    r = h.query("ranks")
+    assert abs(r.max() - g["max_rank"]) <= 2
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_helmholtz_full_size(prec):
+    P = configs.make("helmholtz_p2_64")
+    print(f"helmholtz full {prec}", flush=True)
+    vals = _t(P.op.vals)
+    h = hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, vals_dev=vals)
+    errs = h.query("err")
+    assert errs.max() <= P.tol
+    b = P.rhs[:, 0]
+    x, info = h.gmres(_t(b), tol=P.gmres_tol)
+    g = GOLD["helmholtz_p2_64@64"]
+    assert abs(info[0]["iters"] - g["iters"]) <= 1, (info, g["iters"])
+    assert info[0]["true_relres"] <= P.gmres_tol
+    assert _relres(P.op, b, x.cpu().numpy()) <= P.gmres_tol * 1.01
+    h.close()
+
+
+def test_multiple_rhs_and_batched_problems():
+    probs = [configs.make("helmholtz_p2_64", n=n, seed_offset=i, nrhs=2) for i, n in enumerate((12, 16, 20))]
+    hb = hss.factor_batched([p.op for p in probs], [p.tree for p in probs], 1e-4, prec="fp32")
+    singles = [hss.factor(p.op, p.tree, 1e-4, prec="fp32") for p in probs]
+    # apply on the concatenated vector equals the separate applies
+    xs = [np.random.default_rng(i).standard_normal((p.op.ndof, 2)) + 0j for i, p in enumerate(probs)]
+    yb = hb.apply(_t(np.concatenate(xs, axis=0))).cpu().numpy()
+    off = 0
+    for p, hs, xx in zip(probs, singles, xs):
+        ys = hs.apply(_t(xx)).cpu().numpy()
+        assert np.linalg.norm(yb[off:off + p.op.ndof] - ys) <= 1e-3 * np.linalg.norm(ys)
+        off += p.op.ndof
+    B = np.concatenate([p.rhs for p in probs], axis=0)
+    X, info = hb.gmres(_t(B), tol=1e-8, nprob=len(probs))
+    X = X.cpu().numpy()
+    off = 0
+    for i, p in enumerate(probs):
+        for k in range(2):
+            assert _relres(p.op, p.rhs[:, k], X[off:off + p.op.ndof, k]) <= 1e-8
+            xs1, inf1 = singles[i].gmres(_t(p.rhs[:, k]), tol=1e-8)
+            assert abs(info[i * 2 + k]["iters"] - inf1[0]["iters"]) <= 1
+        off += p.op.ndof
+    for hs in singles:
+        hs.close()
+    hb.close()
+
+
+def test_judge_and_growth_paths():
+    # a tiny l0 forces rank growth; the result still meets tol everywhere
+    P = configs.make("helmholtz_p2_64", n=16)
+    h = hss.factor(P.op, P.tree, P.tol, prec="fp32", seed=P.seed, l0=12)
+    assert h.query("retries")[0] > 0
+    assert h.query("max_err")[0] <= P.tol
+    x, info = h.gmres(_t(P.rhs[:, 0]), tol=1e-8)
+    assert info[0]["true_relres"] <= 1e-8
+    h.close()
+
+
+def test_gmres_maxit_reports_noconv():
+    P = configs.make("helmholtz_p2_64", n=16)
+    h = hss.factor(P.op, P.tree, 1e-1, prec="fp32", seed=P.seed)
+    x, info = h.gmres(_t(P.rhs[:, 0]), tol=1e-12, maxit=1, raise_on_noconv=False)
+    assert info[0]["status"] == hss.HSS_ENOCONV and info[0]["iters"] == 1
+    with pytest.raises(hss.HssError) as e:
+        h.gmres(_t(P.rhs[:, 0]), tol=1e-12, maxit=1)
+    assert e.value.status == hss.HSS_ENOCONV
+    h.close()
+
+
+def test_singular_block_is_reported():
+    op = sipg.assemble(8, 1)
+    op.vals = op.vals.copy()
+    tree = partition.build_tree(8, 8, 16)
+    # zero an element's rows inside a leaf interior: A_ii becomes singular
+    e = 9  # interior element of the first leaf (1, 1)
+    for b in range(op.row_ptr[e], op.row_ptr[e + 1]):
+        op.vals[b] = 0.0
+    with pytest.raises(hss.HssError) as ex:
+        hss.factor(op, tree, 1e-6, prec="fp64")
+    assert ex.value.status == hss.HSS_ESINGULAR
