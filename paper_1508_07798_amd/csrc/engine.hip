@@ -85,19 +85,69 @@ void mark_clean(hipStream_t st) {
 }
 }  // namespace
 
-// Owning list of device allocations of one phase.
+// Device memory of one phase: bump allocation from large chunks (few runtime
+// allocations), plus a staging region for host->device uploads of descriptor
+// arrays that are copied in one transfer per launch point.
 struct Arena {
   hipStream_t st = nullptr;
-  std::vector<std::pair<void*, size_t>> blocks;
+  std::vector<std::pair<void*, size_t>> chunks;
+  char* cur = nullptr;
+  size_t cap = 0, used = 0;
+  // uploads: device region [up_dev, up_dev + up_cap), host bytes not yet copied
+  char* up_dev = nullptr;
+  size_t up_cap = 0, up_used = 0, up_flushed = 0;
+  std::vector<char> up_host;  // bytes [up_flushed, up_used)
   template <class X> X* get(size_t count) {
-    size_t n = count * sizeof(X);
-    void* p = dev_alloc(n, st);
-    blocks.push_back({p, n});
-    return (X*)p;
+    size_t n = (count * sizeof(X) + 255) & ~size_t(255);
+    if (n == 0) n = 256;
+    if (!cur || used + n > cap) {
+      size_t c = std::max(n, (size_t)8 << 20);
+      cur = (char*)dev_alloc(c, st);
+      chunks.push_back({cur, c});
+      cap = c;
+      used = 0;
+    }
+    X* p = (X*)(cur + used);
+    used += n;
+    return p;
+  }
+  // returns the device address the bytes will have once flushed; `flushq`
+  // receives this arena when it holds unflushed bytes
+  template <class X> X* up(const std::vector<X>& v, std::deque<std::vector<char>>& keep,
+                           std::vector<Arena*>& flushq) {
+    if (v.empty()) return nullptr;
+    const size_t bytes = v.size() * sizeof(X);
+    size_t off = (up_used + 255) & ~size_t(255);
+    if (!up_dev || off + bytes > up_cap) {
+      flush(keep);
+      up_cap = std::max(bytes, (size_t)1 << 20);
+      up_dev = (char*)dev_alloc(up_cap, st);
+      chunks.push_back({up_dev, up_cap});
+      up_used = up_flushed = 0;
+      off = 0;
+    }
+    up_host.resize(off + bytes - up_flushed);
+    std::memcpy(up_host.data() + (off - up_flushed), v.data(), bytes);
+    up_used = off + bytes;
+    if (flushq.empty() || std::find(flushq.begin(), flushq.end(), this) == flushq.end()) flushq.push_back(this);
+    return (X*)(up_dev + off);
+  }
+  void flush(std::deque<std::vector<char>>& keep) {
+    if (up_used <= up_flushed) return;
+    keep.emplace_back(std::move(up_host));
+    up_host.clear();
+    HIP_CHECK(hipMemcpyAsync(up_dev + up_flushed, keep.back().data(), up_used - up_flushed,
+                             hipMemcpyHostToDevice, st));
+    up_flushed = up_used;
   }
   void release() {
-    for (auto& b : blocks) dev_free(b.first, b.second, st);
-    blocks.clear();
+    for (auto& b : chunks) dev_free(b.first, b.second, st);
+    chunks.clear();
+    cur = nullptr;
+    cap = used = 0;
+    up_dev = nullptr;
+    up_cap = up_used = up_flushed = 0;
+    up_host.clear();
   }
   ~Arena() { release(); }
 };
@@ -259,14 +309,17 @@ template <class T> struct Engine : EngineBase {
       if (pr.q != q) throw Error(HSS_EINVAL, "all problems of a batch must share q");
     ntot = P.ndof_total;
     if (lds_max > 65536) {
+      HIP_CHECK(hipFuncSetAttribute((const void*)cpqr_kernel<T, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
       HIP_CHECK(hipFuncSetAttribute((const void*)gj_panel_kernel<T, true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 20480));
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 4096));
       if (!std::is_same<T, W>::value)
         HIP_CHECK(hipFuncSetAttribute((const void*)gj_panel_kernel<W, true>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 20480));
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 4096));
     }
   }
   ~Engine() override {
+    flushq.clear();
     (void)hipStreamSynchronize(st);
     keep.clear();
     work.release();
@@ -275,13 +328,12 @@ template <class T> struct Engine : EngineBase {
     mark_clean(st);
   }
 
-  template <class X> X* up(const std::vector<X>& v, Arena& ar) {
-    if (v.empty()) return nullptr;
-    size_t bytes = v.size() * sizeof(X);
-    keep.emplace_back((const char*)v.data(), (const char*)v.data() + bytes);
-    X* d = ar.get<X>(v.size());
-    HIP_CHECK(hipMemcpyAsync(d, keep.back().data(), bytes, hipMemcpyHostToDevice, st));
-    return d;
+  std::vector<Arena*> flushq;  // arenas holding unflushed uploads
+  template <class X> X* up(const std::vector<X>& v, Arena& ar) { return ar.up(v, keep, flushq); }
+  // copy pending uploads before a launch that reads them
+  void fl() {
+    for (Arena* a : flushq) a->flush(keep);
+    flushq.clear();
   }
   template <class X> void h2d(X* dst, const std::vector<X>& v) {
     if (v.empty()) return;
@@ -290,8 +342,13 @@ template <class T> struct Engine : EngineBase {
     HIP_CHECK(hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, st));
   }
   void sync() {
+    fl();
     HIP_CHECK(hipStreamSynchronize(st));
     keep.clear();
+  }
+  void drop(Arena& a) {
+    flushq.erase(std::remove(flushq.begin(), flushq.end(), &a), flushq.end());
+    a.release();
   }
   void check_launch(const char* what) {
     hipError_t e = hipGetLastError();
@@ -303,21 +360,22 @@ template <class T> struct Engine : EngineBase {
   void gemm(const std::vector<GemmDesc>& ds, X alpha, X beta, int cls, Arena& ar) {
     std::vector<GemmDesc> v;
     std::vector<int> pre{0};
-    double fl = 0;
+    double flp = 0;
     for (auto& g : ds) {
       if (g.M <= 0 || g.N <= 0) continue;
       v.push_back(g);
       pre.push_back(pre.back() + cdiv(g.M, GBM) * cdiv(g.N, GBN));
-      fl += Flop<X>::mac * (double)g.M * g.N * g.K;
+      flp += Flop<X>::mac * (double)g.M * g.N * g.K;
     }
     if (v.empty()) return;
     GemmDesc* dd = up(v, ar);
     int* dp = up(pre, ar);
-    int id = prof.start(cls, fl, 0);
+    int id = prof.start(cls, flp, 0);
+    fl();
     gemm_nn_kernel<X><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), alpha, beta);
     prof.stop(id);
     check_launch("gemm");
-    if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_SAMPLE_GEMM) flops_factor += fl;
+    if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_SAMPLE_GEMM) flops_factor += flp;
   }
 
   // ---------------------------------------------------------------- GJ
@@ -328,10 +386,10 @@ template <class T> struct Engine : EngineBase {
     int nmax = 0, wmax = 0;
     for (auto& g : ds) nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W);
     const int sX = (int)sizeof(X);
-    const int avail = (lds_max > 65536 ? lds_max - 20480 : 65536 - 20480);
+    const int64_t avail = lds_max - 4096;
     int nb = 32;
     bool lds = true;
-    while (nb >= 8 && (int64_t)nmax * nb * sX > avail) nb /= 2;
+    while (nb >= 8 && ((int64_t)nmax * nb + nb * nb) * sX > avail) nb /= 2;
     if (nb < 8) {
       nb = 32;
       lds = false;
@@ -345,14 +403,16 @@ template <class T> struct Engine : EngineBase {
     }
     GjDesc<X>* dd = up(ds, ar);
     const int nn = (int)ds.size();
-    const size_t shm = lds ? (size_t)nmax * nb * sX : 0;
+    const size_t shm = lds ? ((size_t)nmax * nb + nb * nb) * sX : 0;
     for (int j0 = 0; j0 < nmax; j0 += nb) {
       int id = prof.start(C_GJ_PANEL, 0, 0);
-      if (lds) gj_panel_kernel<X, true><<<nn, 256, shm, st>>>(dd, j0, nb);
-      else gj_panel_kernel<X, false><<<nn, 256, 0, st>>>(dd, j0, nb);
+      fl();
+      if (lds) gj_panel_kernel<X, true><<<nn, GJ_PANEL_THREADS, shm, st>>>(dd, j0, nb);
+      else gj_panel_kernel<X, false><<<nn, GJ_PANEL_THREADS, 0, st>>>(dd, j0, nb);
       prof.stop(id);
       check_launch("gj_panel");
       id = prof.start(C_GJ_ROWS, 0, 0);
+      fl();
       gj_rows_kernel<X><<<dim3(cdiv(wmax, 64), nn), 256, 0, st>>>(dd, j0, nb);
       prof.stop(id);
       check_launch("gj_rows");
@@ -366,12 +426,10 @@ template <class T> struct Engine : EngineBase {
       gemm<X>(gd, m1, p1, C_GJ_UPDATE, ar);
     }
     int id = prof.start(C_GJ_UNSWAP, 0, 0);
+    fl();
     gj_unswap_kernel<X><<<dim3(cdiv(nmax, 256), nn), 256, 0, st>>>(dd);
     prof.stop(id);
     check_launch("gj_unswap");
-    double fl = 0;
-    for (auto& g : ds) fl += Flop<X>::mac * (double)g.n * g.n * g.W;
-    (void)fl;
   }
 
   // ---------------------------------------------------------------- factor
@@ -524,6 +582,7 @@ template <class T> struct Engine : EngineBase {
         auto* dS = up(Sp, tmp);
         OpDev op{d_row_ptr, d_col_idx, d_vals, q};
         int id = prof.start(C_GATHER, 0, 0);
+        fl();
         gather_kernel<T, W, T><<<dim3(grid1(maxe, 512), (unsigned)wv.size()), 256, 0, st>>>(op, dgd, dM, dA, dS);
         prof.stop(id);
         check_launch("gather");
@@ -557,7 +616,7 @@ template <class T> struct Engine : EngineBase {
       }
       // 4. compression
       compress_wave(wv, Sp, tmp);
-      tmp.release();
+      drop(tmp);
     }
     // root of every problem
     rt.assign(nprob, RootDev{});
@@ -610,6 +669,7 @@ template <class T> struct Engine : EngineBase {
       auto* dR = up(Rp, tmp);
       OpDev op{d_row_ptr, d_col_idx, d_vals, q};
       int id = prof.start(C_ROOT, 0, 0);
+      fl();
       gather_kernel<W, W, T><<<dim3(grid1(maxe, 512), (unsigned)nprob), 256, 0, st>>>(op, dgd, dR, nullptr, nullptr);
       prof.stop(id);
       check_launch("root gather");
@@ -627,7 +687,7 @@ template <class T> struct Engine : EngineBase {
       std::vector<int> sing(nn + nprob + 1);
       HIP_CHECK(hipMemcpyAsync(sing.data(), d_sing, sizeof(int) * sing.size(), hipMemcpyDeviceToHost, st));
       sync();
-      tmp.release();
+      drop(tmp);
       for (auto& a : wave_st) a.release();
       for (int g = 0; g < nn; ++g) nd[g].St = nullptr;
       for (int g = 0; g < nn + nprob; ++g)
@@ -726,6 +786,7 @@ template <class T> struct Engine : EngineBase {
     {
       auto* d = up(all, tmp);
       int id = prof.start(C_SYMM, 0, 0);
+      fl();
       symm_norm_kernel<T><<<dim3(grid1(maxe, 256), nb_boxes), 256, 0, st>>>(d);
       prof.stop(id);
       check_launch("symm");
@@ -828,6 +889,7 @@ template <class T> struct Engine : EngineBase {
       auto* dhs = up(hs, at);
       {
         int id = prof.start(C_OMEGA, 0, 0);
+        fl();
         omega_kernel<T><<<dim3(grid1(maxol, 256), na), 256, 0, st>>>(dbx, o.seed);
         prof.stop(id);
         check_launch("omega");
@@ -837,11 +899,19 @@ template <class T> struct Engine : EngineBase {
         if (byh[hh].empty()) continue;
         int* dl = up(byh[hh], at);
         int id = prof.start(C_SAMPLE, 0, 0);
+        fl();
         sample_kernel<T><<<(unsigned)byh[hh].size(), 256, 0, st>>>(dbx, dhs, dl);
         prof.stop(id);
         check_launch("sample");
         id = prof.start(C_ID, 0, 0);
-        cpqr_kernel<T><<<(unsigned)byh[hh].size(), 256, 0, st>>>(dbx, dhs, dl, tol, o.p_os);
+        fl();
+        {
+          int zmax = 0;
+          for (int t : byh[hh]) zmax = std::max(zmax, hs[t].zcap);
+          const size_t shm = (size_t)lmax * zmax * sizeof(T);
+          if (shm <= (lds_max > 65536 ? 65536 : 32768)) cpqr_kernel<T, true><<<(unsigned)byh[hh].size(), 256, shm, st>>>(dbx, dhs, dl, o.p_os);
+          else cpqr_kernel<T, false><<<(unsigned)byh[hh].size(), 256, 0, st>>>(dbx, dhs, dl, o.p_os);
+        }
         prof.stop(id);
         check_launch("cpqr");
       }
@@ -849,6 +919,7 @@ template <class T> struct Engine : EngineBase {
         if (byh[hh].empty()) continue;
         int* dl = up(byh[hh], at);
         int id = prof.start(C_UTALL, 0, 0);
+        fl();
         utall_kernel<T><<<(unsigned)byh[hh].size(), 256, 0, st>>>(dbx, dhs, dl);
         prof.stop(id);
         check_launch("utall");
@@ -856,36 +927,39 @@ template <class T> struct Engine : EngineBase {
       {
         int* dl = up(leaves, at);
         int id = prof.start(C_EXPAND, 0, 0);
+        fl();
         diag_copy_kernel<T><<<(unsigned)leaves.size(), 256, 0, st>>>(dbx, dhs, dl);
         check_launch("diag_copy");
         if (!tiles.empty()) {
           auto* dt = up(tiles, at);
+          fl();
           expand_kernel<T><<<(unsigned)tiles.size(), 256, (size_t)lmax * tw * sizeof(T), st>>>(dbx, dhs, dt, tw);
           check_launch("expand");
         }
         prof.stop(id);
         id = prof.start(C_JUDGE, 0, 0);
+        fl();
         judge_kernel<T><<<dim3(grid1(maxe, 64), na), 256, 0, st>>>(dbx);
         prof.stop(id);
         check_launch("judge");
       }
       std::vector<double> err(na);
-      std::vector<int> fl(3 * na);
+      std::vector<int> flh(3 * na);
       HIP_CHECK(hipMemcpyAsync(err.data(), d_err, sizeof(double) * na, hipMemcpyDeviceToHost, st));
-      HIP_CHECK(hipMemcpyAsync(fl.data(), d_flags, sizeof(int) * 3 * na, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipMemcpyAsync(flh.data(), d_flags, sizeof(int) * 3 * na, hipMemcpyDeviceToHost, st));
       sync();
-      at.release();
+      drop(at);
       std::vector<int> next;
       for (int a = 0; a < na; ++a) {
         const int i = todo[a];
         const int g = wv[i];
         att[i] += 1;
         const double e = nrm[i] > 0 ? std::sqrt(err[a] / nrm[i]) : 0.0;
-        const bool exhausted = fl[a] & 1;
+        const bool exhausted = flh[a] & 1;
         const int lcap = std::min(all[i].n + o.p_os, 256);
-        rank_v[g] = fl[na + a];
+        rank_v[g] = flh[na + a];
         float tm;
-        std::memcpy(&tm, &fl[2 * na + a], sizeof(float));
+        std::memcpy(&tm, &flh[2 * na + a], sizeof(float));
         tmax_v[g] = tm;
         err_v[g] = e;
         l_v[g] = lcur[i];
@@ -922,6 +996,7 @@ template <class T> struct Engine : EngineBase {
         me = std::max<int64_t>(me, (int64_t)b.n * b.n);
       }
       auto* d = up(cb, tmp);
+      fl();
       copy_box_kernel<T><<<dim3(grid1(me, 256), (unsigned)cb.size()), 256, 0, st>>>(d);
       check_launch("copy_box");
     }
@@ -1201,7 +1276,7 @@ template <class T> struct Engine : EngineBase {
     HIP_CHECK(hipMemcpy2DAsync(xv, ld * sizeof(W), X, ntot * sizeof(W), ntot * sizeof(W), nrhs,
                                hipMemcpyDeviceToDevice, st));
     sync();
-    ga.release();
+    drop(ga);
     mark_clean(st);
     prof.collect();
     int status = HSS_OK;

@@ -37,88 +37,130 @@ template <class R> __device__ inline void argmax_pair(R& v, int& i, R v2, int i2
   }
 }
 
+constexpr int GJ_PANEL_THREADS = 512;
+
+// LU with partial pivoting of the panel rows j0..n-1, columns j0..j0+w-1.
+// Rows are not moved: the pivot of column c is tracked as a physical row and
+// every thread keeps updating the rows it owns, so one barrier per column
+// suffices (the argmax partials are double buffered). The physical pivot
+// sequence is turned into the usual sequence of row interchanges at the end.
+// Dynamic LDS: the panel (Rr x w) plus w x w for Pinv, or a global scratch
+// panel when it does not fit.
 template <class T, bool LDS>
-__global__ __launch_bounds__(256) void gj_panel_kernel(const GjDesc<T>* __restrict__ descs,
-                                                       int j0, int nb) {
+__global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc<T>* __restrict__ descs,
+                                                                    int j0, int nb) {
   using R = typename traits<T>::real;
+  constexpr int NT = GJ_PANEL_THREADS, NW = NT / 64;
   const GjDesc<T> g = descs[blockIdx.x];
   if (j0 >= g.n) return;
   const int w = min(nb, g.n - j0);
   const int Rr = g.n - j0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* P = LDS ? (T*)smem_raw : g.gpanel;
-  __shared__ R red_v[4];
-  __shared__ int red_i[4];
-  __shared__ int s_piv[64];
-  __shared__ T s_inv[32 * 32];
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < Rr * w; idx += 256) {
-    int r = idx % Rr, c = idx / Rr;
+  T* Pi = LDS ? (T*)smem_raw + (size_t)Rr * w : g.pinv;  // w x w (ld w)
+  __shared__ R red_v[2][NW];
+  __shared__ int red_i[2][NW];
+  __shared__ int s_pphys[64];   // physical pivot row of each panel column
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int idx = tid; idx < Rr * w; idx += NT) {
+    const int r = idx % Rr, c = idx / Rr;
     P[r + (size_t)c * Rr] = g.M[(j0 + r) + (size_t)(j0 + c) * g.n];
   }
   __syncthreads();
+  // pivoted[r] is implied by s_pphys; each thread tracks its own rows' state in a bit mask
+  // (at most Rr / NT + 1 rows per thread, <= 64 supported)
+  unsigned long long mine = 0;  // bit t set: row tid + t*NT already chosen as a pivot
   for (int c = 0; c < w; ++c) {
+    // partial argmax of |P(r, c)|^2 over not-yet-pivoted rows
     R best = -1;
     int bi = 0x7fffffff;
-    for (int r = c + tid; r < Rr; r += 256) {
-      R v = traits<T>::abs2(P[r + (size_t)c * Rr]);
+    int t = 0;
+    for (int r = tid; r < Rr; r += NT, ++t) {
+      if ((mine >> t) & 1ull) continue;
+      const R v = traits<T>::abs2(P[r + (size_t)c * Rr]);
       argmax_pair(best, bi, v, r);
     }
     for (int off = 32; off > 0; off >>= 1) {
-      R v2 = __shfl_xor(best, off);
-      int i2 = __shfl_xor(bi, off);
+      const R v2 = __shfl_xor(best, off);
+      const int i2 = __shfl_xor(bi, off);
       argmax_pair(best, bi, v2, i2);
     }
-    if ((tid & 63) == 0) {
-      red_v[tid >> 6] = best;
-      red_i[tid >> 6] = bi;
+    if (lane == 0) {
+      red_v[c & 1][wave] = best;
+      red_i[c & 1][wave] = bi;
     }
     __syncthreads();
-    if (tid == 0) {
-      R bv = red_v[0];
-      int bidx = red_i[0];
-      for (int k = 1; k < 4; ++k) argmax_pair(bv, bidx, red_v[k], red_i[k]);
-      // a NaN column leaves no candidate: keep the diagonal row
-      if (bidx < c || bidx >= Rr) bidx = c;
-      s_piv[c] = bidx;
-    }
-    __syncthreads();
-    const int p = s_piv[c];
-    if (p != c)
-      for (int cc = tid; cc < w; cc += 256) {
-        T tmp = P[c + (size_t)cc * Rr];
-        P[c + (size_t)cc * Rr] = P[p + (size_t)cc * Rr];
-        P[p + (size_t)cc * Rr] = tmp;
+    R bv = red_v[c & 1][0];
+    int p = red_i[c & 1][0];
+    for (int k = 1; k < NW; ++k) argmax_pair(bv, p, red_v[c & 1][k], red_i[c & 1][k]);
+    if (p < 0 || p >= Rr) {  // a NaN column leaves no candidate: take the first free row
+      p = 0;
+      for (int r = 0; r < Rr; ++r) {
+        bool used = false;
+        for (int q = 0; q < c; ++q) used |= (s_pphys[q] == r);
+        if (!used) {
+          p = r;
+          break;
+        }
       }
-    __syncthreads();
-    const T pv = P[c + (size_t)c * Rr];
+    }
+    if (tid == 0) s_pphys[c] = p;
+    if (p % NT == tid) mine |= 1ull << (p / NT);
+    const T pv = P[p + (size_t)c * Rr];
     const bool zero = traits<T>::abs2(pv) == 0;
     if (zero && tid == 0) *g.flag = 1;
     const T inv = zero ? traits<T>::zero() : sc_inv(pv);
-    for (int r = c + 1 + tid; r < Rr; r += 256) {
-      T l = sc_mul(P[r + (size_t)c * Rr], inv);
+    t = 0;
+    for (int r = tid; r < Rr; r += NT, ++t) {
+      if ((mine >> t) & 1ull) continue;
+      const T l = sc_mul(P[r + (size_t)c * Rr], inv);
       P[r + (size_t)c * Rr] = l;
       for (int cc = c + 1; cc < w; ++cc)
-        P[r + (size_t)cc * Rr] = sc_fms(P[r + (size_t)cc * Rr], l, P[c + (size_t)cc * Rr]);
+        P[r + (size_t)cc * Rr] = sc_fms(P[r + (size_t)cc * Rr], l, P[p + (size_t)cc * Rr]);
+    }
+  }
+  __syncthreads();
+  // interchange sequence (LAPACK style: row j0+c <-> row piv[j0+c], in order) from the
+  // physical pivot rows; phys_at / pos_of live in the csave scratch (2 Rr ints <= n nb T)
+  {
+    int* phys_at = (int*)g.csave;
+    int* pos_of = phys_at + Rr;
+    for (int r = tid; r < Rr; r += NT) {
+      phys_at[r] = r;
+      pos_of[r] = r;
     }
     __syncthreads();
+    if (tid == 0) {
+      for (int c = 0; c < w; ++c) {
+        const int pp = s_pphys[c];
+        const int q = pos_of[pp];
+        const int pc = phys_at[c];
+        phys_at[c] = pp;
+        phys_at[q] = pc;
+        pos_of[pp] = c;
+        pos_of[pc] = q;
+        g.piv[j0 + c] = j0 + q;
+      }
+    }
   }
-  if (tid < w) g.piv[j0 + tid] = j0 + s_piv[tid];
-  // Pinv = U11^{-1} L11^{-1}, one column per thread
+  // Pinv = U11^{-1} L11^{-1}; row c of L11 / U11 is physical row s_pphys[c]
   if (tid < w) {
     const int j = tid;
     for (int i = 0; i < w; ++i) {
       T y = (i == j) ? traits<T>::one() : traits<T>::zero();
-      for (int k = 0; k < i; ++k) y = sc_fms(y, P[i + (size_t)k * Rr], s_inv[k + j * 32]);
-      s_inv[i + j * 32] = y;
+      const int pi = s_pphys[i];
+      for (int k = 0; k < i; ++k) y = sc_fms(y, P[pi + (size_t)k * Rr], Pi[k + j * w]);
+      Pi[i + j * w] = y;
     }
     for (int i = w - 1; i >= 0; --i) {
-      T x = s_inv[i + j * 32];
-      for (int k = i + 1; k < w; ++k) x = sc_fms(x, P[i + (size_t)k * Rr], s_inv[k + j * 32]);
-      T d = P[i + (size_t)i * Rr];
-      s_inv[i + j * 32] = traits<T>::abs2(d) == 0 ? x : sc_mul(x, sc_inv(d));
+      const int pi = s_pphys[i];
+      T x = Pi[i + j * w];
+      for (int k = i + 1; k < w; ++k) x = sc_fms(x, P[pi + (size_t)k * Rr], Pi[k + j * w]);
+      const T d = P[pi + (size_t)i * Rr];
+      Pi[i + j * w] = traits<T>::abs2(d) == 0 ? x : sc_mul(x, sc_inv(d));
     }
-    for (int i = 0; i < w; ++i) g.pinv[i + j * w] = s_inv[i + j * 32];
+    if (LDS)
+      for (int i = 0; i < w; ++i) g.pinv[i + j * w] = Pi[i + j * w];
   }
 }
 

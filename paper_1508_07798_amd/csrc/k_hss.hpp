@@ -124,15 +124,21 @@ __global__ __launch_bounds__(256) void symm_norm_kernel(const CompBox<T>* __rest
   if (threadIdx.x == 0) atomicAdd(b.nrm2, red[0]);
 }
 
-// one workgroup per HSS node of one height: candidates and samples
+// One workgroup per HSS node of one height: candidates and samples
+// Z = Y(R, :) - S(R, tau) Omega(tau, :), written transposed (Zt, l x m). Output
+// tiles of 64 x 64 (4 x 4 per thread); the product runs over tau in slabs of 16
+// staged through LDS.
 template <class T>
 __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restrict__ bx,
                                                      const HssDesc<T>* __restrict__ hs,
                                                      const int* __restrict__ list) {
+  constexpr int KC = 16;
   const HssDesc<T> h = hs[list[blockIdx.x]];
   const CompBox<T> b = bx[h.box];
   __shared__ int s_cand[512];
   __shared__ int s_m;
+  __shared__ T Sg[64][KC + 1];
+  __shared__ T Og[KC][65];
   const int tid = threadIdx.x;
   if (h.left < 0) {
     for (int i = tid; i < h.hi - h.lo; i += 256) s_cand[i] = h.lo + i;
@@ -148,145 +154,206 @@ __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restric
   const int m = s_m;
   for (int i = tid; i < m; i += 256) h.cand[i] = s_cand[i];
   const int l = b.l, n = b.n;
-  // Zt (l x m, column r = samples of candidate r)
-  for (int e = tid; e < m * l; e += 256) {
-    const int r = e % m, c = e / m;
-    const int row = s_cand[r];
-    T acc = b.Y[row + (size_t)c * n];
-    for (int j = h.lo; j < h.hi; ++j) acc = sc_fms(acc, b.S[row + (size_t)j * n], b.Om[j + (size_t)c * n]);
-    h.Zt[c + (size_t)r * l] = acc;
+  const int tx = tid % 16, ty = tid / 16;
+  for (int r0 = 0; r0 < m; r0 += 64) {
+    for (int c0 = 0; c0 < l; c0 += 64) {
+      T acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[a][q] = traits<T>::zero();
+      for (int j0 = h.lo; j0 < h.hi; j0 += KC) {
+        __syncthreads();
+        for (int e = tid; e < 64 * KC; e += 256) {
+          const int rr = e % 64, kk = e / 64;
+          const int r = r0 + rr, jj = j0 + kk;
+          Sg[rr][kk] = (r < m && jj < h.hi) ? b.S[s_cand[r] + (size_t)jj * n] : traits<T>::zero();
+        }
+        for (int e = tid; e < KC * 64; e += 256) {
+          const int kk = e % KC, cc = e / KC;
+          const int jj = j0 + kk, c = c0 + cc;
+          Og[kk][cc] = (jj < h.hi && c < l) ? b.Om[jj + (size_t)c * n] : traits<T>::zero();
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < KC; ++kk) {
+          T sv[4], ov[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) sv[a] = Sg[ty * 4 + a][kk];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) ov[q] = Og[kk][tx * 4 + q];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] = acc[a][q] + sc_mul(sv[a], ov[q]);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int r = r0 + ty * 4 + a;
+        if (r >= m) continue;
+        const int row = s_cand[r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = c0 + tx * 4 + q;
+          if (c < l) h.Zt[c + (size_t)r * l] = b.Y[row + (size_t)c * n] - acc[a][q];
+        }
+      }
+    }
   }
   if (tid == 0) *h.k = m;  // provisional: number of candidates (read by cpqr)
 }
 
-// one workgroup per HSS node: truncated CPQR of Zt (l x m) -> k, skeleton, U
-template <class T>
+// One workgroup per HSS node: truncated CPQR of Zt (l x m) -> k, skeleton, U.
+// The matrix sits in LDS when it fits (LDS = true), else it is used in place.
+// Columns are never moved: the pivot of step j is a physical column chosen
+// from exact trailing norms; every wave takes the same decision from the
+// same LDS data (bit-identical butterfly reductions), so one barrier per step
+// suffices. Groups of 16 lanes apply the Householder reflector to one column
+// each and produce that column's trailing norm for the next step.
+template <class T, bool LDS>
 __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict__ bx,
                                                    const HssDesc<T>* __restrict__ hs,
-                                                   const int* __restrict__ list, double tol,
-                                                   int p_os) {
-  using R = typename traits<T>::real;
+                                                   const int* __restrict__ list, int p_os) {
+  constexpr int GL = 16;
   const HssDesc<T> h = hs[list[blockIdx.x]];
   const CompBox<T> b = bx[h.box];
   const int l = b.l;
   const int m = *h.k;
-  T* A = h.Zt;  // l x m, ld = l
-  __shared__ double s_nrm[512];
-  __shared__ int s_perm[512];
-  __shared__ T s_v[256];
-  __shared__ double red[256];
-  __shared__ int s_k, s_p;
-  __shared__ double s_tot;
-  const int tid = threadIdx.x;
-  const double thresh = b.tol_scale * sqrt(*b.nrm2) / sqrt(2.0 * (double)max(b.n_id, 1)) *
-                        sqrt((double)l);
-  for (int i = tid; i < m; i += 256) s_perm[i] = i;
-  const int kcap = min(l, m);
-  int k = kcap;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* A = LDS ? (T*)smem_raw : h.Zt;  // l x m, ld = l
+  __shared__ double s_nrm[2][512];  // double buffered: read step j, write step j + 1
+  __shared__ int s_sel[256];
+  __shared__ T s_rdiag[256];
+  __shared__ int s_k;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int gid = wave * (64 / GL) + (lane / GL), gl = lane % GL;
+  if (LDS)
+    for (int e = tid; e < l * m; e += 256) A[e] = h.Zt[e];
   __syncthreads();
+  // initial norms
+  for (int c0 = 0; c0 < m; c0 += 16) {
+    const int c = c0 + gid;
+    double s2 = 0;
+    if (c < m)
+      for (int r = gl; r < l; r += GL) s2 += (double)traits<T>::abs2(A[r + (size_t)c * l]);
+    for (int off = GL / 2; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+    if (c < m && gl == 0) s_nrm[0][c] = s2;
+  }
+  __syncthreads();
+  const double thresh = b.tol_scale * sqrt(*b.nrm2) / sqrt(2.0 * (double)max(b.n_id, 1)) * sqrt((double)l);
+  const int kcap = min(l, m);
+  unsigned chosen = 0;  // bit t: column lane + 64 t was a pivot (identical in every wave)
+  int k = kcap;
   for (int j = 0; j < kcap; ++j) {
-    // exact norms of the remaining columns over rows j..l-1
-    for (int c = j + tid; c < m; c += 256) {
-      double s = 0;
-      const T* col = A + (size_t)c * l;
-      for (int r = j; r < l; ++r) s += (double)traits<T>::abs2(col[r]);
-      s_nrm[c] = s;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double tot = 0, best = -1;
-      int bi = j;
-      for (int c = j; c < m; ++c) {
-        tot += s_nrm[c];
-        if (s_nrm[c] > best) {
-          best = s_nrm[c];
-          bi = c;
-        }
+    // pivot: largest trailing norm among free columns (ties: lowest index); total = ||R22||_F^2
+    double best = -1.0, tot = 0.0;
+    int bi = 0x7fffffff;
+    for (int t = 0; lane + 64 * t < m; ++t) {
+      if ((chosen >> t) & 1u) continue;
+      const int c = lane + 64 * t;
+      const double v = s_nrm[j & 1][c];
+      tot += v;
+      if (v > best) {
+        best = v;
+        bi = c;
       }
-      s_tot = tot;
-      s_p = bi;
     }
-    __syncthreads();
-    if (sqrt(s_tot) <= thresh) {
+    for (int off = 32; off > 0; off >>= 1) {
+      tot += __shfl_xor(tot, off);
+      const double v2 = __shfl_xor(best, off);
+      const int i2 = __shfl_xor(bi, off);
+      if (v2 > best || (v2 == best && i2 < bi)) {
+        best = v2;
+        bi = i2;
+      }
+    }
+    if (sqrt(tot) <= thresh || bi >= m) {
       k = j;
       break;
     }
-    const int p = s_p;
-    if (p != j) {
-      for (int r = tid; r < l; r += 256) {
-        T t = A[r + (size_t)j * l];
-        A[r + (size_t)j * l] = A[r + (size_t)p * l];
-        A[r + (size_t)p * l] = t;
-      }
-      if (tid == 0) {
-        int t = s_perm[j];
-        s_perm[j] = s_perm[p];
-        s_perm[p] = t;
-      }
-    }
-    __syncthreads();
-    // Householder vector of A(j:l, j)
-    const T x0 = A[j + (size_t)j * l];
-    const double xn2 = s_nrm[p];
+    const int p = bi;
+    if ((p & 63) == lane) chosen |= 1u << (p >> 6);
+    if (tid == 0) s_sel[j] = p;
+    // reflector H = I - 2 v v^H / (v^H v) with v = x - alpha e1, x = A(j:l, p)
+    const T x0 = A[j + (size_t)p * l];
+    const double xn2 = s_nrm[j & 1][p];
     const double xn = sqrt(xn2);
     const double a0 = sqrt((double)traits<T>::abs2(x0));
-    // alpha = -(x0/|x0|) ||x||
     T alpha;
     if (a0 > 0) alpha = traits<T>::mk(-traits<T>::re(x0) / a0 * xn, -traits<T>::im(x0) / a0 * xn);
     else alpha = traits<T>::mk(-xn, 0.0);
-    const double vv = 2.0 * xn2 + 2.0 * a0 * xn;  // ||x - alpha e1||^2
-    for (int r = j + tid; r < l; r += 256) {
-      T v = A[r + (size_t)j * l];
-      if (r == j) v = v - alpha;
-      s_v[r - j] = v;
-    }
-    __syncthreads();
-    if (vv > 0) {
-      for (int c = j + 1 + tid; c < m; c += 256) {
-        T* col = A + (size_t)c * l;
-        T w = traits<T>::zero();
-        for (int r = j; r < l; ++r) w = w + sc_mul(traits<T>::conj(s_v[r - j]), col[r]);
-        const double f = 2.0 / vv;
-        const T fw = traits<T>::mk(traits<T>::re(w) * f, traits<T>::im(w) * f);
-        for (int r = j; r < l; ++r) col[r] = sc_fms(col[r], fw, s_v[r - j]);
+    if (tid == 0) s_rdiag[j] = alpha;
+    const double vv = 2.0 * xn2 + 2.0 * a0 * xn;
+    const T vj = x0 - alpha;
+    const int ncol_iter = (m + 15) / 16;
+    for (int it = 0; it < ncol_iter; ++it) {
+      const int c = it * 16 + gid;
+      const int cc = c < m ? c : 0;
+      const unsigned mw = __shfl(chosen, cc & 63);
+      const bool active = c < m && c != p && !((mw >> (cc >> 6)) & 1u);
+      T dot = traits<T>::zero();
+      if (active && vv > 0)
+        for (int r = j + gl; r < l; r += GL) {
+          const T vr = (r == j) ? vj : A[r + (size_t)p * l];
+          dot = dot + sc_mul(traits<T>::conj(vr), A[r + (size_t)c * l]);
+        }
+      for (int off = GL / 2; off > 0; off >>= 1) {
+        const double dr = __shfl_xor((double)traits<T>::re(dot), off);
+        const double di = __shfl_xor((double)traits<T>::im(dot), off);
+        dot = traits<T>::mk((double)traits<T>::re(dot) + dr, (double)traits<T>::im(dot) + di);
       }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      A[j + (size_t)j * l] = alpha;
-      for (int r = j + 1; r < l; ++r) A[r + (size_t)j * l] = traits<T>::zero();
+      double s2 = 0;
+      if (active) {
+        const double f = vv > 0 ? 2.0 / vv : 0.0;
+        const T fw = traits<T>::mk(traits<T>::re(dot) * f, traits<T>::im(dot) * f);
+        for (int r = j + gl; r < l; r += GL) {
+          const T vr = (r == j) ? vj : A[r + (size_t)p * l];
+          const T nv = sc_fms(A[r + (size_t)c * l], fw, vr);
+          A[r + (size_t)c * l] = nv;
+          if (r > j) s2 += (double)traits<T>::abs2(nv);
+        }
+      }
+      for (int off = GL / 2; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+      if (active && gl == 0) s_nrm[(j + 1) & 1][c] = s2;
     }
     __syncthreads();
   }
   if (tid == 0) s_k = k;
   __syncthreads();
   k = s_k;
-  // T = R11^{-1} R12 in place (columns k..m-1, rows 0..k-1), one column per thread
+  // T = R11^{-1} R12 for every free column (in place in rows 0..k-1), one column per thread
   float tm = 0.f;
-  for (int c = k + tid; c < m; c += 256) {
+  for (int c = tid; c < m; c += 256) {
+    bool sk = false;
+    for (int i = 0; i < k; ++i) sk |= (s_sel[i] == c);
+    if (sk) continue;
     T* col = A + (size_t)c * l;
     for (int i = k - 1; i >= 0; --i) {
       T x = col[i];
-      for (int jj = i + 1; jj < k; ++jj) x = sc_fms(x, A[i + (size_t)jj * l], col[jj]);
-      const T d = A[i + (size_t)i * l];
+      for (int jj = i + 1; jj < k; ++jj) x = sc_fms(x, A[i + (size_t)s_sel[jj] * l], col[jj]);
+      const T d = s_rdiag[i];
       x = traits<T>::abs2(d) > 0 ? sc_mul(x, sc_inv(d)) : traits<T>::zero();
       col[i] = x;
       tm = fmaxf(tm, (float)sqrt((double)traits<T>::abs2(x)));
     }
   }
   __syncthreads();
-  // U (m x k, ld zcap): rows perm[0..k) = I, rows perm[k..m) = T^T
+  // U (m x k, ld zcap): row sel[i] = e_i, free row c = T(:, c)^T
   for (int e = tid; e < m * k; e += 256) {
-    const int r = e % m, c = e / m;  // r: position in pivot order
+    const int c = e % m, i = e / m;
+    int pos = -1;
+    for (int q = 0; q < k; ++q)
+      if (s_sel[q] == c) pos = q;
     T v;
-    if (r < k) v = (r == c) ? traits<T>::one() : traits<T>::zero();
-    else v = A[c + (size_t)r * l];
-    h.U[s_perm[r] + (size_t)c * h.zcap] = v;
+    if (pos >= 0) v = (pos == i) ? traits<T>::one() : traits<T>::zero();
+    else v = A[i + (size_t)c * l];
+    h.U[c + (size_t)i * h.zcap] = v;
   }
-  for (int i = tid; i < k; i += 256) h.skel[i] = h.cand[s_perm[i]];
-  // stats
+  for (int i = tid; i < k; i += 256) h.skel[i] = h.cand[s_sel[i]];
   for (int off = 32; off > 0; off >>= 1) tm = fmaxf(tm, __shfl_xor(tm, off));
-  if ((tid & 63) == 0) atomicMax((int*)b.tmax, __float_as_int(tm));
+  if (lane == 0) atomicMax((int*)b.tmax, __float_as_int(tm));
+  __syncthreads();
   if (tid == 0) {
     *h.k = k;
     atomicMax(b.kmax, k);
