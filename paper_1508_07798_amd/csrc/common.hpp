@@ -134,3 +134,76 @@ struct Error : std::runtime_error {
                                  " at " + __FILE__ + ":" + std::to_string(__LINE__));     \
   } while (0)
 #endif
+
+#ifdef __HIPCC__
+namespace hss {
+// ------------------------------------------------------------------ DPP reductions
+// Cross-lane moves within 16-lane rows of a wave64 (gfx9 DPP encodings):
+// 0xB1 = quad_perm [1,0,3,2], 0x4E = quad_perm [2,3,0,1],
+// 0x141 = row_half_mirror (8 lanes), 0x140 = row_mirror (16 lanes).
+// Each step pairs every lane with one partner, so after log2(width) steps all
+// lanes of a group hold the same, bit-identical result (a + b == b + a).
+template <int CTRL> __device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_v(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_v(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL>((int)(b & 0xffffffffll));
+  const int hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double rdlane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// sum over aligned groups of GL (2, 4, 8 or 16) lanes
+template <int GL, class R> __device__ __forceinline__ R group_sum(R v) {
+  static_assert(GL == 2 || GL == 4 || GL == 8 || GL == 16, "group width");
+  v = v + dpp_v<0xB1>(v);
+  if (GL >= 4) v = v + dpp_v<0x4E>(v);
+  if (GL >= 8) v = v + dpp_v<0x141>(v);
+  if (GL >= 16) v = v + dpp_v<0x140>(v);
+  return v;
+}
+// sum over the whole wave, uniform result (rows combined in a fixed order)
+template <class R> __device__ __forceinline__ R wave_sum(R v) {
+  v = group_sum<16>(v);
+  return ((rdlane(v, 0) + rdlane(v, 16)) + rdlane(v, 32)) + rdlane(v, 48);
+}
+// (value, index) maximum with ties to the lowest index over the whole wave; uniform
+template <class R> __device__ __forceinline__ void wave_argmax(R& v, int& i) {
+  auto step = [&](R v2, int i2) {
+    if (v2 > v || (v2 == v && i2 < i)) {
+      v = v2;
+      i = i2;
+    }
+  };
+  step(dpp_v<0xB1>(v), dpp_i<0xB1>(i));
+  step(dpp_v<0x4E>(v), dpp_i<0x4E>(i));
+  step(dpp_v<0x141>(v), dpp_i<0x141>(i));
+  step(dpp_v<0x140>(v), dpp_i<0x140>(i));
+  R bv = rdlane(v, 0);
+  int bi = rdlane(i, 0);
+  for (int r = 16; r < 64; r += 16) {
+    const R v2 = rdlane(v, r);
+    const int i2 = rdlane(i, r);
+    if (v2 > bv || (v2 == bv && i2 < bi)) {
+      bv = v2;
+      bi = i2;
+    }
+  }
+  v = bv;
+  i = bi;
+}
+}  // namespace hss
+#endif

@@ -309,13 +309,13 @@ template <class T> struct Engine : EngineBase {
       if (pr.q != q) throw Error(HSS_EINVAL, "all problems of a batch must share q");
     ntot = P.ndof_total;
     if (lds_max > 65536) {
-      HIP_CHECK(hipFuncSetAttribute((const void*)cpqr_kernel<T, true>,
+      HIP_CHECK(hipFuncSetAttribute((const void*)cpqr_kernel<T, true, 8, 8>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
-      HIP_CHECK(hipFuncSetAttribute((const void*)gj_panel_kernel<T, true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 4096));
-      if (!std::is_same<T, W>::value)
-        HIP_CHECK(hipFuncSetAttribute((const void*)gj_panel_kernel<W, true>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 4096));
+      HIP_CHECK(hipFuncSetAttribute((const void*)cpqr_kernel<T, true, 16, 16>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
+      for (const void* f : {(const void*)gj_panel_kernel<T, true, 16>, (const void*)gj_panel_kernel<T, true, 32>,
+                            (const void*)gj_panel_kernel<W, true, 16>, (const void*)gj_panel_kernel<W, true, 32>})
+        HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 4096));
     }
   }
   ~Engine() override {
@@ -356,29 +356,65 @@ template <class T> struct Engine : EngineBase {
   }
 
   // ---------------------------------------------------------------- GEMM
-  template <class X>
-  void gemm(const std::vector<GemmDesc>& ds, X alpha, X beta, int cls, Arena& ar) {
+  struct GemmLaunch {
+    GemmDesc* d = nullptr;
+    int* pre = nullptr;
+    int n = 0, tiles = 0;
+    double flops = 0;
+  };
+  // uploads the descriptors (copied at the next launch point)
+  template <class X> GemmLaunch prep_gemm(const std::vector<GemmDesc>& ds, Arena& ar) {
     std::vector<GemmDesc> v;
     std::vector<int> pre{0};
-    double flp = 0;
+    GemmLaunch L;
     for (auto& g : ds) {
       if (g.M <= 0 || g.N <= 0) continue;
       v.push_back(g);
       pre.push_back(pre.back() + cdiv(g.M, GBM) * cdiv(g.N, GBN));
-      flp += Flop<X>::mac * (double)g.M * g.N * g.K;
+      L.flops += Flop<X>::mac * (double)g.M * g.N * g.K;
     }
-    if (v.empty()) return;
-    GemmDesc* dd = up(v, ar);
-    int* dp = up(pre, ar);
-    int id = prof.start(cls, flp, 0);
+    if (v.empty()) return L;
+    L.d = up(v, ar);
+    L.pre = up(pre, ar);
+    L.n = (int)v.size();
+    L.tiles = pre.back();
+    return L;
+  }
+  template <class X> void run_gemm(const GemmLaunch& L, X alpha, X beta, int cls) {
+    if (L.n == 0) return;
     fl();
-    gemm_nn_kernel<X><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), alpha, beta);
+    int id = prof.start(cls, L.flops, 0);
+    gemm_nn_kernel<X><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
     prof.stop(id);
     check_launch("gemm");
-    if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_SAMPLE_GEMM) flops_factor += flp;
+    if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_SAMPLE_GEMM) flops_factor += L.flops;
+  }
+  template <class X>
+  void gemm(const std::vector<GemmDesc>& ds, X alpha, X beta, int cls, Arena& ar) {
+    run_gemm<X>(prep_gemm<X>(ds, ar), alpha, beta, cls);
   }
 
   // ---------------------------------------------------------------- GJ
+  template <class X> void launch_panel_reg(const GjDesc<X>* dd, int nn, int j0, int nb, int rpt, size_t shm) {
+#define HSS_PANEL_REG(NB_, RPT_)                                                                  \
+  if (nb == NB_ && rpt == RPT_) {                                                                 \
+    gj_panel_reg_kernel<X, NB_, RPT_><<<nn, GJ_PANEL_THREADS, shm, st>>>(dd, j0, nb);             \
+    return;                                                                                       \
+  }
+    if constexpr (sizeof(X) == 4) {
+      HSS_PANEL_REG(32, 1) HSS_PANEL_REG(32, 2) HSS_PANEL_REG(32, 3) HSS_PANEL_REG(32, 4)
+      HSS_PANEL_REG(16, 8)
+    } else if constexpr (sizeof(X) == 8) {
+      HSS_PANEL_REG(32, 1) HSS_PANEL_REG(32, 2) HSS_PANEL_REG(32, 3) HSS_PANEL_REG(16, 4)
+      HSS_PANEL_REG(8, 8)
+    } else {
+      HSS_PANEL_REG(32, 1) HSS_PANEL_REG(16, 2) HSS_PANEL_REG(16, 3) HSS_PANEL_REG(8, 4)
+    }
+#undef HSS_PANEL_REG
+    throw Error(HSS_EDEVICE, "no register panel variant for nb " + std::to_string(nb) + ", rpt " +
+                                 std::to_string(rpt));
+  }
+
   // In-place [M_ii | M_ib] -> [M_ii^{-1} | M_ii^{-1} M_ib] for a batch.
   template <class X>
   void gauss_jordan(std::vector<GjDesc<X>>& ds, Arena& ar) {
@@ -386,13 +422,24 @@ template <class T> struct Engine : EngineBase {
     int nmax = 0, wmax = 0;
     for (auto& g : ds) nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W);
     const int sX = (int)sizeof(X);
-    const int64_t avail = lds_max - 4096;
+    // register-resident panel when the tallest panel fits: rows per thread (rpt) and
+    // panel width (nb) from a budget of 192 registers for the panel values
+    const int words = sX / 4;
+    int rpt = (nmax + GJ_PANEL_THREADS - 1) / GJ_PANEL_THREADS;
+    if (rpt == 5 || rpt == 6 || rpt == 7) rpt = 8;
     int nb = 32;
-    bool lds = true;
-    while (nb >= 8 && ((int64_t)nmax * nb + nb * nb) * sX > avail) nb /= 2;
-    if (nb < 8) {
+    while (nb > 8 && rpt * nb * words > 192) nb /= 2;
+    bool reg = rpt <= 8 && rpt * nb * words <= 192 && !(sX == 16 && rpt > 6);
+    bool lds = false;
+    const int64_t avail = lds_max - 4096;
+    if (!reg) {
       nb = 32;
-      lds = false;
+      lds = true;
+      while (nb >= 16 && ((int64_t)nmax * nb + nb * nb) * sX + 8 * (int64_t)nmax > avail) nb /= 2;
+      if (nb < 16) {
+        nb = 32;
+        lds = false;
+      }
     }
     // scratch per box
     for (auto& g : ds) {
@@ -403,27 +450,33 @@ template <class T> struct Engine : EngineBase {
     }
     GjDesc<X>* dd = up(ds, ar);
     const int nn = (int)ds.size();
-    const size_t shm = lds ? ((size_t)nmax * nb + nb * nb) * sX : 0;
+    const size_t shm = reg ? 8 * (size_t)nmax : lds ? ((size_t)nmax * nb + nb * nb) * sX + 8 * (size_t)nmax : 0;
+    // every panel's trailing-update descriptors, uploaded together
+    std::vector<GemmLaunch> upd;
     for (int j0 = 0; j0 < nmax; j0 += nb) {
-      int id = prof.start(C_GJ_PANEL, 0, 0);
-      fl();
-      if (lds) gj_panel_kernel<X, true><<<nn, GJ_PANEL_THREADS, shm, st>>>(dd, j0, nb);
-      else gj_panel_kernel<X, false><<<nn, GJ_PANEL_THREADS, 0, st>>>(dd, j0, nb);
-      prof.stop(id);
-      check_launch("gj_panel");
-      id = prof.start(C_GJ_ROWS, 0, 0);
-      fl();
-      gj_rows_kernel<X><<<dim3(cdiv(wmax, 64), nn), 256, 0, st>>>(dd, j0, nb);
-      prof.stop(id);
-      check_launch("gj_rows");
       std::vector<GemmDesc> gd;
       for (auto& g : ds) {
         if (j0 >= g.n) continue;
         int w = std::min(nb, g.n - j0);
         gd.push_back({g.csave, g.rbuf, g.M, g.n, g.W, w, g.n, w, g.n});
       }
-      X m1 = traits<X>::mk(-1.0, 0.0), p1 = traits<X>::one();
-      gemm<X>(gd, m1, p1, C_GJ_UPDATE, ar);
+      upd.push_back(prep_gemm<X>(gd, ar));
+    }
+    const X m1 = traits<X>::mk(-1.0, 0.0), p1 = traits<X>::one();
+    for (int j0 = 0, pi = 0; j0 < nmax; j0 += nb, ++pi) {
+      fl();
+      int id = prof.start(C_GJ_PANEL, 0, 0);
+      if (reg) launch_panel_reg<X>(dd, nn, j0, nb, rpt, shm);
+      else if (lds && nb == 16) gj_panel_kernel<X, true, 16><<<nn, GJ_PANEL_THREADS, shm, st>>>(dd, j0, nb);
+      else if (lds) gj_panel_kernel<X, true, 32><<<nn, GJ_PANEL_THREADS, shm, st>>>(dd, j0, nb);
+      else gj_panel_kernel<X, false, 32><<<nn, GJ_PANEL_THREADS, 0, st>>>(dd, j0, nb);
+      prof.stop(id);
+      check_launch("gj_panel");
+      id = prof.start(C_GJ_ROWS, 0, 0);
+      gj_rows_kernel<X><<<dim3(cdiv(wmax, 64), nn), 256, 0, st>>>(dd, j0, nb);
+      prof.stop(id);
+      check_launch("gj_rows");
+      run_gemm<X>(upd[pi], m1, p1, C_GJ_UPDATE);
     }
     int id = prof.start(C_GJ_UNSWAP, 0, 0);
     fl();
@@ -818,7 +871,7 @@ template <class T> struct Engine : EngineBase {
       std::vector<HssDesc<T>> hs;
       std::vector<std::vector<int>> byh;
       std::vector<int> leaves;
-      std::vector<ExpandTile> tiles;
+      std::vector<HTile> tiles;
       double* d_err = at.get<double>(na);
       int* d_flags = at.get<int>(3 * na);
       int* d_kmax = d_flags + na;
@@ -883,7 +936,9 @@ template <class T> struct Engine : EngineBase {
       for (size_t t = 0; t < hs.size(); ++t)
         if (hs[t].left >= 0) {
           const int nc = hs[hs[t].right].hi - hs[hs[t].right].lo;
-          for (int c0 = 0; c0 < nc; c0 += tw) tiles.push_back({(int)t, c0});
+          const int na_ = hs[hs[t].left].hi - hs[hs[t].left].lo;
+          for (int c0 = 0; c0 < nc; c0 += tw)
+            for (int r0 = 0; r0 < na_; r0 += 64) tiles.push_back({(int)t, r0, c0});
         }
       auto* dbx = up(bx, at);
       auto* dhs = up(hs, at);
@@ -898,9 +953,14 @@ template <class T> struct Engine : EngineBase {
       for (size_t hh = 0; hh < byh.size(); ++hh) {
         if (byh[hh].empty()) continue;
         int* dl = up(byh[hh], at);
+        std::vector<HTile> stl;
+        for (int t : byh[hh])
+          for (int r0 = 0; r0 < hs[t].zcap; r0 += 64)
+            for (int c0 = 0; c0 < bx[hs[t].box].l; c0 += 64) stl.push_back({t, r0, c0});
+        HTile* dst = up(stl, at);
         int id = prof.start(C_SAMPLE, 0, 0);
         fl();
-        sample_kernel<T><<<(unsigned)byh[hh].size(), 256, 0, st>>>(dbx, dhs, dl);
+        sample_kernel<T><<<(unsigned)stl.size(), 256, 0, st>>>(dbx, dhs, dst);
         prof.stop(id);
         check_launch("sample");
         id = prof.start(C_ID, 0, 0);
@@ -909,18 +969,28 @@ template <class T> struct Engine : EngineBase {
           int zmax = 0;
           for (int t : byh[hh]) zmax = std::max(zmax, hs[t].zcap);
           const size_t shm = (size_t)lmax * zmax * sizeof(T);
-          if (shm <= (lds_max > 65536 ? 65536 : 32768)) cpqr_kernel<T, true><<<(unsigned)byh[hh].size(), 256, shm, st>>>(dbx, dhs, dl, o.p_os);
-          else cpqr_kernel<T, false><<<(unsigned)byh[hh].size(), 256, 0, st>>>(dbx, dhs, dl, o.p_os);
+          const unsigned g = (unsigned)byh[hh].size();
+          const bool in_lds = shm <= (size_t)(lds_max > 65536 ? 65536 : 32768);
+          if (lmax <= 64) {
+            if (in_lds) cpqr_kernel<T, true, 8, 8><<<g, 256, shm, st>>>(dbx, dhs, dl, o.p_os);
+            else cpqr_kernel<T, false, 8, 8><<<g, 256, 0, st>>>(dbx, dhs, dl, o.p_os);
+          } else {
+            if (in_lds) cpqr_kernel<T, true, 16, 16><<<g, 256, shm, st>>>(dbx, dhs, dl, o.p_os);
+            else cpqr_kernel<T, false, 16, 16><<<g, 256, 0, st>>>(dbx, dhs, dl, o.p_os);
+          }
         }
         prof.stop(id);
         check_launch("cpqr");
       }
       for (size_t hh = 0; hh < byh.size(); ++hh) {
         if (byh[hh].empty()) continue;
-        int* dl = up(byh[hh], at);
+        std::vector<HTile> utl;
+        for (int t : byh[hh])
+          for (int r0 = 0; r0 < hs[t].hi - hs[t].lo; r0 += 64) utl.push_back({t, r0, 0});
+        HTile* dut = up(utl, at);
         int id = prof.start(C_UTALL, 0, 0);
         fl();
-        utall_kernel<T><<<(unsigned)byh[hh].size(), 256, 0, st>>>(dbx, dhs, dl);
+        utall_kernel<T><<<(unsigned)utl.size(), 256, 0, st>>>(dbx, dhs, dut);
         prof.stop(id);
         check_launch("utall");
       }
@@ -1043,7 +1113,7 @@ template <class T> struct Engine : EngineBase {
 
   template <class X> void gemv(const GemvDesc<X>* d, int n, int maxrows, const W* x, W* y, int nrhs, int mode) {
     if (n == 0 || maxrows == 0) return;
-    gemv_kernel<X, W, 4><<<dim3(cdiv(maxrows, 64), n), 256, 0, st>>>(d, x, y, (int64_t)ntot, nrhs, mode);
+    gemv_kernel<X, W, 4><<<dim3(cdiv(maxrows, 64), n), GEMV_THREADS, 0, st>>>(d, x, y, (int64_t)ntot, nrhs, mode);
     check_launch("gemv");
   }
 

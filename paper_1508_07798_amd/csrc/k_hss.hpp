@@ -124,16 +124,24 @@ __global__ __launch_bounds__(256) void symm_norm_kernel(const CompBox<T>* __rest
   if (threadIdx.x == 0) atomicAdd(b.nrm2, red[0]);
 }
 
-// One workgroup per HSS node of one height: candidates and samples
-// Z = Y(R, :) - S(R, tau) Omega(tau, :), written transposed (Zt, l x m). Output
-// tiles of 64 x 64 (4 x 4 per thread); the product runs over tau in slabs of 16
-// staged through LDS.
+// Work item of the tiled HSS kernels: an HSS node and the first row / column
+// of the tile a workgroup computes.
+struct HTile {
+  int hnode;
+  int r0, c0;
+};
+
+// Samples of one HSS height, one workgroup per (HSS node, 64 x 64 output tile):
+// candidates, then Z = Y(R, :) - S(R, tau) Omega(tau, :) written transposed
+// (Zt, l x m). 4 x 4 outputs per thread; the product over tau runs in slabs of
+// 16 staged through LDS. Tiles beyond the candidate count exit.
 template <class T>
 __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restrict__ bx,
                                                      const HssDesc<T>* __restrict__ hs,
-                                                     const int* __restrict__ list) {
+                                                     const HTile* __restrict__ tiles) {
   constexpr int KC = 16;
-  const HssDesc<T> h = hs[list[blockIdx.x]];
+  const HTile tl = tiles[blockIdx.x];
+  const HssDesc<T> h = hs[tl.hnode];
   const CompBox<T> b = bx[h.box];
   __shared__ int s_cand[512];
   __shared__ int s_m;
@@ -152,56 +160,68 @@ __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restric
   }
   __syncthreads();
   const int m = s_m;
-  for (int i = tid; i < m; i += 256) h.cand[i] = s_cand[i];
+  if (tl.r0 == 0 && tl.c0 == 0)
+    for (int i = tid; i < m; i += 256) h.cand[i] = s_cand[i];
   const int l = b.l, n = b.n;
+  const int r0 = tl.r0, c0 = tl.c0;
+  if (r0 >= m) return;
   const int tx = tid % 16, ty = tid / 16;
-  for (int r0 = 0; r0 < m; r0 += 64) {
-    for (int c0 = 0; c0 < l; c0 += 64) {
-      T acc[4][4];
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[a][q] = traits<T>::zero();
+  // slab j0 of S(R, tau) and Omega(tau, :) in registers (4 + 4 values per thread),
+  // prefetched while the previous slab is consumed from LDS
+  T sreg[4], oreg[4];
+  auto load = [&](int j0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
+      const int rr = e % 64, kk = e / 64;
+      const int r = r0 + rr, jj = j0 + kk;
+      sreg[u] = (r < m && jj < h.hi) ? b.S[s_cand[r] + (size_t)jj * n] : traits<T>::zero();
+      const int kk2 = e % KC, cc = e / KC;
+      const int jj2 = j0 + kk2, c = c0 + cc;
+      oreg[u] = (jj2 < h.hi && c < l) ? b.Om[jj2 + (size_t)c * n] : traits<T>::zero();
+    }
+  };
+  load(h.lo);
+  for (int j0 = h.lo; j0 < h.hi; j0 += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
+      Sg[e % 64][e / 64] = sreg[u];
+      Og[e % KC][e / KC] = oreg[u];
+    }
+    __syncthreads();
+    if (j0 + KC < h.hi) load(j0 + KC);
+#pragma unroll 4
+    for (int kk = 0; kk < KC; ++kk) {
+      T sv[4], ov[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) sv[a] = Sg[ty * 4 + a][kk];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ov[q] = Og[kk][tx * 4 + q];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[a][q] = traits<T>::zero();
-      for (int j0 = h.lo; j0 < h.hi; j0 += KC) {
-        __syncthreads();
-        for (int e = tid; e < 64 * KC; e += 256) {
-          const int rr = e % 64, kk = e / 64;
-          const int r = r0 + rr, jj = j0 + kk;
-          Sg[rr][kk] = (r < m && jj < h.hi) ? b.S[s_cand[r] + (size_t)jj * n] : traits<T>::zero();
-        }
-        for (int e = tid; e < KC * 64; e += 256) {
-          const int kk = e % KC, cc = e / KC;
-          const int jj = j0 + kk, c = c0 + cc;
-          Og[kk][cc] = (jj < h.hi && c < l) ? b.Om[jj + (size_t)c * n] : traits<T>::zero();
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < KC; ++kk) {
-          T sv[4], ov[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) sv[a] = Sg[ty * 4 + a][kk];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) ov[q] = Og[kk][tx * 4 + q];
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[a][q] = acc[a][q] + sc_mul(sv[a], ov[q]);
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int r = r0 + ty * 4 + a;
-        if (r >= m) continue;
-        const int row = s_cand[r];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = c0 + tx * 4 + q;
-          if (c < l) h.Zt[c + (size_t)r * l] = b.Y[row + (size_t)c * n] - acc[a][q];
-        }
-      }
+        for (int q = 0; q < 4; ++q) acc[a][q] = acc[a][q] + sc_mul(sv[a], ov[q]);
     }
   }
-  if (tid == 0) *h.k = m;  // provisional: number of candidates (read by cpqr)
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int r = r0 + ty * 4 + a;
+    if (r >= m) continue;
+    const int row = s_cand[r];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + tx * 4 + q;
+      if (c < l) h.Zt[c + (size_t)r * l] = b.Y[row + (size_t)c * n] - acc[a][q];
+    }
+  }
+  if (tid == 0 && r0 == 0 && c0 == 0) *h.k = m;  // provisional: number of candidates (read by cpqr)
 }
 
 // One workgroup per HSS node: truncated CPQR of Zt (l x m) -> k, skeleton, U.
@@ -209,35 +229,40 @@ __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restric
 // Columns are never moved: the pivot of step j is a physical column chosen
 // from exact trailing norms; every wave takes the same decision from the
 // same LDS data (bit-identical butterfly reductions), so one barrier per step
-// suffices. Groups of 16 lanes apply the Householder reflector to one column
-// each and produce that column's trailing norm for the next step.
-template <class T, bool LDS>
+// suffices. Groups of gl lanes apply the reflector to one column each and
+// produce that column's trailing norm for the next step. Reductions run in the
+// real type of the factor (FP32 for the FP32 path).
+// GL lanes per column group; each lane holds up to RPL rows of the reflector and
+// of the column it updates in registers (GL * RPL >= l).
+template <class T, bool LDS, int GL, int RPL>
 __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict__ bx,
                                                    const HssDesc<T>* __restrict__ hs,
                                                    const int* __restrict__ list, int p_os) {
-  constexpr int GL = 16;
+  using R = typename traits<T>::real;
   const HssDesc<T> h = hs[list[blockIdx.x]];
   const CompBox<T> b = bx[h.box];
   const int l = b.l;
   const int m = *h.k;
+  constexpr int NG = 256 / GL;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* A = LDS ? (T*)smem_raw : h.Zt;  // l x m, ld = l
-  __shared__ double s_nrm[2][512];  // double buffered: read step j, write step j + 1
+  __shared__ R s_nrm[2][512];  // double buffered: read at step j, written for step j + 1
   __shared__ int s_sel[256];
+  __shared__ int s_pos[512];   // column -> skeleton position, or -1
   __shared__ T s_rdiag[256];
   __shared__ int s_k;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int gid = wave * (64 / GL) + (lane / GL), gl = lane % GL;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int gid = tid / GL, gl = tid % GL;
   if (LDS)
     for (int e = tid; e < l * m; e += 256) A[e] = h.Zt[e];
+  for (int c = tid; c < m; c += 256) s_pos[c] = -1;
   __syncthreads();
-  // initial norms
-  for (int c0 = 0; c0 < m; c0 += 16) {
+  for (int c0 = 0; c0 < m; c0 += NG) {
     const int c = c0 + gid;
-    double s2 = 0;
+    R s2 = 0;
     if (c < m)
-      for (int r = gl; r < l; r += GL) s2 += (double)traits<T>::abs2(A[r + (size_t)c * l]);
-    for (int off = GL / 2; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+      for (int r = gl; r < l; r += GL) s2 += traits<T>::abs2(A[r + (size_t)c * l]);
+    s2 = group_sum<GL>(s2);
     if (c < m && gl == 0) s_nrm[0][c] = s2;
   }
   __syncthreads();
@@ -246,38 +271,32 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
   unsigned chosen = 0;  // bit t: column lane + 64 t was a pivot (identical in every wave)
   int k = kcap;
   for (int j = 0; j < kcap; ++j) {
-    // pivot: largest trailing norm among free columns (ties: lowest index); total = ||R22||_F^2
-    double best = -1.0, tot = 0.0;
+    R best = -1, tot = 0;
     int bi = 0x7fffffff;
     for (int t = 0; lane + 64 * t < m; ++t) {
       if ((chosen >> t) & 1u) continue;
       const int c = lane + 64 * t;
-      const double v = s_nrm[j & 1][c];
+      const R v = s_nrm[j & 1][c];
       tot += v;
       if (v > best) {
         best = v;
         bi = c;
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      tot += __shfl_xor(tot, off);
-      const double v2 = __shfl_xor(best, off);
-      const int i2 = __shfl_xor(bi, off);
-      if (v2 > best || (v2 == best && i2 < bi)) {
-        best = v2;
-        bi = i2;
-      }
-    }
-    if (sqrt(tot) <= thresh || bi >= m) {
+    tot = wave_sum(tot);
+    wave_argmax(best, bi);
+    if (sqrt((double)tot) <= thresh || bi >= m) {
       k = j;
       break;
     }
     const int p = bi;
     if ((p & 63) == lane) chosen |= 1u << (p >> 6);
-    if (tid == 0) s_sel[j] = p;
-    // reflector H = I - 2 v v^H / (v^H v) with v = x - alpha e1, x = A(j:l, p)
+    if (tid == 0) {
+      s_sel[j] = p;
+      s_pos[p] = j;
+    }
     const T x0 = A[j + (size_t)p * l];
-    const double xn2 = s_nrm[j & 1][p];
+    const double xn2 = (double)s_nrm[j & 1][p];
     const double xn = sqrt(xn2);
     const double a0 = sqrt((double)traits<T>::abs2(x0));
     T alpha;
@@ -285,36 +304,47 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
     else alpha = traits<T>::mk(-xn, 0.0);
     if (tid == 0) s_rdiag[j] = alpha;
     const double vv = 2.0 * xn2 + 2.0 * a0 * xn;
+    const R f = vv > 0 ? (R)(2.0 / vv) : (R)0;
     const T vj = x0 - alpha;
-    const int ncol_iter = (m + 15) / 16;
+    // this lane's rows r = j + gl + GL t of the reflector, in registers
+    T vr[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int r = j + gl + GL * t;
+      vr[t] = r < l ? (r == j ? vj : A[r + (size_t)p * l]) : traits<T>::zero();
+    }
+    const int ncol_iter = (m + NG - 1) / NG;
     for (int it = 0; it < ncol_iter; ++it) {
-      const int c = it * 16 + gid;
+      const int c = it * NG + gid;
       const int cc = c < m ? c : 0;
       const unsigned mw = __shfl(chosen, cc & 63);
       const bool active = c < m && c != p && !((mw >> (cc >> 6)) & 1u);
-      T dot = traits<T>::zero();
-      if (active && vv > 0)
-        for (int r = j + gl; r < l; r += GL) {
-          const T vr = (r == j) ? vj : A[r + (size_t)p * l];
-          dot = dot + sc_mul(traits<T>::conj(vr), A[r + (size_t)c * l]);
-        }
-      for (int off = GL / 2; off > 0; off >>= 1) {
-        const double dr = __shfl_xor((double)traits<T>::re(dot), off);
-        const double di = __shfl_xor((double)traits<T>::im(dot), off);
-        dot = traits<T>::mk((double)traits<T>::re(dot) + dr, (double)traits<T>::im(dot) + di);
+      T ar[RPL];
+      R dre = 0, dim = 0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = j + gl + GL * t;
+        ar[t] = (active && r < l) ? A[r + (size_t)c * l] : traits<T>::zero();
+        const T pr = sc_mul(traits<T>::conj(vr[t]), ar[t]);
+        dre += traits<T>::re(pr);
+        dim += traits<T>::im(pr);
       }
-      double s2 = 0;
+      dre = group_sum<GL>(dre);
+      if (traits<T>::cplx) dim = group_sum<GL>(dim);
+      R s2 = 0;
       if (active) {
-        const double f = vv > 0 ? 2.0 / vv : 0.0;
-        const T fw = traits<T>::mk(traits<T>::re(dot) * f, traits<T>::im(dot) * f);
-        for (int r = j + gl; r < l; r += GL) {
-          const T vr = (r == j) ? vj : A[r + (size_t)p * l];
-          const T nv = sc_fms(A[r + (size_t)c * l], fw, vr);
-          A[r + (size_t)c * l] = nv;
-          if (r > j) s2 += (double)traits<T>::abs2(nv);
+        const T fw = traits<T>::mk(dre * f, dim * f);
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int r = j + gl + GL * t;
+          if (r < l) {
+            const T nv = sc_fms(ar[t], fw, vr[t]);
+            A[r + (size_t)c * l] = nv;
+            if (r > j) s2 += traits<T>::abs2(nv);
+          }
         }
       }
-      for (int off = GL / 2; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+      s2 = group_sum<GL>(s2);
       if (active && gl == 0) s_nrm[(j + 1) & 1][c] = s2;
     }
     __syncthreads();
@@ -322,29 +352,34 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
   if (tid == 0) s_k = k;
   __syncthreads();
   k = s_k;
-  // T = R11^{-1} R12 for every free column (in place in rows 0..k-1), one column per thread
+  // T = R11^{-1} R12, one group per free column: back substitution in axpy form
+  // (x_i final -> broadcast -> subtract R(0:i, i) x_i); rows are spread over the lanes.
   float tm = 0.f;
-  for (int c = tid; c < m; c += 256) {
-    bool sk = false;
-    for (int i = 0; i < k; ++i) sk |= (s_sel[i] == c);
-    if (sk) continue;
-    T* col = A + (size_t)c * l;
+  for (int c0 = 0; c0 < m; c0 += NG) {
+    const int c = c0 + gid;
+    const bool act = c < m && s_pos[c] < 0;
+    T* col = A + (size_t)(act ? c : 0) * l;
     for (int i = k - 1; i >= 0; --i) {
-      T x = col[i];
-      for (int jj = i + 1; jj < k; ++jj) x = sc_fms(x, A[i + (size_t)s_sel[jj] * l], col[jj]);
-      const T d = s_rdiag[i];
-      x = traits<T>::abs2(d) > 0 ? sc_mul(x, sc_inv(d)) : traits<T>::zero();
-      col[i] = x;
-      tm = fmaxf(tm, (float)sqrt((double)traits<T>::abs2(x)));
+      const int src = i % GL;
+      T xi = traits<T>::zero();
+      if (act && gl == src) {
+        const T d = s_rdiag[i];
+        xi = traits<T>::abs2(d) > 0 ? sc_mul(col[i], sc_inv(d)) : traits<T>::zero();
+        col[i] = xi;
+        tm = fmaxf(tm, (float)sqrt((double)traits<T>::abs2(xi)));
+      }
+      const R xr = __shfl(traits<T>::re(xi), src, GL);
+      const R xim = __shfl(traits<T>::im(xi), src, GL);
+      const T xv = traits<T>::mk(xr, xim);
+      if (act)
+        for (int r = gl; r < i; r += GL) col[r] = sc_fms(col[r], A[r + (size_t)s_sel[i] * l], xv);
     }
   }
   __syncthreads();
   // U (m x k, ld zcap): row sel[i] = e_i, free row c = T(:, c)^T
   for (int e = tid; e < m * k; e += 256) {
     const int c = e % m, i = e / m;
-    int pos = -1;
-    for (int q = 0; q < k; ++q)
-      if (s_sel[q] == c) pos = q;
+    const int pos = s_pos[c];
     T v;
     if (pos >= 0) v = (pos == i) ? traits<T>::one() : traits<T>::zero();
     else v = A[i + (size_t)c * l];
@@ -361,55 +396,68 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
   }
 }
 
-// tall bases of one HSS height: leaves copy U, parents diag(Ut_a, Ut_b) U
+// Tall bases of one HSS height, one workgroup per (HSS node, 64-row tile):
+// leaves copy U, parents compute diag(Ut_a, Ut_b) U. Thread = (row, column
+// group of 4): each loaded Ut entry is reused for the thread's columns.
 template <class T>
 __global__ __launch_bounds__(256) void utall_kernel(const CompBox<T>* __restrict__ bx,
                                                     const HssDesc<T>* __restrict__ hs,
-                                                    const int* __restrict__ list) {
-  const HssDesc<T> h = hs[list[blockIdx.x]];
+                                                    const HTile* __restrict__ tiles) {
+  const HTile tl = tiles[blockIdx.x];
+  const HssDesc<T> h = hs[tl.hnode];
   const int k = *h.k;
   const int nt = h.hi - h.lo;
+  const int rl = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  const int r = tl.r0 + rl;
   if (h.left < 0) {
-    for (int e = threadIdx.x; e < nt * k; e += 256) {
-      const int r = e % nt, c = e / nt;
-      h.Ut[r + (size_t)c * nt] = h.U[r + (size_t)c * h.zcap];
-    }
+    if (r < nt)
+      for (int c = cg; c < k; c += 4) h.Ut[r + (size_t)c * nt] = h.U[r + (size_t)c * h.zcap];
     return;
   }
   const HssDesc<T> a = hs[h.left], bb = hs[h.right];
   const int ka = *a.k, kb = *bb.k;
   const int na = a.hi - a.lo, nbb = bb.hi - bb.lo;
-  for (int e = threadIdx.x; e < nt * k; e += 256) {
-    const int r = e % nt, c = e / nt;
-    T acc = traits<T>::zero();
-    if (r < na) {
-      for (int q = 0; q < ka; ++q) acc = acc + sc_mul(a.Ut[r + (size_t)q * na], h.U[q + (size_t)c * h.zcap]);
-    } else {
-      const int rr = r - na;
-      for (int q = 0; q < kb; ++q)
-        acc = acc + sc_mul(bb.Ut[rr + (size_t)q * nbb], h.U[ka + q + (size_t)c * h.zcap]);
+  if (r >= nt) return;
+  const bool left = r < na;
+  const T* src = left ? a.Ut + r : bb.Ut + (r - na);
+  const int ns = left ? na : nbb;
+  const int kk = left ? ka : kb;
+  const int qoff = left ? 0 : ka;
+  for (int c0 = cg; c0 < k; c0 += 64) {
+    T acc[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc[t] = traits<T>::zero();
+    for (int q = 0; q < kk; ++q) {
+      const T u = src[(size_t)q * ns];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int c = c0 + 4 * t;
+        if (c < k) acc[t] = acc[t] + sc_mul(u, h.U[qoff + q + (size_t)c * h.zcap]);
+      }
     }
-    h.Ut[r + (size_t)c * nt] = acc;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int c = c0 + 4 * t;
+      if (c < k) h.Ut[r + (size_t)c * nt] = acc[t];
+    }
   }
 }
 
-// S~ off-diagonal blocks. One workgroup per (internal HSS node, tw-column tile of its
-// right child): out(:, tile) = Ut_a * (S(J_a, J_b) * Ut_b(tile, :)^T), mirrored.
-struct ExpandTile {
-  int hnode;   // internal HSS node
-  int c0;      // first column (within the right child) of the tile
-};
+// S~ off-diagonal blocks, one workgroup per (internal HSS node, tw-column tile of
+// its right child, 64-row tile of its left child):
+// out = Ut_a(rows, :) * (S(J_a, J_b) * Ut_b(cols, :)^T), written with its mirror.
 template <class T>
 __global__ __launch_bounds__(256) void expand_kernel(const CompBox<T>* __restrict__ bx,
                                                      const HssDesc<T>* __restrict__ hs,
-                                                     const ExpandTile* __restrict__ tiles, int tw) {
-  const ExpandTile tl = tiles[blockIdx.x];
+                                                     const HTile* __restrict__ tiles, int tw) {
+  const HTile tl = tiles[blockIdx.x];
   const HssDesc<T> h = hs[tl.hnode];
   const CompBox<T> b = bx[h.box];
   const HssDesc<T> a = hs[h.left], c = hs[h.right];
   const int ka = *a.k, kc = *c.k;
   const int na = a.hi - a.lo, nc = c.hi - c.lo;
   const int cw = min(tw, nc - tl.c0);
+  const int rw = min(64, na - tl.r0);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tmp = (T*)smem_raw;  // ka x tw
   const int n = b.n;
@@ -422,8 +470,9 @@ __global__ __launch_bounds__(256) void expand_kernel(const CompBox<T>* __restric
     tmp[i + j * ka] = acc;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < na * cw; e += 256) {
-    const int r = e % na, j = e / na;
+  for (int e = threadIdx.x; e < rw * cw; e += 256) {
+    const int rr = e % rw, j = e / rw;
+    const int r = tl.r0 + rr;
     T acc = traits<T>::zero();
     for (int q = 0; q < ka; ++q) acc = acc + sc_mul(a.Ut[r + (size_t)q * na], tmp[q + j * ka]);
     const int gr = a.lo + r, gc = c.lo + tl.c0 + j;

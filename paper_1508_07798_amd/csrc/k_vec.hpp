@@ -18,10 +18,14 @@ template <class T> struct GemvDesc {
   const int64_t* out_idx;
 };
 
-// mode 0: y = M x ; mode 1: y -= M x. grid (row tiles of 64, entries); 256 threads.
+// mode 0: y = M x ; mode 1: y -= M x. grid (row tiles of 64, entries); 512 threads
+// = 64 rows x 8 column groups; matrix loads are issued four at a time.
+constexpr int GEMV_THREADS = 512;
 template <class T, class V, int NR>
-__global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc<T>* __restrict__ ds, const V* __restrict__ x,
-                                                   V* __restrict__ y, int64_t ld, int nrhs, int mode) {
+__global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* __restrict__ ds,
+                                                            const V* __restrict__ x, V* __restrict__ y,
+                                                            int64_t ld, int nrhs, int mode) {
+  constexpr int NP = GEMV_THREADS / 64;
   const GemvDesc<T> d = ds[blockIdx.y];
   const int r0 = blockIdx.x * 64;
   if (r0 >= d.rows) return;
@@ -29,7 +33,7 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc<T>* __restrict
   const int rl = tid & 63, part = tid >> 6;
   const int row = r0 + rl;
   __shared__ V xs[NR][256];
-  __shared__ V red[NR][4][64];
+  __shared__ V red[NR][NP][64];
   for (int rb = 0; rb < nrhs; rb += NR) {
     const int nr = min(NR, nrhs - rb);
     V acc[NR];
@@ -38,18 +42,32 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc<T>* __restrict
     for (int c0 = 0; c0 < d.cols; c0 += 256) {
       const int cw = min(256, d.cols - c0);
       __syncthreads();
-      for (int e = tid; e < cw * nr; e += 256) {
+      for (int e = tid; e < cw * nr; e += GEMV_THREADS) {
         const int c = e % cw, k = e / cw;
         const int64_t src = d.in_off >= 0 ? d.in_off + c0 + c : d.in_idx[c0 + c];
         xs[k][c] = x[src + (rb + k) * ld];
       }
       __syncthreads();
       if (row < d.rows) {
-        for (int c = part; c < cw; c += 4) {
-          const V m = to_wide(d.mat[row + (size_t)(c0 + c) * d.rows]);
+        const T* mp = d.mat + row + (size_t)c0 * d.rows;
+        int c = part;
+        for (; c + 3 * NP < cw; c += 4 * NP) {
+          T m4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) m4[u] = mp[(size_t)(c + u * NP) * d.rows];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const V mv = to_wide(m4[u]);
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+              if (k < nr) acc[k] = acc[k] + sc_mul(mv, xs[k][c + u * NP]);
+          }
+        }
+        for (; c < cw; c += NP) {
+          const V mv = to_wide(mp[(size_t)c * d.rows]);
 #pragma unroll
           for (int k = 0; k < NR; ++k)
-            if (k < nr) acc[k] = acc[k] + sc_mul(m, xs[k][c]);
+            if (k < nr) acc[k] = acc[k] + sc_mul(mv, xs[k][c]);
         }
       }
     }
@@ -59,7 +77,8 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc<T>* __restrict
     if (part == 0 && row < d.rows) {
       const int64_t dst = d.out_off >= 0 ? d.out_off + row : d.out_idx[row];
       for (int k = 0; k < nr; ++k) {
-        V s = red[k][0][rl] + red[k][1][rl] + red[k][2][rl] + red[k][3][rl];
+        V s = red[k][0][rl];
+        for (int q = 1; q < NP; ++q) s = s + red[k][q][rl];
         V* yp = y + dst + (rb + k) * ld;
         *yp = mode == 0 ? s : (*yp - s);
       }
