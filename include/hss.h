@@ -156,7 +156,7 @@ hss_status_t gmres_solve(hss_handle_t h, int32_t nrhs, const void* b, void* x, i
  * "flops_factor", "bytes_apply", "bytes_spmv", "time_factor_ms",
  * "prof.<class>.ms|launches|flops|bytes" (HIP-event time, launch count and
  * algorithmic work of the timed launches) for the classes, in bit order:
- * gather, gj_panel, gj_rows, gj_update, gj_unswap, schur_gemm, symm, omega,
+ * gather, gj_panel, gj_rows, gj_update, gj_perm, schur_gemm, symm, omega,
  * sample_gemm, sample, id, utall, expand, judge, root, apply, spmv, gmres. */
 hss_status_t hss_query(hss_handle_t h, const char* key, double* out, int64_t cap, int64_t* len);
 

@@ -105,6 +105,11 @@ HD float sc_fms(float a, float b, float c) { return a - b * c; }
 HD double sc_fms(double a, double b, double c) { return a - b * c; }
 HD cf sc_fms(cf a, cf b, cf c) { return a - b * c; }
 HD cd sc_fms(cd a, cd b, cd c) { return a - b * c; }
+// component-wise select (a ternary on a 16-byte struct can be lowered to a select of
+// addresses through private memory)
+template <class T> HD T sel(bool c, T a, T b) {
+  return traits<T>::mk(c ? traits<T>::re(a) : traits<T>::re(b), c ? traits<T>::im(a) : traits<T>::im(b));
+}
 // conversions between precisions
 HD double to_wide(float a) { return (double)a; }
 HD double to_wide(double a) { return a; }
@@ -183,10 +188,10 @@ template <class R> __device__ __forceinline__ R wave_sum(R v) {
 // (value, index) maximum with ties to the lowest index over the whole wave; uniform
 template <class R> __device__ __forceinline__ void wave_argmax(R& v, int& i) {
   auto step = [&](R v2, int i2) {
-    if (v2 > v || (v2 == v && i2 < i)) {
-      v = v2;
-      i = i2;
-    }
+    // branch-free: the compare result selects, no exec-mask regions
+    const bool take = (v2 > v) | ((v2 == v) & (i2 < i));
+    v = take ? v2 : v;
+    i = take ? i2 : i;
   };
   step(dpp_v<0xB1>(v), dpp_i<0xB1>(i));
   step(dpp_v<0x4E>(v), dpp_i<0x4E>(i));

@@ -154,10 +154,10 @@ struct Arena {
 
 // ------------------------------------------------------------------ profiling
 enum Cls {
-  C_GATHER, C_GJ_PANEL, C_GJ_ROWS, C_GJ_UPDATE, C_GJ_UNSWAP, C_SCHUR, C_SYMM, C_OMEGA, C_SAMPLE_GEMM,
+  C_GATHER, C_GJ_PANEL, C_GJ_ROWS, C_GJ_UPDATE, C_GJ_PERM, C_SCHUR, C_SYMM, C_OMEGA, C_SAMPLE_GEMM,
   C_SAMPLE, C_ID, C_UTALL, C_EXPAND, C_JUDGE, C_ROOT, C_APPLY, C_SPMV, C_GMRES, C_NCLS
 };
-static const char* kClsName[C_NCLS] = {"gather", "gj_panel", "gj_rows", "gj_update", "gj_unswap",
+static const char* kClsName[C_NCLS] = {"gather", "gj_panel", "gj_rows", "gj_update", "gj_perm",
                                        "schur_gemm", "symm", "omega", "sample_gemm", "sample", "id",
                                        "utall", "expand", "judge", "root", "apply", "spmv", "gmres"};
 
@@ -238,6 +238,9 @@ template <class T> struct Engine : EngineBase {
   hss_opts_t o;
   hipStream_t st;
   int lds_max = 65536;
+  // LDS kept for the static arrays of the LDS panel kernel (pivot rows of a
+  // 32-column complex double panel and the reduction buffers)
+  static constexpr int kPanelStaticLds = 24576;
   double tol = 0;
   Prof prof;
   std::deque<std::vector<char>> keep;  // host staging kept alive until the next sync
@@ -251,9 +254,9 @@ template <class T> struct Engine : EngineBase {
   int q = 0;
 
   struct NodeDev {
-    T* G = nullptr;      // [A_ii^{-1} | X], n_i x (n_i + n_b)
+    T* G = nullptr;      // [(P A_ii)^{-1} | X], n_i x (n_i + n_b)
     T* Abi = nullptr;    // n_b x n_i
-    int* piv = nullptr;
+    int* rowperm = nullptr;  // P: row rowperm[i] of A_ii is row i of P A_ii
     int64_t* gidx = nullptr;
     int32_t* src = nullptr;
     int64_t* bpos = nullptr;  // global tree positions of B
@@ -261,8 +264,8 @@ template <class T> struct Engine : EngineBase {
   };
   std::vector<NodeDev> nd;
   struct RootDev {
-    W* R = nullptr;
-    int* piv = nullptr;
+    W* R = nullptr;      // (P A_root)^{-1}
+    int* rowperm = nullptr;
     int64_t* gidx = nullptr;
     int32_t* src = nullptr;
     int n = 0;
@@ -315,7 +318,7 @@ template <class T> struct Engine : EngineBase {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
       for (const void* f : {(const void*)gj_panel_kernel<T, true, 16>, (const void*)gj_panel_kernel<T, true, 32>,
                             (const void*)gj_panel_kernel<W, true, 16>, (const void*)gj_panel_kernel<W, true, 32>})
-        HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 4096));
+        HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - kPanelStaticLds));
     }
   }
   ~Engine() override {
@@ -384,7 +387,10 @@ template <class T> struct Engine : EngineBase {
     if (L.n == 0) return;
     fl();
     int id = prof.start(cls, L.flops, 0);
-    gemm_nn_kernel<X><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+    if (cls == C_SCHUR) gemm_nn_kernel<X, GEMM_SCHUR><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+    else if (cls == C_GJ_UPDATE) gemm_nn_kernel<X, GEMM_GJ_UPDATE><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+    else if (cls == C_SAMPLE_GEMM) gemm_nn_kernel<X, GEMM_SAMPLE><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+    else gemm_nn_kernel<X, GEMM_GENERIC><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
     prof.stop(id);
     check_launch("gemm");
     if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_SAMPLE_GEMM) flops_factor += L.flops;
@@ -431,11 +437,11 @@ template <class T> struct Engine : EngineBase {
     while (nb > 8 && rpt * nb * words > 192) nb /= 2;
     bool reg = rpt <= 8 && rpt * nb * words <= 192 && !(sX == 16 && rpt > 6);
     bool lds = false;
-    const int64_t avail = lds_max - 4096;
+    const int64_t avail = lds_max - kPanelStaticLds;
     if (!reg) {
       nb = 32;
       lds = true;
-      while (nb >= 16 && ((int64_t)nmax * nb + nb * nb) * sX + 8 * (int64_t)nmax > avail) nb /= 2;
+      while (nb >= 16 && (int64_t)nmax * nb * sX > avail) nb /= 2;
       if (nb < 16) {
         nb = 32;
         lds = false;
@@ -447,10 +453,11 @@ template <class T> struct Engine : EngineBase {
       g.csave = ar.get<X>((size_t)g.n * nb);
       g.rbuf = ar.get<X>((size_t)nb * g.W);
       g.gpanel = lds ? nullptr : ar.get<X>((size_t)g.n * nb);
+      g.mv = ar.get<int>(1 + 4 * (size_t)nb);
     }
     GjDesc<X>* dd = up(ds, ar);
     const int nn = (int)ds.size();
-    const size_t shm = reg ? 8 * (size_t)nmax : lds ? ((size_t)nmax * nb + nb * nb) * sX + 8 * (size_t)nmax : 0;
+    const size_t shm = lds ? (size_t)nmax * nb * sX : 0;
     // every panel's trailing-update descriptors, uploaded together
     std::vector<GemmLaunch> upd;
     for (int j0 = 0; j0 < nmax; j0 += nb) {
@@ -458,7 +465,7 @@ template <class T> struct Engine : EngineBase {
       for (auto& g : ds) {
         if (j0 >= g.n) continue;
         int w = std::min(nb, g.n - j0);
-        gd.push_back({g.csave, g.rbuf, g.M, g.n, g.W, w, g.n, w, g.n});
+        gd.push_back({g.csave, g.rbuf, g.M, g.n, g.W, w, g.n, w, g.n, j0, j0 + w});
       }
       upd.push_back(prep_gemm<X>(gd, ar));
     }
@@ -473,16 +480,11 @@ template <class T> struct Engine : EngineBase {
       prof.stop(id);
       check_launch("gj_panel");
       id = prof.start(C_GJ_ROWS, 0, 0);
-      gj_rows_kernel<X><<<dim3(cdiv(wmax, 64), nn), 256, 0, st>>>(dd, j0, nb);
+      gj_rows_kernel<X><<<dim3(cdiv(wmax, 64) + cdiv(nmax, 256), nn), 256, 0, st>>>(dd, j0, nb, cdiv(wmax, 64));
       prof.stop(id);
       check_launch("gj_rows");
       run_gemm<X>(upd[pi], m1, p1, C_GJ_UPDATE);
     }
-    int id = prof.start(C_GJ_UNSWAP, 0, 0);
-    fl();
-    gj_unswap_kernel<X><<<dim3(cdiv(nmax, 256), nn), 256, 0, st>>>(dd);
-    prof.stop(id);
-    check_launch("gj_unswap");
   }
 
   // ---------------------------------------------------------------- factor
@@ -571,7 +573,7 @@ template <class T> struct Engine : EngineBase {
         nd[g].bpos = db + boff[g];
         nd[g].G = fbase + foff[g];
         nd[g].Abi = fbase + aoff[g];
-        nd[g].piv = pbase + poff[g];
+        nd[g].rowperm = pbase + poff[g];
       }
     }
     rank_v.assign(nn, 0);
@@ -650,7 +652,7 @@ template <class T> struct Engine : EngineBase {
           g.M = nd[wv[i]].G;
           g.n = (int)n.idof.size();
           g.W = (int)(n.idof.size() + n.bdof.size());
-          g.piv = nd[wv[i]].piv;
+          g.rowperm = nd[wv[i]].rowperm;
           g.flag = d_sing + wv[i];
           gj.push_back(g);
         }
@@ -694,7 +696,7 @@ template <class T> struct Engine : EngineBase {
         for (size_t k = 0; k < b.bdof.size(); ++k) sall.push_back((int32_t)((1 << 30) + k));
         rt[p].n = (int)r.dofs.size();
         rt[p].R = persist.get<W>((size_t)rt[p].n * rt[p].n);
-        rt[p].piv = persist.get<int>(rt[p].n);
+        rt[p].rowperm = persist.get<int>(rt[p].n);
         max_nr = std::max(max_nr, rt[p].n);
         maxe = std::max<int64_t>(maxe, (int64_t)rt[p].n * rt[p].n);
       }
@@ -731,7 +733,7 @@ template <class T> struct Engine : EngineBase {
         GjDesc<W> g{};
         g.M = rt[p].R;
         g.n = g.W = rt[p].n;
-        g.piv = rt[p].piv;
+        g.rowperm = rt[p].rowperm;
         g.flag = d_sing + nn + p;
         gj.push_back(g);
       }
@@ -1084,7 +1086,7 @@ template <class T> struct Engine : EngineBase {
         const int ni = (int)n.idof.size(), nbd = (int)n.bdof.size();
         if (ni == 0) continue;
         const int64_t ip = pr.dof_off + n.ipos;
-        f1.push_back({nd[g].G, ni, ni, ip, nullptr, ip, nullptr});
+        f1.push_back({nd[g].G, ni, ni, ip, nullptr, ip, nullptr, nd[g].rowperm});
         f2.push_back({nd[g].Abi, nbd, ni, ip, nullptr, -1, nd[g].bpos});
         b1.push_back({nd[g].G + (size_t)ni * ni, ni, nbd, -1, nd[g].bpos, ip, nullptr});
         a.max_ni = std::max(a.max_ni, ni);
@@ -1098,7 +1100,7 @@ template <class T> struct Engine : EngineBase {
     std::vector<GemvDesc<W>> rd;
     for (size_t p = 0; p < P.roots.size(); ++p) {
       const int64_t ip = P.probs[p].dof_off + P.roots[p].ipos;
-      rd.push_back({rt[p].R, rt[p].n, rt[p].n, ip, nullptr, ip, nullptr});
+      rd.push_back({rt[p].R, rt[p].n, rt[p].n, ip, nullptr, ip, nullptr, rt[p].rowperm});
     }
     d_rootdesc = up(rd, persist);
   }
@@ -1462,7 +1464,7 @@ void debug_gemm_t(int nb, const void* const* A, const void* const* B, void* cons
   int* dp = ar.get<int>(pre.size());
   HIP_CHECK(hipMemcpyAsync(dd, v.data(), v.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, st));
   HIP_CHECK(hipMemcpyAsync(dp, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice, st));
-  gemm_nn_kernel<X><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), traits<X>::mk(al[0], al[1]),
+  gemm_nn_kernel<X, GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), traits<X>::mk(al[0], al[1]),
                                                 traits<X>::mk(be[0], be[1]));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(HSS_EDEVICE, hipGetErrorString(e));
@@ -1505,11 +1507,27 @@ void debug_gj_t(int nb, void* const* Mat, const int32_t* n, const int32_t* m, in
     g.M = (X*)Mat[b];
     g.n = n[b];
     g.W = n[b] + m[b];
-    g.piv = ar.get<int>(n[b]);
+    g.rowperm = ar.get<int>(n[b]);
     g.flag = flags + b;
     ds.push_back(g);
   }
   eng.template gauss_jordan<X>(ds, ar);
+  // explicit inverse: undo the pivoted column order through a copy
+  if (!ds.empty()) {
+    std::vector<X*> outs;
+    int nmax = 0;
+    for (auto& g : ds) {
+      outs.push_back(ar.get<X>((size_t)g.n * g.n));
+      nmax = std::max(nmax, g.n);
+    }
+    GjDesc<X>* dd = eng.up(ds, ar);
+    X** dout = eng.up(outs, ar);
+    eng.fl();
+    gj_colperm_kernel<X><<<dim3(cdiv(nmax, 64), (unsigned)ds.size()), 256, 0, st>>>(dd, dout);
+    HIP_CHECK(hipGetLastError());
+    for (size_t b = 0; b < ds.size(); ++b)
+      HIP_CHECK(hipMemcpyAsync(ds[b].M, outs[b], sizeof(X) * ds[b].n * ds[b].n, hipMemcpyDeviceToDevice, st));
+  }
   std::vector<int> f(nb);
   HIP_CHECK(hipMemcpyAsync(f.data(), flags, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
   eng.sync();

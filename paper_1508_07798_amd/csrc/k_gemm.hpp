@@ -1,5 +1,6 @@
 // Batched variable-size GEMM on CDNA4 matrix cores:
-//   C_b = alpha * A_b * B_b + beta * C_b   (all column-major, no transposes)
+//   C_b = alpha * A_b * B_b + beta * C_b   (all column-major, no transposes;
+//   beta is taken as 0 on an optional column window of each entry)
 // for every entry b of a descriptor array, one launch for all entries.
 //
 // Tiles of 64 x 64 outputs per 256-thread workgroup (4 wavefronts, each a
@@ -21,6 +22,7 @@ struct GemmDesc {
   void* C;
   int M, N, K;
   int lda, ldb, ldc;
+  int z0, z1;  // columns [z0, z1) of C are written with beta = 0 (old values ignored)
 };
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -59,8 +61,12 @@ template <class T> struct gemm_cfg {
   static constexpr int BK = traits<T>::cplx ? 8 : 16;
 };
 
+// Role of a GEMM launch; it only separates the kernel symbols so that a profile
+// tells the Schur update, the Gauss-Jordan trailing update and the sampling apart.
+enum GemmRole { GEMM_GENERIC = 0, GEMM_SCHUR = 1, GEMM_GJ_UPDATE = 2, GEMM_SAMPLE = 3 };
+
 // One 64 x 64 tile of C.
-template <class T>
+template <class T, int ROLE>
 __global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict__ descs,
                                                       const int* __restrict__ tprefix, int nent,
                                                       T alpha, T beta) {
@@ -188,7 +194,8 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict
         else val = acc[0][i][j][v];
         T* cp = Cg + row + (size_t)col * g.ldc;
         T out = sc_mul(alpha, val);
-        if (!(traits<T>::re(beta) == 0 && traits<T>::im(beta) == 0)) out = out + sc_mul(beta, *cp);
+        const bool keep = col < g.z0 || col >= g.z1;
+        if (keep && !(traits<T>::re(beta) == 0 && traits<T>::im(beta) == 0)) out = out + sc_mul(beta, *cp);
         *cp = out;
       }
     }

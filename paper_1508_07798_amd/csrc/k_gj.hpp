@@ -1,18 +1,22 @@
 // Batched blocked Gauss-Jordan elimination with partial pivoting.
 //
 // For every box of a wave, M = [A^_ii | A^_ib] (n x (n + m), column-major)
-// is reduced in place to [A^_ii^{-1} | X], X = A^_ii^{-1} A^_ib: the
-// elimination of I^ behind equation (32). Per panel of nb columns:
-//   1. gj_panel: LU with partial pivoting of the panel rows j0..n-1 (in LDS),
-//      giving the pivot rows and Pinv = (L11 U11)^{-1} of the pivot block;
-//   2. gj_rows: apply the row swaps to every column, scale the pivot rows
-//      R' = Pinv * M(j0:j1, :) (the panel columns become Pinv), save the
-//      swapped panel columns (pivot rows zeroed) and zero them in M;
-//   3. one GEMM over all rows: M -= Csave * R'.
+// is reduced in place to [(P A^_ii)^{-1} | X], X = A^_ii^{-1} A^_ib: the
+// elimination of I^ behind equation (32). P is the row permutation chosen by
+// partial pivoting, recorded as rowperm ((P A)(i, :) = A(rowperm[i], :)). The
+// inverse stays in that pivoted column order: A^{-1} y = (P A)^{-1} (P y), so a
+// product with A^{-1} gathers its input through rowperm. Per panel of nb columns:
+//   1. gj_panel: LU with partial pivoting of the panel rows j0..n-1, giving the
+//      pivot rows, their net movement (at most 2 nb rows move) and
+//      Pinv = (L11 U11)^{-1} of the pivot block;
+//   2. gj_rows: apply the row movement to every column, form the scaled
+//      pivot rows R' = Pinv * M(j0:j1, :) (Pinv in the panel columns) and the
+//      saved panel columns Csave of the interchanged M (pivot block -I);
+//   3. one GEMM over all rows: M = M - Csave * R', with M's old panel columns
+//      ignored (beta = 0 there), which leaves R' in the pivot rows.
 // The elimination of the panel columns from every row (not only the rows
 // below) is what turns the LU of the panel into a Gauss-Jordan step; all
-// flops except the panel's sit in the GEMM. At the end the columns of the
-// inverse are swapped back in reverse pivot order (gj_unswap).
+// flops except the panel's sit in the GEMM.
 #pragma once
 
 #include <type_traits>
@@ -24,12 +28,18 @@ namespace hss {
 template <class T> struct GjDesc {
   T* M;          // n x W, ld = n
   int n, W;
-  int* piv;      // [n] global pivot rows
   T* pinv;       // nb x nb scratch
   T* csave;      // n x nb scratch
   T* rbuf;       // nb x W scratch
   T* gpanel;     // (n x nb) scratch when the panel does not fit in LDS
   int* flag;     // set to 1 on an exactly zero pivot
+  int* mv;       // [1 + 4 nb] net row movement of the current panel: count, then (dst, src) pairs
+  int* rowperm;  // [n] net row permutation: original row now at each position
+};
+
+template <class R> struct RedPair {
+  R v;
+  int i;
 };
 
 template <class R> __device__ inline void argmax_pair(R& v, int& i, R v2, int i2) {
@@ -49,13 +59,119 @@ template <int I0, int N, class F> __device__ __forceinline__ void static_for(F&&
 
 constexpr int GJ_PANEL_THREADS = 512;
 
-// LU with partial pivoting of the panel rows j0..n-1, columns j0..j0+w-1.
-// Rows are not moved: the pivot of column c is tracked as a physical row and
-// every thread keeps updating the rows it owns, so one barrier per column
-// suffices (the argmax partials are double buffered). The physical pivot
-// sequence is turned into the usual sequence of row interchanges at the end.
-// Dynamic LDS: the panel (Rr x w), w x w for Pinv and 2 Rr ints for the
-// interchange bookkeeping; or global scratch when it does not fit.
+// Net row movement of a panel, computed by one wave once the pivots of all w (<= 32)
+// columns are known: position c takes its pivot row pphys[c]; the rows r0 < w that
+// are not pivots fill, in increasing order, the positions >= w whose rows became
+// pivots (every such pairing is a valid partial-pivoting order). Writes
+// mv = [count, (dst, src), ...] with positions relative to the panel start.
+__device__ __forceinline__ void panel_moves(int* mv, const int* pphys, int w) {
+  const int lane = threadIdx.x & 63;
+  const int pc = lane < w ? pphys[lane] : -1;
+  unsigned pivlow = 0;  // bit r0: row r0 < w is a pivot
+  for (int r0 = 0; r0 < w; ++r0)
+    if (__ballot(pc == r0)) pivlow |= 1u << r0;
+  const bool disp = lane < w && !((pivlow >> lane) & 1u);  // row `lane` leaves the pivot block
+  const bool vac = lane < w && pc >= w;                     // position pc loses its row
+  const bool mov = lane < w && pc != lane;
+  const unsigned long long below = (1ull << lane) - 1;
+  const unsigned long long bd = __ballot(disp), bv = __ballot(vac), bm = __ballot(mov);
+  const int kd = __popcll(bd & below), km = __popcll(bm & below), n1 = __popcll(bm);
+  int dst = -1;
+  unsigned long long rem = bv;
+  for (int k = 0; rem; ++k) {
+    const int lv = __ffsll((long long)rem) - 1;  // uniform: k-th vacated position's lane
+    rem &= rem - 1;
+    const int pos = __builtin_amdgcn_readlane(pc, lv);
+    if (disp && kd == k) dst = pos;
+  }
+  if (mov) {
+    mv[1 + 2 * km] = lane;
+    mv[2 + 2 * km] = pc;
+  }
+  if (disp) {
+    mv[1 + 2 * (n1 + kd)] = dst;
+    mv[2 + 2 * (n1 + kd)] = lane;
+  }
+  if (lane == 0) mv[0] = n1 + __popcll(bd);
+}
+
+// Pinv = (L11 U11)^{-1} from the packed L\U rows of the pivot block in LDS
+// (lu[c * LD + i]: row c, unit lower part left of the diagonal). Groups of 32
+// lanes; lane gl works on row gl and each group solves for one column of Pinv
+// (forward, then backward substitution), broadcasting every finished entry with
+// readlane. Row entries are read from LDS in batches of 8. A zero diagonal entry
+// leaves its row unscaled (the zero pivot is reported through the flag).
+template <class T, int NB, int LD>
+__device__ __forceinline__ void pivot_block_inverse(const T* lu, int w, T* __restrict__ pinv) {
+  using R = typename traits<T>::real;
+  const int tid = threadIdx.x, gg = tid >> 5, gl = tid & 31, half = tid & 32;
+  const T* row = lu + (gl < w ? gl : 0) * LD;
+  T dinv = traits<T>::one();
+  if (gl < w) {
+    const T d = row[gl];
+    if (traits<T>::abs2(d) != 0) dinv = sc_inv(d);
+  }
+  auto bcast = [&](const T& x, int i) {
+    const R a0 = rdlane(traits<T>::re(x), i), a1 = rdlane(traits<T>::re(x), 32 + i);
+    const R b0 = rdlane(traits<T>::im(x), i), b1 = rdlane(traits<T>::im(x), 32 + i);
+    return traits<T>::mk(half ? a1 : a0, half ? b1 : b0);
+  };
+  for (int j0c = 0; j0c < w; j0c += GJ_PANEL_THREADS / 32) {
+    const int j = j0c + gg;
+    T x = sel(gl == j, traits<T>::one(), traits<T>::zero());
+    static_for<0, NB / 8>([&](auto chi) {
+      constexpr int cb = decltype(chi)::value * 8;
+      if (cb < w) {
+        R rr[8], ri[8];
+        static_for<0, 8>([&](auto ui) {
+          constexpr int u = decltype(ui)::value;
+          const T v = row[cb + u];
+          rr[u] = traits<T>::re(v);
+          ri[u] = traits<T>::im(v);
+        });
+        static_for<0, 8>([&](auto ui) {
+          constexpr int u = decltype(ui)::value;
+          constexpr int i = cb + u;
+          if (i < w) {
+            const T xi = bcast(x, i);
+            const T nx = sc_fms(x, traits<T>::mk(rr[u], ri[u]), xi);
+            x = sel(gl > i && gl < w, nx, x);
+          }
+        });
+      }
+    });
+    static_for<0, NB / 8>([&](auto chk) {
+      constexpr int cb = NB - 8 - decltype(chk)::value * 8;
+      if (cb < w) {
+        R rr[8], ri[8];
+        static_for<0, 8>([&](auto ui) {
+          constexpr int u = decltype(ui)::value;
+          const T v = row[cb + u];
+          rr[u] = traits<T>::re(v);
+          ri[u] = traits<T>::im(v);
+        });
+        static_for<0, 8>([&](auto ui) {
+          constexpr int u = 7 - decltype(ui)::value;
+          constexpr int i = cb + u;
+          if (i < w) {
+            x = sel(gl == i, sc_mul(x, dinv), x);
+            const T xi = bcast(x, i);
+            const T nx = sc_fms(x, traits<T>::mk(rr[u], ri[u]), xi);
+            x = sel(gl < i, nx, x);
+          }
+        });
+      }
+    });
+    if (j < w && gl < w) pinv[gl + j * w] = x;
+  }
+}
+
+// LU with partial pivoting of the panel rows j0..n-1, columns j0..j0+w-1, for
+// panels too tall for the register-resident kernel below. Rows are not moved:
+// the pivot of column c is tracked as a physical row and every thread keeps
+// updating the rows it owns, so one barrier per column suffices (the argmax
+// partials are double buffered). The panel (Rr x w) sits in dynamic LDS, or in
+// global scratch when it does not fit.
 template <class T, bool LDS, int NB>
 __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc<T>* __restrict__ descs,
                                                                     int j0, int nb) {
@@ -67,10 +183,10 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc
   const int Rr = g.n - j0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* P = LDS ? (T*)smem_raw : g.gpanel;
-  T* Pi = LDS ? (T*)smem_raw + (size_t)Rr * w : g.pinv;  // w x w region (LDS layout anchor)
   __shared__ R red_v[2][NW];
   __shared__ int red_i[2][NW];
-  __shared__ int s_pphys[64];   // physical pivot row of each panel column
+  __shared__ int s_pphys[64];     // physical pivot row of each panel column
+  __shared__ T s_lu[NB][NB + 1];  // packed L\U row of the pivot of column c
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // panel load, four independent loads in flight per thread
   for (int idx0 = tid; idx0 < Rr * w; idx0 += 4 * NT) {
@@ -78,7 +194,7 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int idx = idx0 + u * NT;
-      v[u] = idx < Rr * w ? g.M[(j0 + idx % Rr) + (size_t)(j0 + idx / Rr) * g.n] : traits<T>::zero();
+      v[u] = sel(idx < Rr * w, g.M[(j0 + idx % Rr) + (size_t)(j0 + idx / Rr) * g.n], traits<T>::zero());
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -122,6 +238,8 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc
     }
     if (tid == 0) s_pphys[c] = p;
     if (p % NT == tid) mine |= 1ull << (p / NT);
+    // the pivot row is final from here on (multipliers left of c, U from c)
+    if (tid < w) s_lu[c][tid] = P[p + (size_t)tid * Rr];
     const T pv = P[p + (size_t)c * Rr];
     const bool zero = traits<T>::abs2(pv) == 0;
     if (zero && tid == 0) *g.flag = 1;
@@ -163,7 +281,7 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc
           for (int u = 0; u < 16; ++u) {
             const T rv = traits<T>::mk(rre[u], rim[u]);
             const T nv = sc_fms(rv, l, traits<T>::mk(pre[u], pim[u]));
-            P[r + (size_t)(ch + u) * Rr] = (ch + u > c) ? nv : rv;
+            P[r + (size_t)(ch + u) * Rr] = sel(ch + u > c, nv, rv);
           }
         }
       }
@@ -179,80 +297,14 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc
     }
   }
   __syncthreads();
-  // interchange sequence (LAPACK style: row j0+c <-> row piv[j0+c], in order) from the
-  // physical pivot rows; phys_at / pos_of live in the csave scratch (2 Rr ints <= n nb T)
-  {
-    int* phys_at = LDS ? (int*)(Pi + (size_t)w * w) : (int*)g.csave;
-    int* pos_of = phys_at + Rr;
-    for (int r = tid; r < Rr; r += NT) {
-      phys_at[r] = r;
-      pos_of[r] = r;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      for (int c = 0; c < w; ++c) {
-        const int pp = s_pphys[c];
-        const int q = pos_of[pp];
-        const int pc = phys_at[c];
-        phys_at[c] = pp;
-        phys_at[q] = pc;
-        pos_of[pp] = c;
-        pos_of[pc] = q;
-        g.piv[j0 + c] = j0 + q;
-      }
-    }
-  }
-  // Pinv = U11^{-1} L11^{-1}; row c of L11 / U11 is physical row s_pphys[c]. Groups of 32
-  // lanes: lane gl holds row gl of the packed L\U block in registers, a group computes
-  // one column of Pinv by forward then backward substitution, broadcasting each
-  // finished entry with readlane (the step index is uniform across the wave).
-  __syncthreads();
-  {
-    const int gg = tid >> 5, gl = tid & 31, half = tid & 32;
-    // complex double rows do not fit in registers next to the rest: read them per step
-    constexpr bool REG = sizeof(T) <= 8;
-    constexpr int NR = REG ? NB : 1;
-    T row[NR];
-    const int pr = gl < w ? s_pphys[gl] : 0;
-    auto rowv = [&](int i) -> T {
-      if (REG) return row[REG ? i : 0];
-      return (gl < w && i < w) ? P[pr + (size_t)i * Rr] : traits<T>::zero();
-    };
-    if (REG) {
-#pragma unroll
-      for (int i = 0; i < NR; ++i) row[i] = (gl < w && i < w) ? P[pr + (size_t)i * Rr] : traits<T>::zero();
-    }
-    for (int j0c = 0; j0c < w; j0c += NT / 32) {
-      const int j = j0c + gg;
-      T x = (gl == j) ? traits<T>::one() : traits<T>::zero();
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const R a0 = rdlane(traits<T>::re(x), i), a1 = rdlane(traits<T>::re(x), 32 + i);
-        const R b0 = rdlane(traits<T>::im(x), i), b1 = rdlane(traits<T>::im(x), 32 + i);
-        const T xi = traits<T>::mk(half ? a1 : a0, half ? b1 : b0);
-        if (i < w && gl > i) x = sc_fms(x, rowv(i), xi);
-      }
-#pragma unroll
-      for (int ii = NB - 1; ii >= 0; --ii) {
-        if (ii < w && gl == ii) {
-          const T d = rowv(ii);
-          x = traits<T>::abs2(d) == 0 ? x : sc_mul(x, sc_inv(d));
-        }
-        const R a0 = rdlane(traits<T>::re(x), ii), a1 = rdlane(traits<T>::re(x), 32 + ii);
-        const R b0 = rdlane(traits<T>::im(x), ii), b1 = rdlane(traits<T>::im(x), 32 + ii);
-        const T xi = traits<T>::mk(half ? a1 : a0, half ? b1 : b0);
-        if (ii < w && gl < ii) x = sc_fms(x, rowv(ii), xi);
-      }
-      if (j < w && gl < w) g.pinv[gl + j * w] = x;
-    }
-  }
+  if (wave == 0) panel_moves(g.mv, s_pphys, w);
+  pivot_block_inverse<T, NB, NB + 1>(&s_lu[0][0], w, g.pinv);
 }
 
-// Register-resident variant of the panel LU: thread tid owns rows tid + t * NT
-// (t < RPT) of the panel and keeps their NB columns in registers; only the
-// pivot row travels, through LDS (two barriers per column). The pivot rows are
-// kept in LDS (packed L\U rows) for the pivot-block inverse. Pivots, the
-// interchange sequence and Pinv are produced exactly as by gj_panel_kernel.
+// Register-resident panel LU: thread tid owns rows tid + t * NT (t < RPT) of the
+// panel and keeps their NB columns in registers; only candidate pivot rows travel,
+// through LDS. The pivot rows are kept in LDS (packed L\U rows) for the pivot-block
+// inverse. Pivots, row movement and Pinv are the same as from gj_panel_kernel.
 template <class T, int NB, int RPT>
 __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_reg_kernel(const GjDesc<T>* __restrict__ descs,
                                                                         int j0, int nb) {
@@ -262,13 +314,10 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_reg_kernel(const Gj
   if (j0 >= g.n) return;
   const int w = min(nb, g.n - j0);
   const int Rr = g.n - j0;
-  __shared__ R red_v[2][NW];
-  __shared__ int red_i[2][NW];
+  __shared__ RedPair<R> s_red[2][NW];
   __shared__ int s_pphys[NB];
   __shared__ T s_lu[NB][NB + 1];  // packed L\U row of the pivot of column c, in order
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  int* phys_at = (int*)smem_raw;  // 2 Rr ints
-  int* pos_of = phys_at + Rr;
+  __shared__ T s_cand[2][NW][RPT][NB];  // candidate pivot row of every wave, double buffered
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   using V = T;
   R re[RPT][NB], im[RPT][NB];
@@ -283,205 +332,275 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_reg_kernel(const Gj
     });
   });
   unsigned done = 0;  // bit t: own row t is a pivot row
-  // the column loop is expanded at compile time so that every register index is a constant
-  static_for<0, NB>([&](auto cidx) {
-    constexpr int c = decltype(cidx)::value;
-    if (c < w) {
-      R best = -1;
-      int bi = 0x7fffffff;
-      static_for<0, RPT>([&](auto tidx) {
-        constexpr int t = decltype(tidx)::value;
-        const int r = tid + t * NT;
-        const R v = re[t][c] * re[t][c] + im[t][c] * im[t][c];
-        if (r < Rr && !((done >> t) & 1u) && (v > best || (v == best && r < bi))) {
-          best = v;
-          bi = r;
-        }
-      });
-      wave_argmax(best, bi);
-      if (lane == 0) {
-        red_v[c & 1][wave] = best;
-        red_i[c & 1][wave] = bi;
-      }
-      __syncthreads();
-      R bv = red_v[c & 1][0];
-      int p = red_i[c & 1][0];
-      for (int k = 1; k < NW; ++k) argmax_pair(bv, p, red_v[c & 1][k], red_i[c & 1][k]);
-      if (p < 0 || p >= Rr) {
-        // a NaN column: take the first row that is not a pivot yet
-        p = Rr;
-        for (int r = 0; r < Rr && p == Rr; ++r) {
-          bool used = false;
-          for (int q = 0; q < c; ++q) used |= (s_pphys[q] == r);
-          if (!used) p = r;
-        }
-      }
-      // the owner publishes the pivot row
-      if (p % NT == tid) {
-        // values picked by selects (a branch per row slot would let the compiler merge
-        // the register reads into one indexed access, which forces the rows to scratch)
-        const int ts = p / NT;
-        done |= 1u << ts;
-        static_for<0, NB>([&](auto ci) {
-          constexpr int cc = decltype(ci)::value;
-          R vr = re[0][cc], vi = im[0][cc];
-          static_for<1, RPT>([&](auto tidx) {
-            constexpr int t = decltype(tidx)::value;
-            R xr = re[t][cc], xi = im[t][cc];
-            asm("" : "+v"(xr), "+v"(xi));  // opaque copies: keeps the selects on values
-            vr = ts == t ? xr : vr;
-            vi = ts == t ? xi : vi;
-          });
-          s_lu[c][cc] = traits<T>::mk(vr, vi);
-        });
-        s_pphys[c] = p;
-      }
-      __syncthreads();
-      const T pv = s_lu[c][c];
-      const bool zero = traits<T>::abs2(pv) == 0;
-      if (zero && tid == 0) *g.flag = 1;
-      const T inv = zero ? traits<T>::zero() : sc_inv(pv);
-      static_for<0, RPT>([&](auto tidx) {
-        constexpr int t = decltype(tidx)::value;
-        if (!((done >> t) & 1u)) {
-          const T l = sc_mul(traits<T>::mk(re[t][c], im[t][c]), inv);
-          re[t][c] = traits<T>::re(l);
-          im[t][c] = traits<T>::im(l);
-          static_for<c + 1, NB>([&](auto ci) {
-            constexpr int cc = decltype(ci)::value;
-            const T nv = sc_fms(traits<T>::mk(re[t][cc], im[t][cc]), l, s_lu[c][cc]);
-            re[t][cc] = traits<T>::re(nv);
-            im[t][cc] = traits<T>::im(nv);
-          });
-        }
-      });
-    }
+  // Values of the current column of the own rows; refreshed while column c is updated.
+  R cr[RPT], ci[RPT];
+  static_for<0, RPT>([&](auto tidx) {
+    constexpr int t = decltype(tidx)::value;
+    cr[t] = re[t][0];
+    ci[t] = im[t][0];
   });
-  __syncthreads();
-  // interchange sequence (rows j0 + c <-> piv[j0 + c], in order)
-  for (int r = tid; r < Rr; r += NT) {
-    phys_at[r] = r;
-    pos_of[r] = r;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int c = 0; c < w; ++c) {
-      const int pp = s_pphys[c];
-      const int q = pos_of[pp];
-      const int pc = phys_at[c];
-      phys_at[c] = pp;
-      phys_at[q] = pc;
-      pos_of[pp] = c;
-      pos_of[pc] = q;
-      g.piv[j0 + c] = j0 + q;
+  // The column loop runs at run time (compact code); register indices stay
+  // compile-time constants and the columns at or left of c are skipped with branches
+  // on the uniform c. One barrier per column: before it, every wave publishes its best
+  // candidate row (double-buffered), after it every thread reduces the wave partials
+  // and reads the winning row.
+  for (int c = 0; c < w; ++c) {
+    const int buf = c & 1;
+    R best = -1;
+    int bi = 0x7fffffff;
+    static_for<0, RPT>([&](auto tidx) {
+      constexpr int t = decltype(tidx)::value;
+      const int r = tid + t * NT;
+      const R v = cr[t] * cr[t] + ci[t] * ci[t];
+      const bool take = (r < Rr) & !((done >> t) & 1u) & ((v > best) | ((v == best) & (r < bi)));
+      best = take ? v : best;
+      bi = take ? r : bi;
+    });
+    const int mine = bi;
+    wave_argmax(best, bi);
+    if (lane == 0) {
+      s_red[buf][wave].v = best;
+      s_red[buf][wave].i = bi;
     }
-  }
-  // Pinv = U11^{-1} L11^{-1} from the packed rows, 32-lane groups, readlane broadcasts
-  {
-    const int gg = tid >> 5, gl = tid & 31, half = tid & 32;
-    for (int j0c = 0; j0c < w; j0c += NT / 32) {
-      const int j = j0c + gg;
-      T x = (gl == j) ? traits<T>::one() : traits<T>::zero();
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const R a0 = rdlane(traits<T>::re(x), i), a1 = rdlane(traits<T>::re(x), 32 + i);
-        const R b0 = rdlane(traits<T>::im(x), i), b1 = rdlane(traits<T>::im(x), 32 + i);
-        const T xi = traits<T>::mk(half ? a1 : a0, half ? b1 : b0);
-        if (i < w && gl > i && gl < w) x = sc_fms(x, s_lu[gl][i], xi);
-      }
-#pragma unroll
-      for (int ii = NB - 1; ii >= 0; --ii) {
-        if (ii < w && gl == ii) {
-          const T d = s_lu[ii][ii];
-          x = traits<T>::abs2(d) == 0 ? x : sc_mul(x, sc_inv(d));
+    if (bi == mine && bi < Rr) {
+      // this lane holds the wave's candidate: publish its row (one branch per row slot,
+      // each to its own buffer, so the register reads keep constant indices)
+      static_for<0, RPT>([&](auto tidx) {
+        constexpr int t = decltype(tidx)::value;
+        if (bi == tid + t * NT) {
+          static_for<0, NB>([&](auto cidx) {
+            constexpr int cc = decltype(cidx)::value;
+            s_cand[buf][wave][t][cc] = traits<T>::mk(re[t][cc], im[t][cc]);
+          });
         }
-        const R a0 = rdlane(traits<T>::re(x), ii), a1 = rdlane(traits<T>::re(x), 32 + ii);
-        const R b0 = rdlane(traits<T>::im(x), ii), b1 = rdlane(traits<T>::im(x), 32 + ii);
-        const T xi = traits<T>::mk(half ? a1 : a0, half ? b1 : b0);
-        if (ii < w && gl < ii) x = sc_fms(x, s_lu[gl][ii], xi);
-      }
-      if (j < w && gl < w) g.pinv[gl + j * w] = x;
+      });
     }
+    __syncthreads();
+    RedPair<R> pr[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) pr[k] = s_red[buf][k];
+    R bv = pr[0].v;
+    int p = pr[0].i;
+#pragma unroll
+    for (int k = 1; k < NW; ++k) {
+      const bool take = (pr[k].v > bv) | ((pr[k].v == bv) & (pr[k].i < p));
+      bv = take ? pr[k].v : bv;
+      p = take ? pr[k].i : p;
+    }
+    if (p < 0 || p >= Rr) {
+      // a NaN column leaves no candidate: take the first row that is not a pivot yet
+      // and publish it through the LDS copy of the panel rows of slot 0 (rare path)
+      p = Rr;
+      for (int r = 0; r < Rr && p == Rr; ++r) {
+        bool used = false;
+        for (int q = 0; q < c; ++q) used |= (s_pphys[q] == r);
+        if (!used) p = r;
+      }
+      __syncthreads();
+      static_for<0, RPT>([&](auto tidx) {
+        constexpr int t = decltype(tidx)::value;
+        if (p == tid + t * NT) {
+          static_for<0, NB>([&](auto cidx) {
+            constexpr int cc = decltype(cidx)::value;
+            s_cand[buf][(p % NT) >> 6][t][cc] = traits<T>::mk(re[t][cc], im[t][cc]);
+          });
+        }
+      });
+      __syncthreads();
+    }
+    const T* prow = &s_cand[buf][(p % NT) >> 6][p / NT][0];
+    if ((p % NT) == tid) done |= 1u << (p / NT);
+    if (tid < NB) s_lu[c][tid] = prow[tid];
+    if (tid == 0) s_pphys[c] = p;
+    const T pv = prow[c];
+    const bool zero = traits<T>::abs2(pv) == 0;
+    if (zero && tid == 0) *g.flag = 1;
+    const T inv = zero ? traits<T>::zero() : sc_inv(pv);
+    // multipliers of the own rows (a pivot row's registers are not read again)
+    T l[RPT];
+    static_for<0, RPT>([&](auto tidx) {
+      constexpr int t = decltype(tidx)::value;
+      l[t] = sc_mul(traits<T>::mk(cr[t], ci[t]), inv);
+    });
+    // chunks of columns: the chunk of the pivot row is read from LDS in one batch
+    constexpr int CH = sizeof(T) == 16 ? 4 : 8;
+    static_for<0, NB / CH>([&](auto chi) {
+      constexpr int cb = decltype(chi)::value * CH;
+      if (cb + CH - 1 >= c) {
+        R pre[CH], pim[CH];
+        static_for<0, CH>([&](auto ui) {
+          constexpr int u = decltype(ui)::value;
+          const T v = prow[cb + u];
+          pre[u] = traits<T>::re(v);
+          pim[u] = traits<T>::im(v);
+        });
+        static_for<0, CH>([&](auto ui) {
+          constexpr int u = decltype(ui)::value;
+          constexpr int cc = cb + u;
+          if (cc == c) {
+            static_for<0, RPT>([&](auto tidx) {
+              constexpr int t = decltype(tidx)::value;
+              re[t][cc] = traits<T>::re(l[t]);
+              im[t][cc] = traits<T>::im(l[t]);
+            });
+          } else if (cc > c) {
+            const T pw = traits<T>::mk(pre[u], pim[u]);
+            static_for<0, RPT>([&](auto tidx) {
+              constexpr int t = decltype(tidx)::value;
+              const T nv = sc_fms(traits<T>::mk(re[t][cc], im[t][cc]), l[t], pw);
+              re[t][cc] = traits<T>::re(nv);
+              im[t][cc] = traits<T>::im(nv);
+              if (cc == c + 1) {
+                cr[t] = re[t][cc];
+                ci[t] = im[t][cc];
+              }
+            });
+          }
+        });
+      }
+    });
   }
+  __syncthreads();
+  if (wave == 0) panel_moves(g.mv, s_pphys, w);
+  pivot_block_inverse<T, NB, NB + 1>(&s_lu[0][0], w, g.pinv);
 }
 
-// Row swaps, pivot-row scaling and panel bookkeeping; grid (tiles of 64 columns, box).
+// Row interchanges, pivot-row scaling and the saved panel columns; grid
+// (ntx column tiles of 64 + row blocks of 256, box). The panel columns of M are
+// not touched here: the trailing GEMM rewrites them completely (beta = 0 on the
+// panel's column window), so the row blocks can copy them to csave concurrently.
+//   column tile: interchanges on its columns outside the panel, then
+//                R' = Pinv * (pivot rows) into rbuf (Pinv itself for panel columns)
+//                and zeros into the pivot rows of M;
+//   row block:   csave = panel columns of the interchanged M, pivot block -I.
+// With C = M - csave R' (beta 0 on the panel window) this gives the pivot rows R',
+// the other rows M - csave R', and the panel columns -csave Pinv / Pinv.
 template <class T>
 __global__ __launch_bounds__(256) void gj_rows_kernel(const GjDesc<T>* __restrict__ descs,
-                                                      int j0, int nb) {
+                                                      int j0, int nb, int ntx) {
+  using R = typename traits<T>::real;
   const GjDesc<T> g = descs[blockIdx.y];
   if (j0 >= g.n) return;
   const int w = min(nb, g.n - j0);
+  const int tid = threadIdx.x;
+  __shared__ int s_mv[2 * 64];
+  const int nm = g.mv[0];
+  if (tid < 2 * nm) s_mv[tid] = g.mv[1 + tid];
+  if ((int)blockIdx.x >= ntx) {
+    // ---- row block: csave rows [r0, r0 + 256)
+    const int r0 = ((int)blockIdx.x - ntx) * 256;
+    if (r0 >= g.n) return;
+    __shared__ int s_src[256];
+    s_src[tid] = -1;
+    __syncthreads();
+    if (tid < nm) {
+      const int dst = j0 + s_mv[2 * tid];
+      if (dst >= r0 && dst < r0 + 256) s_src[dst - r0] = j0 + s_mv[2 * tid + 1];
+    }
+    __syncthreads();
+    const int r = r0 + tid;
+    if (r >= g.n) return;
+    const bool pivrow = r >= j0 && r < j0 + w;
+    const int src = s_src[tid] >= 0 ? s_src[tid] : r;
+    constexpr int U = 8;
+    for (int cb = 0; cb < w; cb += U) {
+      R vr[U], vi[U];
+      static_for<0, U>([&](auto uu) {
+        constexpr int u = decltype(uu)::value;
+        const T x = (cb + u < w && !pivrow) ? g.M[src + (size_t)(j0 + cb + u) * g.n] : traits<T>::zero();
+        vr[u] = traits<T>::re(x);
+        vi[u] = traits<T>::im(x);
+      });
+      static_for<0, U>([&](auto uu) {
+        constexpr int u = decltype(uu)::value;
+        if (cb + u < w) {
+          const T x = pivrow ? (r - j0 == cb + u ? traits<T>::mk(-1.0, 0.0) : traits<T>::zero())
+                             : traits<T>::mk(vr[u], vi[u]);
+          g.csave[r + (size_t)(cb + u) * g.n] = x;
+        }
+      });
+    }
+    return;
+  }
+  // ---- column tile
   const int c0 = blockIdx.x * 64;
   if (c0 >= g.W) return;
   const int cw = min(64, g.W - c0);
   __shared__ T s_pinv[32 * 32];
   __shared__ T s_seg[32][65];
-  __shared__ int s_piv[32];
-  const int tid = threadIdx.x;
-  for (int i = tid; i < w * w; i += 256) s_pinv[i] = g.pinv[i];
-  if (tid < w) s_piv[tid] = g.piv[j0 + tid];
+  static_for<0, 4>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    const int i = tid + k * 256;
+    if (i < w * w) s_pinv[i] = g.pinv[i];
+  });
   __syncthreads();
-  // 1. swaps, column by column (sequential in the pivot order)
-  if (tid < cw) {
-    T* col = g.M + (size_t)(c0 + tid) * g.n;
-    for (int i = 0; i < w; ++i) {
-      int p = s_piv[i];
-      if (p != j0 + i) {
-        T a = col[j0 + i];
-        col[j0 + i] = col[p];
-        col[p] = a;
-      }
+  // 1. the panel's row interchanges as one permutation of at most 2 nb rows: every
+  //    moved entry of the tile (outside the panel columns) is loaded, then all are stored
+  {
+    constexpr int PER = 64 * 64 / 256;
+    R vr[PER], vi[PER];
+    const int tot = nm * cw;
+    static_for<0, PER>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      const int idx = tid + k * 256;
+      const int e = nm > 0 ? idx % nm : 0;
+      const int col = c0 + (nm > 0 ? idx / nm : 0);
+      const bool act = idx < tot && (col < j0 || col >= j0 + w);
+      const T x = act ? g.M[(j0 + s_mv[2 * e + 1]) + (size_t)col * g.n] : traits<T>::zero();
+      vr[k] = traits<T>::re(x);
+      vi[k] = traits<T>::im(x);
+    });
+    __syncthreads();
+    static_for<0, PER>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      const int idx = tid + k * 256;
+      const int e = nm > 0 ? idx % nm : 0;
+      const int col = c0 + (nm > 0 ? idx / nm : 0);
+      if (idx < tot && (col < j0 || col >= j0 + w))
+        g.M[(j0 + s_mv[2 * e]) + (size_t)col * g.n] = traits<T>::mk(vr[k], vi[k]);
+    });
+    if (g.rowperm && blockIdx.x == 0) {
+      if (j0 == 0)
+        for (int i = tid; i < g.n; i += 256) g.rowperm[i] = i;
+      __syncthreads();
+      const int rp = tid < nm ? g.rowperm[j0 + s_mv[2 * tid + 1]] : 0;
+      __syncthreads();
+      if (tid < nm) g.rowperm[j0 + s_mv[2 * tid]] = rp;
     }
   }
   __syncthreads();
-  // 2. panel columns: save (pivot rows zeroed) and clear in M
-  const bool has_panel = (j0 < c0 + cw) && (j0 + w > c0);
-  if (has_panel) {
-    for (int idx = tid; idx < g.n * w; idx += 256) {
-      int r = idx % g.n, c = idx / g.n;
-      T* mp = g.M + r + (size_t)(j0 + c) * g.n;
-      bool pivrow = r >= j0 && r < j0 + w;
-      g.csave[r + (size_t)c * g.n] = pivrow ? traits<T>::zero() : *mp;
-      if (!pivrow) *mp = traits<T>::zero();
-    }
-  }
-  // 3. stage the pivot-row segment, then R' = Pinv * segment
+  // 2. stage the pivot-row segment, then R' = Pinv * segment; zero the pivot rows
   for (int idx = tid; idx < w * cw; idx += 256) {
-    int i = idx % w, c = idx / w;
+    const int i = idx % w, c = idx / w;
     s_seg[i][c] = g.M[(j0 + i) + (size_t)(c0 + c) * g.n];
   }
   __syncthreads();
   for (int idx = tid; idx < w * cw; idx += 256) {
-    int i = idx % w, c = idx / w;
-    int gc = c0 + c;
+    const int i = idx % w, c = idx / w;
+    const int gc = c0 + c;
     T v;
     if (gc >= j0 && gc < j0 + w) {
       v = s_pinv[i + (gc - j0) * w];
     } else {
       v = traits<T>::zero();
       for (int k = 0; k < w; ++k) v = v + sc_mul(s_pinv[i + k * w], s_seg[k][c]);
+      g.M[(j0 + i) + (size_t)gc * g.n] = traits<T>::zero();
     }
     g.rbuf[i + (size_t)gc * w] = v;
-    g.M[(j0 + i) + (size_t)gc * g.n] = v;
   }
 }
 
-// Undo the row interchanges on the columns of the inverse: for j = n-1..0
-// swap columns j and piv[j]. Each thread owns rows, so no synchronisation.
+// Explicit inverse from the pivoted one: A^{-1} = (P A)^{-1} P, i.e. column
+// rowperm[i] of A^{-1} is column i of M; written to out (n x n, ld n). Grid
+// (column tiles, box); one thread per row of a 64-column tile.
 template <class T>
-__global__ __launch_bounds__(256) void gj_unswap_kernel(const GjDesc<T>* __restrict__ descs) {
+__global__ __launch_bounds__(256) void gj_colperm_kernel(const GjDesc<T>* __restrict__ descs, T* const* outs) {
   const GjDesc<T> g = descs[blockIdx.y];
-  for (int r = blockIdx.x * 256 + threadIdx.x; r < g.n; r += gridDim.x * 256) {
-    for (int j = g.n - 1; j >= 0; --j) {
-      int p = g.piv[j];
-      if (p != j) {
-        T a = g.M[r + (size_t)j * g.n];
-        g.M[r + (size_t)j * g.n] = g.M[r + (size_t)p * g.n];
-        g.M[r + (size_t)p * g.n] = a;
-      }
-    }
-  }
+  T* out = outs[blockIdx.y];
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= g.n) return;
+  for (int r = threadIdx.x; r < g.n; r += 256)
+    for (int i = c0; i < min(c0 + 64, g.n); ++i) out[r + (size_t)g.rowperm[i] * g.n] = g.M[r + (size_t)i * g.n];
 }
 
 }  // namespace hss

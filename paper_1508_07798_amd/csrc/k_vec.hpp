@@ -16,6 +16,7 @@ template <class T> struct GemvDesc {
   const int64_t* in_idx;
   int64_t out_off;       // contiguous output offset, or -1 to use out_idx
   const int64_t* out_idx;
+  const int* in_perm;    // if set: input c is in_off + in_perm[c] (a permuted contiguous segment)
 };
 
 // mode 0: y = M x ; mode 1: y -= M x. grid (row tiles of 64, entries); 512 threads
@@ -44,7 +45,8 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* _
       __syncthreads();
       for (int e = tid; e < cw * nr; e += GEMV_THREADS) {
         const int c = e % cw, k = e / cw;
-        const int64_t src = d.in_off >= 0 ? d.in_off + c0 + c : d.in_idx[c0 + c];
+        const int64_t src = d.in_perm ? d.in_off + d.in_perm[c0 + c]
+                                      : d.in_off >= 0 ? d.in_off + c0 + c : d.in_idx[c0 + c];
         xs[k][c] = x[src + (rb + k) * ld];
       }
       __syncthreads();
