@@ -21,7 +21,64 @@ sys.path.insert(0, ROOT)
 
 CLASSES = ["gather", "gj_panel", "gj_rows", "gj_update", "gj_perm", "schur_gemm", "symm", "omega",
            "sample_gemm", "sample", "id", "utall", "expand", "judge", "root", "apply", "spmv", "gmres"]
-PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "hbm": 8000.0}
+# MI355X peaks: dense MFMA FP32 / FP64, vector FP32 / FP64, HBM3E
+PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "alu_fp32": 157.3, "alu_fp64": 78.6, "hbm": 8000.0}
+# bound of each kernel class and whether its algorithmic work is counted in flops or bytes
+BOUND = {"gather": "hbm", "gj_panel": "alu", "gj_rows": "hbm", "gj_update": "mfma", "schur_gemm": "mfma",
+         "symm": "hbm", "omega": "hbm", "sample_gemm": "mfma", "sample": "alu", "id": "alu", "utall": "alu",
+         "expand": "alu", "judge": "hbm", "apply": "hbm", "spmv": "hbm", "root": "hbm", "gj_perm": "hbm"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "roofline_traffic.json")
+
+
+def class_table(h, steps=1):
+    """Per-class time, launches and algorithmic work from a handle's HIP-event profile."""
+    out = {}
+    for c in CLASSES:
+        ms = float(h.query(f"prof.{c}.ms")[0]) / steps
+        n = float(h.query(f"prof.{c}.launches")[0]) / steps
+        if n == 0:
+            continue
+        fl = float(h.query(f"prof.{c}.flops")[0]) / steps
+        by = float(h.query(f"prof.{c}.bytes")[0]) / steps
+        out[c] = {"ms": ms, "launches": n, "flops": fl, "bytes": by}
+    return out
+
+
+def roofline_entry(cls, rec, fp64):
+    bound = BOUND.get(cls, "alu")
+    if bound == "hbm":
+        peak, unit, work = PEAK["hbm"], "GB/s", rec["bytes"]
+        achieved = work / (rec["ms"] * 1e-3) / 1e9 if work > 0 else None
+    else:
+        peak = PEAK[f"{bound}_{'fp64' if fp64 else 'fp32'}"]
+        unit, work = "TFLOP/s", rec["flops"]
+        achieved = work / (rec["ms"] * 1e-3) / 1e12 if work > 0 else None
+    return {"bound": bound, "achieved": None if achieved is None else round(achieved, 4), "peak": peak,
+            "unit": unit, "frac": None if achieved is None else round(achieved / peak, 5),
+            "avg_launch_ms": round(rec["ms"] / rec["launches"], 5),
+            "work_per_launch": work / rec["launches"], "ms_per_step": round(rec["ms"], 4)}
+
+
+def sha256(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of `cls` from the committed counter summary, or None when
+    the summary covers another class or its kernel sources have changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("class") != cls:
+        return None
+    for rel, digest in t.get("sources", {}).items():
+        if sha256(os.path.join(ROOT, rel)) != digest:
+            return None
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline(P):
@@ -50,9 +107,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=None, help="0 skips the FP64 form")
-    ap.add_argument("--copy-calib-mb", type=int, default=0,
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--roofline-class", default="schur_gemm")
+    ap.add_argument("--roofline-class", default=None,
+                    help="kernel class for the roofline object (default: the dominant one)")
     ap.add_argument("--profile-all", action="store_true", help="print the time of every kernel class")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -68,8 +126,8 @@ def main():
 
     P = configs.make("helmholtz_p2_64")
     dev = torch.device("cuda:0")
-    if args.copy_calib_mb > 0:
-        src = torch.ones(args.copy_calib_mb << 18, dtype=torch.float32, device=dev)
+    if args.copy_calib_mib > 0:
+        src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
@@ -77,7 +135,6 @@ def main():
     vals = torch.from_numpy(P.op.vals).to(dev)
     b = torch.from_numpy(np.ascontiguousarray(P.rhs[:, 0])).to(dev)
     kh = P.kappa / P.op.n
-    cls_bit = 1 << (CLASSES.index(args.roofline_class) + 1)
 
     def step(prec, profile):
         h = hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, vals_dev=vals, profile=profile,
@@ -85,53 +142,68 @@ def main():
         x, info = h.gmres(b, tol=P.gmres_tol, restart=P.restart)
         return h, x, info
 
+    def stats(h, info):
+        """What the report needs from a handle (queried before it is closed)."""
+        return {"iters": info[0]["iters"], "relres": info[0]["true_relres"],
+                "table": class_table(h), "flops_factor": float(h.query("flops_factor")[0]),
+                "t_factor": float(h.query("time_factor_ms")[0]), "t_wait": float(h.query("host_wait_ms")[0]),
+                "phases": h.query("phase_ms"), "max_rank": int(h.query("ranks").max())}
+
     def timed(prec, steps, warmup, profile):
+        """Each step factors, solves, reads its statistics and frees the handle, so
+        that the device memory of one step is reused by the next. HIP events (about
+        10 us of device time per record) time the profiled class in the last step only."""
         for _ in range(warmup):
-            h, _, _ = step(prec, profile)
+            h, _, _ = step(prec, 0)
             h.close()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = []
-        for _ in range(steps):
-            h, x, info = step(prec, profile)
-            out.append((h, x, info))
+        for i in range(steps):
+            h, x, info = step(prec, profile if i == steps - 1 else 0)
+            out.append(stats(h, info))
+            h.close()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
         return ms, out
 
+    # one profiled warm-up step names the dominant kernel class (wrapper class gmres excluded)
+    h, _, _ = step("fp32", 1)
+    warm = class_table(h)
+    h.close()
+    dom = args.roofline_class or max((c for c in warm if c != "gmres"), key=lambda c: warm[c]["ms"])
+    cls_bit = 1 << (CLASSES.index(dom) + 1)
+    # timed steps: HIP events only around the dominant class's launches
     ms, runs = timed("fp32", args.steps, args.warmup, cls_bit)
-    h, x, info = runs[-1]
-    iters = [r[2][0]["iters"] for r in runs]
-    relres = max(r[2][0]["true_relres"] for r in runs)
-    # dominant-kernel roofline from the HIP events recorded in the timed steps
-    kms = sum(float(r[0].query(f"prof.{args.roofline_class}.ms")[0]) for r in runs)
-    kl = sum(float(r[0].query(f"prof.{args.roofline_class}.launches")[0]) for r in runs)
-    kfl = sum(float(r[0].query(f"prof.{args.roofline_class}.flops")[0]) for r in runs)
-    avg_ms = kms / max(kl, 1)
-    per_launch_flops = kfl / max(kl, 1)
-    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    flops_factor = float(h.query("flops_factor")[0])
-    t_factor = float(np.mean([float(r[0].query("time_factor_ms")[0]) for r in runs]))
-    ranks = h.query("ranks")
-    for r in runs:
-        r[0].close()
+    iters = [r["iters"] for r in runs]
+    relres = max(r["relres"] for r in runs)
+    tot = runs[-1]["table"][dom]
+    roof = roofline_entry(dom, tot, fp64=False)
+    roof["kernel"] = dom
+    roof["traffic"] = measured_traffic(dom)
+    flops_factor = runs[-1]["flops_factor"]
+    t_factor = float(np.mean([r["t_factor"] for r in runs]))
+    t_wait = float(np.mean([r["t_wait"] for r in runs]))
+    phases = np.mean([r["phases"] for r in runs], axis=0)
+    max_rank = runs[-1]["max_rank"]
+    # per-class table from one more profiled step
+    h, _, _ = step("fp32", 1)
+    table = class_table(h)
+    h.close()
+    classes = {c: roofline_entry(c, rec, fp64=False) for c, rec in table.items() if c != "gmres"}
 
     fsteps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
     ms64 = iters64 = t_factor64 = None
     if fsteps > 0:
         ms64, runs64 = timed("fp64", fsteps, 1, 0)
-        iters64 = runs64[-1][2][0]["iters"]
-        t_factor64 = float(np.mean([float(r[0].query("time_factor_ms")[0]) for r in runs64]))
-        for r in runs64:
-            r[0].close()
+        iters64 = runs64[-1]["iters"]
+        t_factor64 = float(np.mean([r["t_factor"] for r in runs64]))
 
     if args.profile_all:
-        h, _, _ = step("fp32", 1)
-        tot = {c: float(h.query(f"prof.{c}.ms")[0]) for c in CLASSES}
-        for c in sorted(tot, key=lambda c: -tot[c]):
-            print(f"  {c:12s} {tot[c]:8.3f} ms  launches {int(h.query(f'prof.{c}.launches')[0])}"
-                  f"  flops {h.query(f'prof.{c}.flops')[0]:.3e}", file=sys.stderr)
-        h.close()
+        for c in sorted(classes, key=lambda c: -classes[c]["ms_per_step"]):
+            e = classes[c]
+            print(f"  {c:12s} {e['ms_per_step']:8.3f} ms  {e['bound']:4s} achieved {e['achieved']} {e['unit']}"
+                  f"  frac {e['frac']}", file=sys.stderr)
 
     cpu = None
     if not args.no_cpu:
@@ -159,16 +231,17 @@ def main():
         "fp64_ms_per_step": None if ms64 is None else round(ms64, 3),
         "speedup_vs_fp64": None if ms64 is None else round(ms64 / ms, 3),
         "factor_ms": round(t_factor, 3),
+        "factor_host_wait_ms": round(t_wait, 3),
+        "factor_phase_ms": dict(zip(["upload", "features", "gather", "gauss_jordan", "schur", "compression",
+                                     "root", "apply_setup"], [round(float(v), 3) for v in phases])),
         "factor_ms_fp64": None if t_factor64 is None else round(t_factor64, 3),
         "factor_tflops": round(flops_factor / (t_factor * 1e-3) / 1e12, 4),
         "gmres_iters": iters[-1],
         "gmres_iters_fp64": iters64,
         "true_relres": relres,
-        "max_rank": int(ranks.max()),
-        "roofline": {"bound": "mfma", "kernel": args.roofline_class, "achieved": round(achieved, 3),
-                     "peak": PEAK["mfma_fp32"], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK["mfma_fp32"], 4), "traffic": None,
-                     "avg_launch_ms": round(avg_ms, 5), "flops_per_launch": per_launch_flops},
+        "max_rank": max_rank,
+        "roofline": roof,
+        "kernel_classes": classes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

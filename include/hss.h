@@ -153,7 +153,10 @@ hss_status_t gmres_solve(hss_handle_t h, int32_t nrhs, const void* b, void* x, i
  * (largest ID rank per box), "attempts" (per box), "l" (final sample count per
  * box), "err" (per box judge error), "node_heap" / "node_prob" / "node_ni" /
  * "node_nb" (per box), "features" (8 per box), "fallbacks", "retries",
- * "flops_factor", "bytes_apply", "bytes_spmv", "time_factor_ms",
+ * "flops_factor", "bytes_apply", "bytes_spmv", "time_factor_ms", "host_wait_ms"
+ * (time the factorization spent waiting for the device at its sync points),
+ * "phase_ms" (8 values: host wall time of operator upload, features, gather,
+ * Gauss-Jordan, Schur GEMM, compression, root, apply set-up),
  * "prof.<class>.ms|launches|flops|bytes" (HIP-event time, launch count and
  * algorithmic work of the timed launches) for the classes, in bit order:
  * gather, gj_panel, gj_rows, gj_update, gj_perm, schur_gemm, symm, omega,

@@ -85,6 +85,51 @@ void mark_clean(hipStream_t st) {
 }
 }  // namespace
 
+// Pinned host staging for uploads: chunks from hipHostMalloc, cached for the
+// process so that a factorization does not pay for host allocations.
+namespace {
+std::mutex g_pin_mu;
+std::vector<std::pair<char*, size_t>> g_pin_free;
+}  // namespace
+struct Pinned {
+  std::vector<std::pair<char*, size_t>> chunks;  // in use by this owner
+  size_t ci = 0, off = 0;                        // current chunk and offset
+  char* get(size_t n) {
+    n = (n + 255) & ~size_t(255);
+    while (ci < chunks.size() && off + n > chunks[ci].second) ++ci, off = 0;
+    if (ci == chunks.size()) {
+      const size_t want = std::max(n, (size_t)4 << 20);
+      std::pair<char*, size_t> c{nullptr, 0};
+      {
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        for (auto it = g_pin_free.begin(); it != g_pin_free.end(); ++it)
+          if (it->second >= want) {
+            c = *it;
+            g_pin_free.erase(it);
+            break;
+          }
+      }
+      if (!c.first) {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, want, hipHostMallocDefault) != hipSuccess || !h)
+          throw Error(HSS_ENOMEM, "pinned host allocation failed");
+        c = {(char*)h, want};
+      }
+      chunks.push_back(c);
+      off = 0;
+    }
+    char* p = chunks[ci].first + off;
+    off += n;
+    return p;
+  }
+  // the stream has drained: every staged byte has been copied
+  void reset() { ci = 0, off = 0; }
+  ~Pinned() {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    for (auto& c : chunks) g_pin_free.push_back(c);
+  }
+};
+
 // Device memory of one phase: bump allocation from large chunks (few runtime
 // allocations), plus a staging region for host->device uploads of descriptor
 // arrays that are copied in one transfer per launch point.
@@ -113,8 +158,7 @@ struct Arena {
   }
   // returns the device address the bytes will have once flushed; `flushq`
   // receives this arena when it holds unflushed bytes
-  template <class X> X* up(const std::vector<X>& v, std::deque<std::vector<char>>& keep,
-                           std::vector<Arena*>& flushq) {
+  template <class X> X* up(const std::vector<X>& v, Pinned& keep, std::vector<Arena*>& flushq) {
     if (v.empty()) return nullptr;
     const size_t bytes = v.size() * sizeof(X);
     size_t off = (up_used + 255) & ~size_t(255);
@@ -132,12 +176,13 @@ struct Arena {
     if (flushq.empty() || std::find(flushq.begin(), flushq.end(), this) == flushq.end()) flushq.push_back(this);
     return (X*)(up_dev + off);
   }
-  void flush(std::deque<std::vector<char>>& keep) {
+  void flush(Pinned& keep) {
     if (up_used <= up_flushed) return;
-    keep.emplace_back(std::move(up_host));
+    const size_t bytes = up_used - up_flushed;
+    char* h = keep.get(bytes);
+    std::memcpy(h, up_host.data(), bytes);
     up_host.clear();
-    HIP_CHECK(hipMemcpyAsync(up_dev + up_flushed, keep.back().data(), up_used - up_flushed,
-                             hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(up_dev + up_flushed, h, bytes, hipMemcpyHostToDevice, st));
     up_flushed = up_used;
   }
   void release() {
@@ -161,6 +206,13 @@ static const char* kClsName[C_NCLS] = {"gather", "gj_panel", "gj_rows", "gj_upda
                                        "schur_gemm", "symm", "omega", "sample_gemm", "sample", "id",
                                        "utall", "expand", "judge", "root", "apply", "spmv", "gmres"};
 
+// HIP events are created once per process and reused by every handle's profiler
+// (creating them per factorization costs more than the kernels they time).
+namespace {
+std::mutex g_ev_mu;
+std::vector<hipEvent_t> g_ev_free;
+}  // namespace
+
 struct Prof {
   bool on = false;
   unsigned mask = ~0u;  // kernel classes that are timed
@@ -177,8 +229,15 @@ struct Prof {
   long launches[C_NCLS] = {};
   hipEvent_t ev() {
     if (used == pool.size()) {
-      hipEvent_t e;
-      HIP_CHECK(hipEventCreate(&e));
+      hipEvent_t e = nullptr;
+      {
+        std::lock_guard<std::mutex> lk(g_ev_mu);
+        if (!g_ev_free.empty()) {
+          e = g_ev_free.back();
+          g_ev_free.pop_back();
+        }
+      }
+      if (!e) HIP_CHECK(hipEventCreate(&e));
       pool.push_back(e);
     }
     return pool[used++];
@@ -213,7 +272,8 @@ struct Prof {
     for (int i = 0; i < C_NCLS; ++i) ms[i] = flops[i] = bytes[i] = 0, launches[i] = 0;
   }
   ~Prof() {
-    for (auto e : pool) (void)hipEventDestroy(e);
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    for (auto e : pool) g_ev_free.push_back(e);
   }
 };
 
@@ -243,14 +303,14 @@ template <class T> struct Engine : EngineBase {
   static constexpr int kPanelStaticLds = 24576;
   double tol = 0;
   Prof prof;
-  std::deque<std::vector<char>> keep;  // host staging kept alive until the next sync
+  Pinned keep;  // pinned host staging, reused after each sync
   Arena persist, scratch;
 
   // operator on the device
   int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr, *d_dof_elem = nullptr, *d_dof_prob = nullptr;
   W* d_vals = nullptr;
   int64_t *d_elem_dof = nullptr, *d_seg_off = nullptr, *d_perm = nullptr;
-  int64_t ntot = 0;
+  int64_t ntot = 0, nnzb = 0;
   int q = 0;
 
   struct NodeDev {
@@ -277,7 +337,8 @@ template <class T> struct Engine : EngineBase {
   std::vector<double> err_v;
   std::vector<float> tmax_v;
   int fallbacks = 0, retries = 0;
-  double flops_factor = 0, time_factor_ms = 0;
+  double flops_factor = 0, time_factor_ms = 0, host_wait_ms = 0;
+  double phase_ms[8] = {};
   std::vector<float> feat_v;
 
   // apply
@@ -324,7 +385,6 @@ template <class T> struct Engine : EngineBase {
   ~Engine() override {
     flushq.clear();
     (void)hipStreamSynchronize(st);
-    keep.clear();
     work.release();
     scratch.release();
     persist.release();
@@ -340,14 +400,29 @@ template <class T> struct Engine : EngineBase {
   }
   template <class X> void h2d(X* dst, const std::vector<X>& v) {
     if (v.empty()) return;
-    size_t bytes = v.size() * sizeof(X);
-    keep.emplace_back((const char*)v.data(), (const char*)v.data() + bytes);
-    HIP_CHECK(hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, st));
+    const size_t bytes = v.size() * sizeof(X);
+    if (bytes > ((size_t)4 << 20)) {  // large: copy directly and wait (no pinned copy kept)
+      HIP_CHECK(hipMemcpyAsync(dst, v.data(), bytes, hipMemcpyHostToDevice, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      return;
+    }
+    char* h = keep.get(bytes);
+    std::memcpy(h, v.data(), bytes);
+    HIP_CHECK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st));
   }
   void sync() {
     fl();
+    const auto t0 = std::chrono::high_resolution_clock::now();
     HIP_CHECK(hipStreamSynchronize(st));
-    keep.clear();
+    host_wait_ms += std::chrono::duration<double, std::milli>(std::chrono::high_resolution_clock::now() - t0).count();
+    keep.reset();
+  }
+  // asynchronous device -> pinned host copy; the data is there after the next sync()
+  // and stays valid until the staging buffer is next used
+  template <class X> const X* d2h_pinned(const X* dsrc, size_t n) {
+    X* h = (X*)keep.get(std::max<size_t>(n, 1) * sizeof(X));
+    if (n) HIP_CHECK(hipMemcpyAsync(h, dsrc, n * sizeof(X), hipMemcpyDeviceToHost, st));
+    return h;
   }
   void drop(Arena& a) {
     flushq.erase(std::remove(flushq.begin(), flushq.end(), &a), flushq.end());
@@ -472,14 +547,24 @@ template <class T> struct Engine : EngineBase {
     const X m1 = traits<X>::mk(-1.0, 0.0), p1 = traits<X>::one();
     for (int j0 = 0, pi = 0; j0 < nmax; j0 += nb, ++pi) {
       fl();
-      int id = prof.start(C_GJ_PANEL, 0, 0);
+      // algorithmic work of this panel step: LU flops of the panels, bytes of gj_rows
+      double pfl = 0, rby = 0;
+      if (prof.on) {
+        for (auto& g : ds) {
+          if (j0 >= g.n) continue;
+          const double w = std::min(nb, g.n - j0), R = g.n - j0;
+          for (int c = 0; c < (int)w; ++c) pfl += Flop<X>::mac * (R - c - 1) * (w - c - 1);
+          rby += (2.0 * g.n * w + 3.0 * w * g.W) * sX;
+        }
+      }
+      int id = prof.start(C_GJ_PANEL, pfl, 0);
       if (reg) launch_panel_reg<X>(dd, nn, j0, nb, rpt, shm);
       else if (lds && nb == 16) gj_panel_kernel<X, true, 16><<<nn, GJ_PANEL_THREADS, shm, st>>>(dd, j0, nb);
       else if (lds) gj_panel_kernel<X, true, 32><<<nn, GJ_PANEL_THREADS, shm, st>>>(dd, j0, nb);
       else gj_panel_kernel<X, false, 32><<<nn, GJ_PANEL_THREADS, 0, st>>>(dd, j0, nb);
       prof.stop(id);
       check_launch("gj_panel");
-      id = prof.start(C_GJ_ROWS, 0, 0);
+      id = prof.start(C_GJ_ROWS, 0, rby);
       gj_rows_kernel<X><<<dim3(cdiv(wmax, 64) + cdiv(nmax, 256), nn), 256, 0, st>>>(dd, j0, nb, cdiv(wmax, 64));
       prof.stop(id);
       check_launch("gj_rows");
@@ -490,6 +575,15 @@ template <class T> struct Engine : EngineBase {
   // ---------------------------------------------------------------- factor
   void factor(const hss_block_op_t* A, double tol_) override {
     auto t0 = std::chrono::high_resolution_clock::now();
+    // host wall time per phase: 0 operator and index upload, 1 features, 2 gather,
+    // 3 Gauss-Jordan, 4 Schur GEMM, 5 compression, 6 root, 7 apply set-up
+    std::fill(std::begin(phase_ms), std::end(phase_ms), 0.0);
+    auto tl = t0;
+    auto lap = [&](int k) {
+      const auto now = std::chrono::high_resolution_clock::now();
+      phase_ms[k] += std::chrono::duration<double, std::milli>(now - tl).count();
+      tl = now;
+    };
     tol = tol_;
     const int nprob = (int)P.probs.size();
     // operator upload (FP64)
@@ -512,6 +606,7 @@ template <class T> struct Engine : EngineBase {
       }
       d_row_ptr = up(rp, persist);
       d_col_idx = up(ci, persist);
+      nnzb = (int64_t)ci.size();
       d_elem_dof = up(elem_dof, persist);
       d_seg_off = up(seg, persist);
       d_dof_elem = up(dof_elem, persist);
@@ -583,10 +678,13 @@ template <class T> struct Engine : EngineBase {
     tmax_v.assign(nn, 0.f);
     fallbacks = retries = 0;
     flops_factor = 0;
+    host_wait_ms = 0;
     int* d_sing = persist.get<int>(nn + nprob + 1);
     HIP_CHECK(hipMemsetAsync(d_sing, 0, sizeof(int) * (nn + nprob + 1), st));
+    lap(0);
     // features need the diagonal-block norms: computed on the host copy if available
     compute_features(A);
+    lap(1);
 
     std::vector<Arena> wave_st(P.waves.size());
     for (size_t h = 0; h < P.waves.size(); ++h) {
@@ -636,7 +734,12 @@ template <class T> struct Engine : EngineBase {
         auto* dA = up(Ap, tmp);
         auto* dS = up(Sp, tmp);
         OpDev op{d_row_ptr, d_col_idx, d_vals, q};
-        int id = prof.start(C_GATHER, 0, 0);
+        double gby = 0;
+        for (auto& g : gd) {
+          const double e = (double)g.ni * (g.ni + g.nb) + (double)g.nb * g.ni + (double)g.nb * g.nb;
+          gby += e * (sizeof(T) + (g.st[0] ? sizeof(T) : sizeof(W)));
+        }
+        int id = prof.start(C_GATHER, 0, gby);
         fl();
         gather_kernel<T, W, T><<<dim3(grid1(maxe, 512), (unsigned)wv.size()), 256, 0, st>>>(op, dgd, dM, dA, dS);
         prof.stop(id);
@@ -656,7 +759,9 @@ template <class T> struct Engine : EngineBase {
           g.flag = d_sing + wv[i];
           gj.push_back(g);
         }
+        lap(2);
         gauss_jordan<T>(gj, tmp);
+        lap(3);
       }
       // 3. Schur update S = A_bb - A_bi X
       {
@@ -669,9 +774,11 @@ template <class T> struct Engine : EngineBase {
         }
         gemm<T>(gd, traits<T>::mk(-1.0, 0.0), traits<T>::one(), C_SCHUR, tmp);
       }
+      lap(4);
       // 4. compression
       compress_wave(wv, Sp, tmp);
       drop(tmp);
+      lap(5);
     }
     // root of every problem
     rt.assign(nprob, RootDev{});
@@ -753,8 +860,10 @@ template <class T> struct Engine : EngineBase {
           throw Error(HSS_ESINGULAR, "zero pivot in " + who);
         }
     }
+    lap(6);
     build_apply();
     sync();
+    lap(7);
     mark_clean(st);
     prof.collect();
     time_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::high_resolution_clock::now() - t0).count();
@@ -840,7 +949,9 @@ template <class T> struct Engine : EngineBase {
     }
     {
       auto* d = up(all, tmp);
-      int id = prof.start(C_SYMM, 0, 0);
+      double sby = 0;
+      for (auto& b : all) sby += 2.0 * b.n * b.n * sizeof(T);
+      int id = prof.start(C_SYMM, 0, sby);
       fl();
       symm_norm_kernel<T><<<dim3(grid1(maxe, 256), nb_boxes), 256, 0, st>>>(d);
       prof.stop(id);
@@ -862,8 +973,10 @@ template <class T> struct Engine : EngineBase {
       int lcap = std::min(all[i].n + o.p_os, 256);
       lcur[i] = std::min(std::max(predicted_l(wv[i]), 4), lcap);
     }
+    // the norms are read at the first judge sync (no wait here)
     std::vector<double> nrm(nb_boxes, 0.0);
-    HIP_CHECK(hipMemcpyAsync(nrm.data(), d_nrm, sizeof(double) * nb_boxes, hipMemcpyDeviceToHost, st));
+    const double* h_nrm = d2h_pinned(d_nrm, nb_boxes);
+    bool have_nrm = false;
     std::vector<int> fallback_boxes;
     while (!todo.empty()) {
       Arena at;
@@ -942,37 +1055,60 @@ template <class T> struct Engine : EngineBase {
           for (int c0 = 0; c0 < nc; c0 += tw)
             for (int r0 = 0; r0 < na_; r0 += 64) tiles.push_back({(int)t, r0, c0});
         }
+      // every list of this attempt is uploaded before its first launch (one copy)
       auto* dbx = up(bx, at);
       auto* dhs = up(hs, at);
+      const int nh = (int)byh.size();
+      std::vector<int*> d_lvl(nh, nullptr);
+      std::vector<HTile*> d_stl(nh, nullptr), d_utl(nh, nullptr);
+      std::vector<unsigned> n_stl(nh, 0), n_utl(nh, 0);
+      std::vector<double> sfl(nh, 0.0);
+      std::vector<int> zmax(nh, 0);
+      for (int hh = 0; hh < nh; ++hh) {
+        if (byh[hh].empty()) continue;
+        d_lvl[hh] = up(byh[hh], at);
+        std::vector<HTile> stl, utl;
+        for (int t : byh[hh]) {
+          const HssDesc<T>& d = hs[t];
+          for (int r0 = 0; r0 < d.zcap; r0 += 64)
+            for (int c0 = 0; c0 < bx[d.box].l; c0 += 64) stl.push_back({t, r0, c0});
+          for (int r0 = 0; r0 < d.hi - d.lo; r0 += 64) utl.push_back({t, r0, 0});
+          sfl[hh] += Flop<T>::mac * (double)d.zcap * (d.hi - d.lo) * bx[d.box].l;
+          zmax[hh] = std::max(zmax[hh], d.zcap);
+        }
+        d_stl[hh] = up(stl, at);
+        d_utl[hh] = up(utl, at);
+        n_stl[hh] = (unsigned)stl.size();
+        n_utl[hh] = (unsigned)utl.size();
+      }
+      int* d_leaves = up(leaves, at);
+      HTile* d_tiles = tiles.empty() ? nullptr : up(tiles, at);
+      double oby = 0, jby = 0;
+      for (auto& b : bx) {
+        oby += (double)b.n * b.l * sizeof(T);
+        jby += 2.0 * b.n * b.n * sizeof(T);
+      }
       {
-        int id = prof.start(C_OMEGA, 0, 0);
+        int id = prof.start(C_OMEGA, 0, oby);
         fl();
         omega_kernel<T><<<dim3(grid1(maxol, 256), na), 256, 0, st>>>(dbx, o.seed);
         prof.stop(id);
         check_launch("omega");
       }
       gemm<T>(yg, traits<T>::one(), traits<T>::zero(), C_SAMPLE_GEMM, at);
-      for (size_t hh = 0; hh < byh.size(); ++hh) {
+      for (int hh = 0; hh < nh; ++hh) {
         if (byh[hh].empty()) continue;
-        int* dl = up(byh[hh], at);
-        std::vector<HTile> stl;
-        for (int t : byh[hh])
-          for (int r0 = 0; r0 < hs[t].zcap; r0 += 64)
-            for (int c0 = 0; c0 < bx[hs[t].box].l; c0 += 64) stl.push_back({t, r0, c0});
-        HTile* dst = up(stl, at);
-        int id = prof.start(C_SAMPLE, 0, 0);
+        int id = prof.start(C_SAMPLE, sfl[hh], 0);
         fl();
-        sample_kernel<T><<<(unsigned)stl.size(), 256, 0, st>>>(dbx, dhs, dst);
+        sample_kernel<T><<<n_stl[hh], 256, 0, st>>>(dbx, dhs, d_stl[hh]);
         prof.stop(id);
         check_launch("sample");
         id = prof.start(C_ID, 0, 0);
-        fl();
         {
-          int zmax = 0;
-          for (int t : byh[hh]) zmax = std::max(zmax, hs[t].zcap);
-          const size_t shm = (size_t)lmax * zmax * sizeof(T);
+          const size_t shm = (size_t)lmax * zmax[hh] * sizeof(T);
           const unsigned g = (unsigned)byh[hh].size();
           const bool in_lds = shm <= (size_t)(lds_max > 65536 ? 65536 : 32768);
+          int* dl = d_lvl[hh];
           if (lmax <= 64) {
             if (in_lds) cpqr_kernel<T, true, 8, 8><<<g, 256, shm, st>>>(dbx, dhs, dl, o.p_os);
             else cpqr_kernel<T, false, 8, 8><<<g, 256, 0, st>>>(dbx, dhs, dl, o.p_os);
@@ -984,42 +1120,37 @@ template <class T> struct Engine : EngineBase {
         prof.stop(id);
         check_launch("cpqr");
       }
-      for (size_t hh = 0; hh < byh.size(); ++hh) {
+      for (int hh = 0; hh < nh; ++hh) {
         if (byh[hh].empty()) continue;
-        std::vector<HTile> utl;
-        for (int t : byh[hh])
-          for (int r0 = 0; r0 < hs[t].hi - hs[t].lo; r0 += 64) utl.push_back({t, r0, 0});
-        HTile* dut = up(utl, at);
         int id = prof.start(C_UTALL, 0, 0);
-        fl();
-        utall_kernel<T><<<(unsigned)utl.size(), 256, 0, st>>>(dbx, dhs, dut);
+        utall_kernel<T><<<n_utl[hh], 256, 0, st>>>(dbx, dhs, d_utl[hh]);
         prof.stop(id);
         check_launch("utall");
       }
       {
-        int* dl = up(leaves, at);
         int id = prof.start(C_EXPAND, 0, 0);
-        fl();
-        diag_copy_kernel<T><<<(unsigned)leaves.size(), 256, 0, st>>>(dbx, dhs, dl);
+        diag_copy_kernel<T><<<(unsigned)leaves.size(), 256, 0, st>>>(dbx, dhs, d_leaves);
         check_launch("diag_copy");
         if (!tiles.empty()) {
-          auto* dt = up(tiles, at);
-          fl();
-          expand_kernel<T><<<(unsigned)tiles.size(), 256, (size_t)lmax * tw * sizeof(T), st>>>(dbx, dhs, dt, tw);
+          expand_kernel<T><<<(unsigned)tiles.size(), 256, (size_t)lmax * tw * sizeof(T), st>>>(dbx, dhs, d_tiles, tw);
           check_launch("expand");
         }
         prof.stop(id);
-        id = prof.start(C_JUDGE, 0, 0);
-        fl();
+        id = prof.start(C_JUDGE, 0, jby);
         judge_kernel<T><<<dim3(grid1(maxe, 64), na), 256, 0, st>>>(dbx);
         prof.stop(id);
         check_launch("judge");
       }
-      std::vector<double> err(na);
-      std::vector<int> flh(3 * na);
-      HIP_CHECK(hipMemcpyAsync(err.data(), d_err, sizeof(double) * na, hipMemcpyDeviceToHost, st));
-      HIP_CHECK(hipMemcpyAsync(flh.data(), d_flags, sizeof(int) * 3 * na, hipMemcpyDeviceToHost, st));
+      const double* h_err = d2h_pinned(d_err, na);
+      const int* h_flh = d2h_pinned(d_flags, 3 * na);
       sync();
+      // pinned results stay valid until the next staging request
+      std::vector<double> err(h_err, h_err + na);
+      std::vector<int> flh(h_flh, h_flh + 3 * na);
+      if (!have_nrm) {
+        nrm.assign(h_nrm, h_nrm + nb_boxes);
+        have_nrm = true;
+      }
       drop(at);
       std::vector<int> next;
       for (int a = 0; a < na; ++a) {
@@ -1154,7 +1285,7 @@ template <class T> struct Engine : EngineBase {
 
   // ---------------------------------------------------------------- GMRES
   void spmv(const W* x, const W* b, W* y, int nrhs, int mode) {
-    int id = prof.start(C_SPMV, 0, 0);
+    int id = prof.start(C_SPMV, 0, ((double)nnzb * q * q + (mode ? 3.0 : 2.0) * ntot * nrhs) * sizeof(W));
     spmv_kernel<W><<<grid1(ntot * nrhs, 4096), 256, 0, st>>>(d_row_ptr, d_col_idx, d_vals, q, d_dof_elem, d_elem_dof,
                                                              ntot, x, b, y, ntot, nrhs, mode);
     prof.stop(id);
@@ -1403,6 +1534,8 @@ template <class T> struct Engine : EngineBase {
       for (auto& pr : P.probs) nnzb += pr.row_ptr[pr.n_el];
       out = {nnzb * q * q * sizeof(W) + 2.0 * ntot * sizeof(W)};
     } else if (key == "time_factor_ms") out = {time_factor_ms};
+    else if (key == "host_wait_ms") out = {host_wait_ms};
+    else if (key == "phase_ms") out.assign(std::begin(phase_ms), std::end(phase_ms));
     else if (key.rfind("prof.", 0) == 0) {
       prof.collect();
       std::string rest = key.substr(5);
