@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--roofline-class", default=None,
                     help="kernel class for the roofline object (default: the dominant one)")
     ap.add_argument("--profile-all", action="store_true", help="print the time of every kernel class")
+    ap.add_argument("--no-model", action="store_true", help="plain adaptive ID (no rank model)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -136,9 +137,16 @@ def main():
     b = torch.from_numpy(np.ascontiguousarray(P.rhs[:, 0])).to(dev)
     kh = P.kappa / P.op.n
 
-    def step(prec, profile):
+    # the rank model is trained once, before any timing, on smaller seeded problems
+    from paper_1508_07798_amd import rank_model
+    model = None
+    minfo = None
+    if not args.no_model:
+        model, minfo = rank_model.fit_default()
+
+    def step(prec, profile, use_model=True):
         h = hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, vals_dev=vals, profile=profile,
-                       kappa_h=kh)
+                       kappa_h=kh, rank_model=model if use_model else None)
         x, info = h.gmres(b, tol=P.gmres_tol, restart=P.restart)
         return h, x, info
 
@@ -147,20 +155,21 @@ def main():
         return {"iters": info[0]["iters"], "relres": info[0]["true_relres"],
                 "table": class_table(h), "flops_factor": float(h.query("flops_factor")[0]),
                 "t_factor": float(h.query("time_factor_ms")[0]), "t_wait": float(h.query("host_wait_ms")[0]),
-                "phases": h.query("phase_ms"), "max_rank": int(h.query("ranks").max())}
+                "phases": h.query("phase_ms"), "max_rank": int(h.query("ranks").max()),
+                "attempts": np.asarray(h.query("attempts")), "retries": float(h.query("retries")[0])}
 
-    def timed(prec, steps, warmup, profile):
+    def timed(prec, steps, warmup, profile, use_model=True):
         """Each step factors, solves, reads its statistics and frees the handle, so
         that the device memory of one step is reused by the next. HIP events (about
         10 us of device time per record) time the profiled class in the last step only."""
         for _ in range(warmup):
-            h, _, _ = step(prec, 0)
+            h, _, _ = step(prec, 0, use_model)
             h.close()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = []
         for i in range(steps):
-            h, x, info = step(prec, profile if i == steps - 1 else 0)
+            h, x, info = step(prec, profile if i == steps - 1 else 0, use_model)
             out.append(stats(h, info))
             h.close()
         torch.cuda.synchronize()
@@ -191,6 +200,20 @@ def main():
     table = class_table(h)
     h.close()
     classes = {c: roofline_entry(c, rec, fp64=False) for c, rec in table.items() if c != "gmres"}
+
+    # the same mixed form without the rank model (plain adaptive ID)
+    plain = None
+    if model is not None:
+        ms_plain, runs_plain = timed("fp32", max(1, args.steps // 2), 1, 0, use_model=False)
+        att_m = runs[-1]["attempts"]
+        att_p = runs_plain[-1]["attempts"]
+        plain = {"ms_per_step": round(ms_plain, 3), "gmres_iters": runs_plain[-1]["iters"],
+                 "factor_ms": round(float(np.mean([r["t_factor"] for r in runs_plain])), 3),
+                 "compress_attempts": int(att_p.sum()),
+                 "boxes_retried_frac": round(float(np.mean(att_p[att_p > 0] > 1)), 4)}
+        minfo.update({"compress_attempts": int(att_m.sum()),
+                      "boxes_retried_frac": round(float(np.mean(att_m[att_m > 0] > 1)), 4),
+                      "speedup_vs_plain": round(ms_plain / ms, 3)})
 
     fsteps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
     ms64 = iters64 = t_factor64 = None
@@ -240,6 +263,8 @@ def main():
         "gmres_iters_fp64": iters64,
         "true_relres": relres,
         "max_rank": max_rank,
+        "rank_model": minfo,
+        "plain_adaptive": plain,
         "roofline": roof,
         "kernel_classes": classes,
         "cpu_baseline": cpu,

@@ -94,7 +94,8 @@ typedef struct {
   uint64_t seed;           /* Philox key of the Gaussian test matrices            */
   const float* rank_model; /* NULL: plain adaptive ID; else HSS_MLP_NPARAMS host
                               floats (W1,b1,W2,b2,W3,b3, row-major [out][in]) of
-                              the rank predictor that presizes l per box         */
+                              the rank predictor that presizes l per box as
+                              32 * ceil((1.5 k^ + p_os) / 32), k^ its prediction */
   double kappa_h;          /* wavenumber * element size, a rank-model feature    */
   void* hip_stream;        /* hipStream_t for all work (NULL: null stream)       */
   int32_t profile;         /* 0: off; 1: time every kernel class with HIP events on

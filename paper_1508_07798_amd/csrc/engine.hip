@@ -870,32 +870,62 @@ template <class T> struct Engine : EngineBase {
   }
 
   // ---------------------------------------------------------------- features
+  // Per-box inputs of the rank model: depth, log sizes of B and I^, kappa*h, tol,
+  // and mean / spread of log10 ||A_ee||_F over the box's elements (from the host
+  // values, or computed on the device when the values are device-resident).
   void compute_features(const hss_block_op_t* A) {
     const int nn = (int)P.nodes.size();
+    const int nprob = (int)P.probs.size();
+    // log-norms of the diagonal blocks per global element
+    std::vector<float> lnorm;
+    bool dev = false;
+    for (int p = 0; p < nprob; ++p) dev |= (A[p].vals_on_device != 0);
+    int64_t nel = 0;
+    for (auto& pr : P.probs) nel += pr.n_el;
+    lnorm.assign((size_t)nel, 0.f);
+    const size_t blk = (size_t)q * q;
+    if (dev) {
+      std::vector<int64_t> bi((size_t)nel, -1);
+      for (auto& pr : P.probs)
+        for (int e = 0; e < pr.n_el; ++e)
+          if (pr.diag_blk[e] >= 0) bi[pr.el_off + e] = pr.blk_off + pr.diag_blk[e];
+      Arena t;
+      t.st = st;
+      int64_t* db = up(bi, t);
+      float* dout = t.get<float>((size_t)nel);
+      fl();
+      diag_lognorm_kernel<W><<<cdiv(nel, 256), 256, 0, st>>>(d_vals, db, (int)blk, (int)nel, dout);
+      check_launch("diag_lognorm");
+      const float* h = d2h_pinned(dout, (size_t)nel);
+      sync();
+      std::copy(h, h + nel, lnorm.begin());
+      drop(t);
+    } else {
+      for (auto& pr : P.probs) {
+        const int p = (int)(&pr - &P.probs[0]);
+        for (int e = 0; e < pr.n_el; ++e) {
+          const int b = pr.diag_blk[e];
+          double f = 0;
+          if (b >= 0) {
+            const double* v = (const double*)A[p].vals + (CX ? 2 : 1) * (size_t)b * blk;
+            for (size_t k = 0; k < (CX ? 2 : 1) * blk; ++k) f += v[k] * v[k];
+          }
+          lnorm[pr.el_off + e] = (float)(0.5 * std::log10(std::max(f, 1e-300)));
+        }
+      }
+    }
     feat_v.assign((size_t)nn * 8, 0.f);
     for (int g = 0; g < nn; ++g) {
       const PNode& n = P.nodes[g];
       const PProblem& pr = P.probs[n.prob];
       double s1 = 0, s2 = 0;
       int cnt = 0;
-      if (!A[n.prob].vals_on_device) {
-        const size_t blk = (size_t)q * q;
-        for (int e : n.elems) {
-          int b = pr.diag_blk[e];
-          if (b < 0) continue;
-          double f = 0;
-          if (CX) {
-            const double* v = (const double*)A[n.prob].vals + 2 * (size_t)b * blk;
-            for (size_t k = 0; k < 2 * blk; ++k) f += v[k] * v[k];
-          } else {
-            const double* v = (const double*)A[n.prob].vals + (size_t)b * blk;
-            for (size_t k = 0; k < blk; ++k) f += v[k] * v[k];
-          }
-          double lf = 0.5 * std::log10(std::max(f, 1e-300));
-          s1 += lf;
-          s2 += lf * lf;
-          ++cnt;
-        }
+      for (int e : n.elems) {
+        if (pr.diag_blk[e] < 0) continue;
+        const double lf = lnorm[pr.el_off + e];
+        s1 += lf;
+        s2 += lf * lf;
+        ++cnt;
       }
       double mean = cnt ? s1 / cnt : 0, var = cnt ? std::max(0.0, s2 / cnt - mean * mean) : 0;
       float* f = &feat_v[(size_t)g * 8];
@@ -910,8 +940,8 @@ template <class T> struct Engine : EngineBase {
     }
   }
 
-  // predicted sample count per box from the rank model (host evaluation of the
-  // same network the GPU trains; tiny)
+  // sample count per box from the rank model (host evaluation of the same network
+  // the GPU trains; tiny), or l0 without a model
   int predicted_l(int g) const {
     if (!o.rank_model) return o.l0;
     const float* w = o.rank_model;
@@ -927,9 +957,12 @@ template <class T> struct Engine : EngineBase {
       for (int i = 0; i < 64; ++i) z += w[576 + j * 64 + i] * h1[i];
       out += w[4736 + j] * std::tanh(z);
     }
-    double k = std::exp2((double)out) - 1.0;
-    int kk = (int)std::ceil(std::max(0.0, k) * 1.1);
-    return std::max(kk + o.p_os, o.p_os + 2);
+    // l = 32 ceil((1.5 k^ + p_os) / 32): room above the predicted rank keeps the
+    // a-posteriori estimate on the samples reliable (few judge retries), and l in
+    // steps of 32 matches the sampling and CPQR kernels' tiles
+    const double k = std::max(0.0, std::exp2((double)out) - 1.0);
+    const int want = (int)std::ceil(1.5 * k) + o.p_os;
+    return std::max(32, 32 * ((want + 31) / 32));
   }
 
   // ---------------------------------------------------------------- compression

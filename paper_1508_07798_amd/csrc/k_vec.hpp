@@ -89,6 +89,20 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* _
   }
 }
 
+// log10 of the Frobenius norm of every element's diagonal block (rank-model
+// features): out[e] = 0.5 log10(sum |A_ee|^2), blk[e] the block index (or -1).
+template <class V>
+__global__ void diag_lognorm_kernel(const V* __restrict__ vals, const int64_t* __restrict__ blk, int q2, int n,
+                                    float* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t b = blk[e];
+  double f = 0;
+  if (b >= 0)
+    for (int k = 0; k < q2; ++k) f += traits<V>::abs2(vals[b * q2 + k]);
+  out[e] = (float)(0.5 * log10(f > 1e-300 ? f : 1e-300));
+}
+
 // tree order <-> dof order. perm[t] = global dof of tree position t.
 template <class V>
 __global__ void permute_kernel(const V* __restrict__ x, int64_t ldx, V* __restrict__ y, int64_t ldy,

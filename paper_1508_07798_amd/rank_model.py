@@ -1,0 +1,105 @@
+"""Rank-predictor MLP: training data from factorizations, training on the GPU.
+
+The library sizes each separator's randomized sampling from a predicted ID rank
+k^ as l = 32 ceil((1.5 k^ + p_os) / 32) (hss_opts_t.rank_model): samples well
+above the rank keep the a-posteriori error estimate reliable, so few boxes need
+a second round. The paper chooses an
+anticipated rank from observed rank laws (Section 4); here a small network
+8 -> 64 -> 64 -> 1 (tanh, tanh, linear) learns log2(1 + k) from the ranks the
+adaptive ID itself produced on other problems. The judge and the rank-growth
+fallback stay in place, so a poor prediction costs time, never accuracy.
+
+Training runs on the device through the library's own forward / backward /
+Adam kernels (hss_mlp_train).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import hss
+
+SIZES = (8, 64, 64, 1)
+
+
+def init_weights(seed: int = 0) -> np.ndarray:
+    """Flat parameter vector in the library's layout (W1, b1, W2, b2, W3, b3,
+    row-major [out][in]); weights N(0, 1/fan_in), biases 0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(3):
+        fan_in, fan_out = SIZES[i], SIZES[i + 1]
+        parts.append((rng.standard_normal((fan_out, fan_in)) / np.sqrt(fan_in)).ravel())
+        parts.append(np.zeros(fan_out))
+    w = np.concatenate(parts).astype(np.float32)
+    assert w.size == hss.MLP_NPARAMS
+    return w
+
+
+def samples(handle) -> tuple[np.ndarray, np.ndarray]:
+    """(features [nbox, 8], largest ID rank per box) of a factorization; boxes
+    whose complement was not compressed (rank 0) are left out."""
+    f = np.asarray(handle.query("features"), dtype=np.float32).reshape(-1, 8)
+    k = np.asarray(handle.query("ranks"), dtype=np.float64)
+    keep = k > 0
+    return f[keep], k[keep]
+
+
+def collect(problems, prec="fp32", device="cuda:0"):
+    """Factor every problem with the plain adaptive ID and gather (features, ranks)."""
+    import torch
+    X, K = [], []
+    for P in problems:
+        vals = torch.from_numpy(P.op.vals).to(device)
+        kh = P.kappa / P.op.n if P.kappa else 0.0
+        h = hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, vals_dev=vals, kappa_h=kh)
+        x, k = samples(h)
+        h.close()
+        X.append(x)
+        K.append(k)
+    return np.concatenate(X), np.concatenate(K)
+
+
+def train(X: np.ndarray, ranks: np.ndarray, steps: int = 1500, lr: float = 3e-3, seed: int = 0,
+          device="cuda:0"):
+    """Full-batch Adam on the device; returns (weights as a host float32 array, loss history)."""
+    import torch
+    w = torch.from_numpy(init_weights(seed)).to(device)
+    x = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(device)
+    t = torch.from_numpy(np.log2(1.0 + ranks).astype(np.float32)).to(device)
+    hist = hss.mlp_train(w, x, t, steps, lr=lr)
+    return w.cpu().numpy(), hist.cpu().numpy()
+
+
+def predict_rank(w: np.ndarray, X: np.ndarray, device="cuda:0") -> np.ndarray:
+    import torch
+    wd = torch.from_numpy(np.ascontiguousarray(w, dtype=np.float32)).to(device)
+    x = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(device)
+    y = hss.mlp_forward(wd, x).cpu().numpy().astype(np.float64)
+    return np.exp2(y) - 1.0
+
+
+def training_problems(seed_offsets=(1, 2)):
+    """Smaller seeded Helmholtz problems of the bench family (p = 2, 8 dofs per
+    wavelength): grids 16..48 with other seeds than the measured workload."""
+    from workloads import configs
+    out = []
+    for so in seed_offsets:
+        for n in (16, 24, 32, 40, 48):
+            out.append(configs.make("helmholtz_p2_64", n=n, seed_offset=so))
+    return out
+
+
+def fit_default(device="cuda:0", steps=1500):
+    """Collect ranks on the training problems and train; returns (weights, info)."""
+    t0 = time.perf_counter()
+    X, K = collect(training_problems(), device=device)
+    t1 = time.perf_counter()
+    w, hist = train(X, K, steps=steps, device=device)
+    t2 = time.perf_counter()
+    pred = predict_rank(w, X, device=device)
+    info = {"samples": int(X.shape[0]), "collect_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3),
+            "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+            "train_under_predicted": float(np.mean(pred < K))}
+    return w, info
