@@ -4,7 +4,10 @@
  * Same conventions as hss.h (status codes, hss_last_error, column-major,
  * device pointers, work on `hip_stream`, returns after the stream is synced).
  *
- * scalar codes: 0 = float, 1 = double, 2 = complex float, 3 = complex double.
+ * scalar codes: 0 = float, 1 = double, 2 = complex float, 3 = complex double;
+ * hss_debug_gemm also takes 4 = float operands on BF16 matrix cores (each value
+ * split into bf16 hi + lo parts, three products, FP32 accumulation: the Schur
+ * update of the HSS_PREC_BF16 factorization).
  */
 #ifndef HSS_DEBUG_H
 #define HSS_DEBUG_H

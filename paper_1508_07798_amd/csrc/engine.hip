@@ -470,6 +470,17 @@ template <class T> struct Engine : EngineBase {
     check_launch("gemm");
     if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_SAMPLE_GEMM) flops_factor += L.flops;
   }
+  // real FP32 operands on BF16 matrix cores (three products of the hi / lo split)
+  void run_gemm_bf16(const GemmLaunch& L, float alpha, float beta, int cls) {
+    if (L.n == 0) return;
+    fl();
+    int id = prof.start(cls, L.flops, 0);
+    if (cls == C_SCHUR) gemm_bf16x3_kernel<GEMM_SCHUR><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+    else gemm_bf16x3_kernel<GEMM_GENERIC><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+    prof.stop(id);
+    check_launch("gemm_bf16x3");
+    if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_SAMPLE_GEMM) flops_factor += L.flops;
+  }
   template <class X>
   void gemm(const std::vector<GemmDesc>& ds, X alpha, X beta, int cls, Arena& ar) {
     run_gemm<X>(prep_gemm<X>(ds, ar), alpha, beta, cls);
@@ -772,7 +783,15 @@ template <class T> struct Engine : EngineBase {
           if (ni == 0 || nbd == 0) continue;
           gd.push_back({nd[wv[i]].Abi, nd[wv[i]].G + (size_t)ni * ni, Sp[i], nbd, nbd, ni, nbd, ni, nbd});
         }
-        gemm<T>(gd, traits<T>::mk(-1.0, 0.0), traits<T>::one(), C_SCHUR, tmp);
+        if constexpr (std::is_same<T, float>::value) {
+          if (o.prec == HSS_PREC_BF16) {
+            run_gemm_bf16(prep_gemm<T>(gd, tmp), -1.f, 1.f, C_SCHUR);
+          } else {
+            gemm<T>(gd, traits<T>::mk(-1.0, 0.0), traits<T>::one(), C_SCHUR, tmp);
+          }
+        } else {
+          gemm<T>(gd, traits<T>::mk(-1.0, 0.0), traits<T>::one(), C_SCHUR, tmp);
+        }
       }
       lap(4);
       // 4. compression
@@ -1595,7 +1614,8 @@ template <class T> struct Engine : EngineBase {
 
 std::unique_ptr<EngineBase> make_engine(Plan&& plan, const hss_opts_t& opts, bool cplx) {
   const bool fp64 = opts.prec == HSS_PREC_FP64;
-  if (opts.prec == HSS_PREC_BF16) throw Error(HSS_EUNSUPPORTED, "BF16 Schur products are not built yet");
+  if (opts.prec == HSS_PREC_BF16 && cplx)
+    throw Error(HSS_EUNSUPPORTED, "BF16 Schur products are built for real operators only");
   if (cplx) {
     if (fp64) return std::unique_ptr<EngineBase>(new Engine<cd>(std::move(plan), opts));
     return std::unique_ptr<EngineBase>(new Engine<cf>(std::move(plan), opts));
@@ -1615,7 +1635,7 @@ template <class X> struct DebugRunner : Engine<X> {
 template <class X>
 void debug_gemm_t(int nb, const void* const* A, const void* const* B, void* const* C, const int32_t* M,
                   const int32_t* N, const int32_t* K, const int32_t* lda, const int32_t* ldb, const int32_t* ldc,
-                  const double* al, const double* be, hipStream_t st) {
+                  const double* al, const double* be, hipStream_t st, bool bf16x3 = false) {
   std::vector<GemmDesc> v;
   std::vector<int> pre{0};
   for (int b = 0; b < nb; ++b) {
@@ -1630,8 +1650,15 @@ void debug_gemm_t(int nb, const void* const* A, const void* const* B, void* cons
   int* dp = ar.get<int>(pre.size());
   HIP_CHECK(hipMemcpyAsync(dd, v.data(), v.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, st));
   HIP_CHECK(hipMemcpyAsync(dp, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice, st));
-  gemm_nn_kernel<X, GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), traits<X>::mk(al[0], al[1]),
-                                                traits<X>::mk(be[0], be[1]));
+  if constexpr (std::is_same<X, float>::value) {
+    if (bf16x3)
+      gemm_bf16x3_kernel<GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), (float)al[0], (float)be[0]);
+    else
+      gemm_nn_kernel<X, GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), (float)al[0], (float)be[0]);
+  } else {
+    gemm_nn_kernel<X, GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), traits<X>::mk(al[0], al[1]),
+                                                                traits<X>::mk(be[0], be[1]));
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(HSS_EDEVICE, hipGetErrorString(e));
   HIP_CHECK(hipStreamSynchronize(st));
@@ -1648,6 +1675,7 @@ void debug_gemm(int scalar, int nb, const void* const* A, const void* const* B, 
     case 1: debug_gemm_t<double>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
     case 2: debug_gemm_t<cf>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
     case 3: debug_gemm_t<cd>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
+    case 4: debug_gemm_t<float>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st, true); break;
     default: throw Error(HSS_EINVAL, "unknown scalar code");
   }
 }

@@ -201,4 +201,113 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict
     }
 }
 
+// ---------------------------------------------------------------- BF16 x 3
+// Real FP32 operands on BF16 matrix cores with FP32 accumulation: every value is
+// split x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), and the product is
+// taken as hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-16 relative, is dropped),
+// which keeps about 16 significant bits, i.e. ~1e-5 relative error per product
+// sum instead of BF16's ~4e-3. v_mfma_f32_16x16x32_bf16: lane l holds A(l % 16,
+// 8 (l / 16) + j) and B(8 (l / 16) + j, l % 16) for j < 8; the result layout is
+// that of the FP32 16x16 MFMA. Tiles, slabs and the prologue as gemm_nn_kernel.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int ROLE>
+__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmDesc* __restrict__ descs,
+                                                          const int* __restrict__ tprefix, int nent, float alpha,
+                                                          float beta) {
+  constexpr int BK = 32, LDK = BK + 8;  // row pitch 80 bytes: 16-byte aligned 8-element reads
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][GBM][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][GBN][LDK];
+  const int bid = blockIdx.x;
+  int lo = 0, hi = nent;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (tprefix[mid] <= bid) lo = mid; else hi = mid;
+  }
+  const GemmDesc g = descs[lo];
+  const int t = bid - tprefix[lo];
+  const int tmc = (g.M + GBM - 1) / GBM;
+  const int m0 = (t % tmc) * GBM, n0 = (t / tmc) * GBN;
+  const float* __restrict__ Ag = (const float*)g.A;
+  const float* __restrict__ Bg = (const float*)g.B;
+  float* __restrict__ Cg = (float*)g.C;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+  constexpr int E = GBM * BK / 256;  // 8 values of A and of B per thread and slab
+  float ra[E], rb[E];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = tid + e * 256;
+      const int i = idx % GBM, k = idx / GBM;  // A: m fastest (coalesced)
+      const int gi = m0 + i, gk = k0 + k;
+      ra[e] = (gi < g.M && gk < g.K) ? Ag[gi + (size_t)gk * g.lda] : 0.f;
+      const int kb = idx % BK, j = idx / BK;    // B: k fastest (coalesced)
+      const int gkb = k0 + kb, gj = n0 + j;
+      rb[e] = (gkb < g.K && gj < g.N) ? Bg[gkb + (size_t)gj * g.ldb] : 0.f;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = tid + e * 256;
+      const int i = idx % GBM, k = idx / GBM;
+      const __bf16 ah = (__bf16)ra[e];
+      As[0][i][k] = ah;
+      As[1][i][k] = (__bf16)(ra[e] - (float)ah);
+      const int kb = idx % BK, j = idx / BK;
+      const __bf16 bh = (__bf16)rb[e];
+      Bs[0][j][kb] = bh;
+      Bs[1][j][kb] = (__bf16)(rb[e] - (float)bh);
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    store();
+    __syncthreads();
+    if (k0 + BK < g.K) load(k0 + BK);
+    bf16x8 a[2][2], b[2][2];  // [plane][block]
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[p][i] = *(const bf16x8*)&As[p][wm + i * 16 + li][lk * 8];
+        b[p][i] = *(const bf16x8*)&Bs[p][wn + i * 16 + li][lk * 8];
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + j * 16 + li;
+      if (col >= g.N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + i * 16 + mfma_acc<float>::row(lk, v);
+        if (row >= g.M) continue;
+        float* cp = Cg + row + (size_t)col * g.ldc;
+        float out = alpha * acc[i][j][v];
+        const bool keep = col < g.z0 || col >= g.z1;
+        if (keep && beta != 0.f) out += beta * *cp;
+        *cp = out;
+      }
+    }
+}
+
 }  // namespace hss

@@ -308,15 +308,20 @@ def _scalar_code(t):
     return _SCALAR[str(t.dtype).replace("torch.", "")]
 
 
-def debug_gemm(As, Bs, Cs, alpha=1.0, beta=0.0, stream=None):
+def debug_gemm(As, Bs, Cs, alpha=1.0, beta=0.0, stream=None, bf16x3=False):
     """C_b = alpha A_b B_b + beta C_b in place (column-major views of CUDA tensors:
-    pass tensors shaped [cols, rows] in row-major storage, i.e. X.T of the matrix)."""
+    pass tensors shaped [cols, rows] in row-major storage, i.e. X.T of the matrix).
+    bf16x3: float32 operands on the BF16 matrix cores (hi / lo split, three products)."""
     L = lib()
     L.hss_debug_gemm.restype = C.c_int
     n = len(As)
     P = C.c_void_p * n
     I = C.c_int32 * n
     code = _scalar_code(As[0])
+    if bf16x3:
+        if code != 0:
+            raise ValueError("bf16x3 takes float32 operands")
+        code = 4
     M = I(*[c.shape[1] for c in Cs])
     N = I(*[c.shape[0] for c in Cs])
     K = I(*[a.shape[0] for a in As])

@@ -47,6 +47,29 @@ def test_batched_gemm(name):
         assert np.abs(got - R).max() <= tol * scale * max(1.0, np.abs(R).max()), (m, n, k)
 
 
+def test_batched_gemm_bf16x3():
+    """FP32 operands on BF16 matrix cores (hi / lo split, three products): about 16
+    significant bits per product, i.e. far better than plain BF16 (~4e-3)."""
+    print("bf16x3 gemm", flush=True)
+    rng = np.random.default_rng(9)
+    shapes = [(70, 45, 33), (1, 130, 7), (64, 64, 64), (129, 3, 200), (200, 150, 1), (300, 257, 513)]
+    As, Bs, Cs, ref, mag = [], [], [], [], []
+    for (m, n, k) in shapes:
+        A = rng.standard_normal((m, k)).astype(np.float32)
+        B = rng.standard_normal((k, n)).astype(np.float32)
+        Cm = rng.standard_normal((m, n)).astype(np.float32)
+        ref.append(-(A.astype(np.float64) @ B.astype(np.float64)) + Cm)
+        mag.append(np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64)) + np.abs(Cm))
+        As.append(_dev(A, torch.float32))
+        Bs.append(_dev(B, torch.float32))
+        Cs.append(_dev(Cm, torch.float32))
+    hss.debug_gemm(As, Bs, Cs, alpha=-1.0, beta=1.0, bf16x3=True)
+    for (m, n, k), Cd, R, Mg in zip(shapes, Cs, ref, mag):
+        got = Cd.cpu().numpy().T.astype(np.float64)
+        # each product carries a relative error below 2^-15; bound by the sum of |terms|
+        assert np.all(np.abs(got - R) <= 4e-5 * Mg + 1e-6), (m, n, k)
+
+
 @pytest.mark.parametrize("name", list(DT))
 def test_batched_gauss_jordan(name):
     npdt, tdt, tol = DT[name]

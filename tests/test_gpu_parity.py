@@ -100,6 +100,29 @@ def test_helmholtz_reduced(name, n, prec):
     h.close()
 
 
+@pytest.mark.parametrize("n,prec", [(16, "bf16"), (32, "bf16"), (32, "fp32"), (16, "fp64")])
+def test_variable_coefficient_poisson(n, prec):
+    """-div(a grad u) with a = exp(Gaussian random field), p = 3: the BF16 path runs
+    the Schur updates on BF16 matrix cores (hi / lo split) with FP32 elsewhere."""
+    P = configs.make("varpoisson_p3_128", n=n)
+    print(f"varpoisson n={n} {prec}", flush=True)
+    h = hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed)
+    assert h.query("max_err")[0] <= P.tol
+    b = P.rhs[:, 0]
+    x, info = h.gmres(_t(b), tol=P.gmres_tol)
+    g = GOLD[f"varpoisson_p3_128@{n}"]
+    assert abs(info[0]["iters"] - g["iters"]) <= 1, (info, g["iters"])
+    assert _relres(P.op, b, x.cpu().numpy()) <= P.gmres_tol
+    h.close()
+
+
+def test_bf16_is_rejected_for_complex_operators():
+    P = configs.make("helmholtz_p2_64", n=8)
+    with pytest.raises(hss.HssError) as e:
+        hss.factor(P.op, P.tree, P.tol, prec="bf16")
+    assert e.value.status == -6
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_helmholtz_full_size(prec):
     P = configs.make("helmholtz_p2_64")
