@@ -22,12 +22,22 @@ sys.path.insert(0, ROOT)
 CLASSES = ["gather", "gj_panel", "gj_rows", "gj_update", "gj_perm", "schur_gemm", "symm", "omega",
            "sample_gemm", "sample", "id", "utall", "expand", "judge", "root", "apply", "spmv", "gmres"]
 # MI355X peaks: dense MFMA FP32 / FP64, vector FP32 / FP64, HBM3E
-PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "alu_fp32": 157.3, "alu_fp64": 78.6, "hbm": 8000.0}
+PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "mfma_bf16": 2500.0, "alu_fp32": 157.3, "alu_fp64": 78.6,
+        "hbm": 8000.0}
 # bound of each kernel class and whether its algorithmic work is counted in flops or bytes
 BOUND = {"gather": "hbm", "gj_panel": "alu", "gj_rows": "hbm", "gj_update": "mfma", "schur_gemm": "mfma",
          "symm": "hbm", "omega": "hbm", "sample_gemm": "mfma", "sample": "alu", "id": "alu", "utall": "alu",
          "expand": "alu", "judge": "hbm", "apply": "hbm", "spmv": "hbm", "root": "hbm", "gj_perm": "hbm"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "roofline_traffic.json")
+# measured workloads: the mixed form's precision and the arithmetic type it computes in
+WORKLOADS = {
+    "helmholtz_p2_64": {"mixed": "fp32", "dtype": "c64",
+                        "desc": "helmholtz_p2_64: impedance Helmholtz, SIPG p=2, 64x64 elements, 36864 dofs, "
+                                "8 dofs/wavelength, ID tol 1e-4, GMRES(30) to 1e-8"},
+    "varpoisson_p3_128": {"mixed": "bf16", "dtype": "f32 (bf16 Schur products)",
+                          "desc": "varpoisson_p3_128: -div(a grad u), a = exp(GRF l=0.1, var 1), SIPG p=3, "
+                                  "128x128 elements, 262144 dofs, ID tol 1e-5, GMRES(30) to 1e-8"},
+}
 
 
 def class_table(h, steps=1):
@@ -44,8 +54,15 @@ def class_table(h, steps=1):
     return out
 
 
-def roofline_entry(cls, rec, fp64):
+def roofline_entry(cls, rec, fp64, bf16_schur=False):
     bound = BOUND.get(cls, "alu")
+    if bf16_schur and cls == "schur_gemm":  # BF16 matrix cores (algorithmic flops, dense BF16 peak)
+        achieved = rec["flops"] / (rec["ms"] * 1e-3) / 1e12 if rec["flops"] > 0 else None
+        return {"bound": "mfma", "achieved": None if achieved is None else round(achieved, 4),
+                "peak": PEAK["mfma_bf16"], "unit": "TFLOP/s",
+                "frac": None if achieved is None else round(achieved / PEAK["mfma_bf16"], 5),
+                "avg_launch_ms": round(rec["ms"] / rec["launches"], 5),
+                "work_per_launch": rec["flops"] / rec["launches"], "ms_per_step": round(rec["ms"], 4)}
     if bound == "hbm":
         peak, unit, work = PEAK["hbm"], "GB/s", rec["bytes"]
         achieved = work / (rec["ms"] * 1e-3) / 1e9 if work > 0 else None
@@ -113,6 +130,8 @@ def main():
                     help="kernel class for the roofline object (default: the dominant one)")
     ap.add_argument("--profile-all", action="store_true", help="print the time of every kernel class")
     ap.add_argument("--no-model", action="store_true", help="plain adaptive ID (no rank model)")
+    ap.add_argument("--workload", default="helmholtz_p2_64", choices=sorted(WORKLOADS),
+                    help="measured workload (default: the Helmholtz configuration the metric is quoted on)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -125,7 +144,9 @@ def main():
     from paper_1508_07798_amd import hss
     from workloads import configs
 
-    P = configs.make("helmholtz_p2_64")
+    W = WORKLOADS[args.workload]
+    P = configs.make(args.workload)
+    MIX = W["mixed"]
     dev = torch.device("cuda:0")
     if args.copy_calib_mib > 0:
         src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
@@ -135,14 +156,14 @@ def main():
         del src, dst
     vals = torch.from_numpy(P.op.vals).to(dev)
     b = torch.from_numpy(np.ascontiguousarray(P.rhs[:, 0])).to(dev)
-    kh = P.kappa / P.op.n
+    kh = P.kappa / P.op.n if P.kappa else 0.0
 
     # the rank model is trained once, before any timing, on smaller seeded problems
     from paper_1508_07798_amd import rank_model
     model = None
     minfo = None
     if not args.no_model:
-        model, minfo = rank_model.fit_default()
+        model, minfo = rank_model.fit_default(family=args.workload, prec=MIX)
 
     def step(prec, profile, use_model=True):
         h = hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, vals_dev=vals, profile=profile,
@@ -177,17 +198,17 @@ def main():
         return ms, out
 
     # one profiled warm-up step names the dominant kernel class (wrapper class gmres excluded)
-    h, _, _ = step("fp32", 1)
+    h, _, _ = step(MIX, 1)
     warm = class_table(h)
     h.close()
     dom = args.roofline_class or max((c for c in warm if c != "gmres"), key=lambda c: warm[c]["ms"])
     cls_bit = 1 << (CLASSES.index(dom) + 1)
     # timed steps: HIP events only around the dominant class's launches
-    ms, runs = timed("fp32", args.steps, args.warmup, cls_bit)
+    ms, runs = timed(MIX, args.steps, args.warmup, cls_bit)
     iters = [r["iters"] for r in runs]
     relres = max(r["relres"] for r in runs)
     tot = runs[-1]["table"][dom]
-    roof = roofline_entry(dom, tot, fp64=False)
+    roof = roofline_entry(dom, tot, fp64=False, bf16_schur=MIX == "bf16")
     roof["kernel"] = dom
     roof["traffic"] = measured_traffic(dom)
     flops_factor = runs[-1]["flops_factor"]
@@ -196,15 +217,16 @@ def main():
     phases = np.mean([r["phases"] for r in runs], axis=0)
     max_rank = runs[-1]["max_rank"]
     # per-class table from one more profiled step
-    h, _, _ = step("fp32", 1)
+    h, _, _ = step(MIX, 1)
     table = class_table(h)
     h.close()
-    classes = {c: roofline_entry(c, rec, fp64=False) for c, rec in table.items() if c != "gmres"}
+    classes = {c: roofline_entry(c, rec, fp64=False, bf16_schur=MIX == "bf16") for c, rec in table.items()
+               if c != "gmres"}
 
     # the same mixed form without the rank model (plain adaptive ID)
     plain = None
     if model is not None:
-        ms_plain, runs_plain = timed("fp32", max(1, args.steps // 2), 1, 0, use_model=False)
+        ms_plain, runs_plain = timed(MIX, max(1, args.steps // 2), 1, 0, use_model=False)
         att_m = runs[-1]["attempts"]
         att_p = runs_plain[-1]["attempts"]
         plain = {"ms_per_step": round(ms_plain, 3), "gmres_iters": runs_plain[-1]["iters"],
@@ -246,11 +268,9 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64",
+        "dtype": W["dtype"],
         "data": "synthetic",
-        "config": {"workload": "helmholtz_p2_64: impedance Helmholtz, SIPG p=2, 64x64 elements, 36864 dofs, "
-                               "8 dofs/wavelength, ID tol 1e-4, GMRES(30) to 1e-8",
-                   "global_batch": 1, "parallelism": "single GPU"},
+        "config": {"workload": W["desc"], "global_batch": 1, "parallelism": "single GPU"},
         "fp64_ms_per_step": None if ms64 is None else round(ms64, 3),
         "speedup_vs_fp64": None if ms64 is None else round(ms64 / ms, 3),
         "factor_ms": round(t_factor, 3),

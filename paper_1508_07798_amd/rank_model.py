@@ -80,21 +80,21 @@ def predict_rank(w: np.ndarray, X: np.ndarray, device="cuda:0") -> np.ndarray:
     return np.exp2(y) - 1.0
 
 
-def training_problems(seed_offsets=(1, 2)):
-    """Smaller seeded Helmholtz problems of the bench family (p = 2, 8 dofs per
-    wavelength): grids 16..48 with other seeds than the measured workload."""
+def training_problems(family="helmholtz_p2_64", seed_offsets=(1, 2), grids=(16, 24, 32, 40, 48)):
+    """Smaller seeded problems of the measured workload's family (same PDE, degree
+    and tolerance) with other seeds than the measured workload."""
     from workloads import configs
     out = []
     for so in seed_offsets:
-        for n in (16, 24, 32, 40, 48):
-            out.append(configs.make("helmholtz_p2_64", n=n, seed_offset=so))
+        for n in grids:
+            out.append(configs.make(family, n=n, seed_offset=so))
     return out
 
 
-def fit_default(device="cuda:0", steps=1500):
+def fit_default(device="cuda:0", steps=1500, family="helmholtz_p2_64", prec="fp32"):
     """Collect ranks on the training problems and train; returns (weights, info)."""
     t0 = time.perf_counter()
-    X, K = collect(training_problems(), device=device)
+    X, K = collect(training_problems(family), prec=prec, device=device)
     t1 = time.perf_counter()
     w, hist = train(X, K, steps=steps, device=device)
     t2 = time.perf_counter()
