@@ -101,6 +101,8 @@ typedef struct {
   int32_t profile;         /* 0: off; 1: time every kernel class with HIP events on
                               hip_stream; otherwise bit (c + 1) times class c in the
                               order of the hss_query "prof." classes            */
+  int32_t apply_graph;     /* 1 (default): the apply sweeps run as a captured HIP
+                              graph, one per right-hand-side count; 0: eager      */
 } hss_opts_t;
 
 typedef struct {

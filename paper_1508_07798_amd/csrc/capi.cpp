@@ -82,6 +82,7 @@ void hss_default_opts(hss_opts_t* o) {
   o->kappa_h = 0.0;
   o->hip_stream = nullptr;
   o->profile = 0;
+  o->apply_graph = 1;
 }
 
 const char* hss_last_error(void) { return g_err.c_str(); }

@@ -385,6 +385,7 @@ template <class T> struct Engine : EngineBase {
   ~Engine() override {
     flushq.clear();
     (void)hipStreamSynchronize(st);
+    release_graphs();
     work.release();
     scratch.release();
     persist.release();
@@ -1290,16 +1291,65 @@ template <class T> struct Engine : EngineBase {
 
   void ensure_work(int nrhs) {
     if (nrhs <= work_nrhs) return;
+    // the captured sweeps hold the old work buffers
+    HIP_CHECK(hipStreamSynchronize(st));
+    release_graphs();
     work.release();
     d_r = work.get<W>((size_t)ntot * nrhs);
     d_t = work.get<W>((size_t)ntot * nrhs);
     work_nrhs = nrhs;
   }
 
-  template <class X> void gemv(const GemvDesc<X>* d, int n, int maxrows, const W* x, W* y, int nrhs, int mode) {
+  template <class X>
+  void gemv(const GemvDesc<X>* d, int n, int maxrows, const W* x, W* y, int nrhs, int mode, hipStream_t s) {
     if (n == 0 || maxrows == 0) return;
-    gemv_kernel<X, W, 4><<<dim3(cdiv(maxrows, 64), n), GEMV_THREADS, 0, st>>>(d, x, y, (int64_t)ntot, nrhs, mode);
+    gemv_kernel<X, W, 4><<<dim3(cdiv(maxrows, 64), n), GEMV_THREADS, 0, s>>>(d, x, y, (int64_t)ntot, nrhs, mode);
     check_launch("gemv");
+  }
+  // the forward sweep, the root solve and the backward sweep on the tree-ordered
+  // work vectors (d_r in, d_t out): fixed buffers, so the sequence can be captured
+  void sweeps(int nrhs, hipStream_t s) {
+    for (size_t h = 0; h < aw.size(); ++h) {
+      gemv<T>(aw[h].fwd1, aw[h].n, aw[h].max_ni, d_r, d_t, nrhs, 0, s);
+      gemv<T>(aw[h].fwd2, aw[h].n, aw[h].max_nb, d_t, d_r, nrhs, 1, s);
+    }
+    gemv<W>(d_rootdesc, (int)rt.size(), max_nr, d_r, d_t, nrhs, 0, s);
+    for (size_t h = aw.size(); h-- > 0;) gemv<T>(aw[h].bwd, aw[h].n, aw[h].max_ni, d_t, d_t, nrhs, 1, s);
+  }
+  // captured sweeps, one executable graph per right-hand-side count; captured on a
+  // private stream (the caller's may be the null stream) and launched on st
+  struct ApplyGraph {
+    int nrhs;
+    hipGraphExec_t exec;
+  };
+  std::vector<ApplyGraph> agraphs;
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t apply_graph(int nrhs) {
+    for (auto& g : agraphs)
+      if (g.nrhs == nrhs) return g.exec;
+    if (!cap_st) HIP_CHECK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
+    hipGraph_t gr = nullptr;
+    HIP_CHECK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal));
+    try {
+      sweeps(nrhs, cap_st);
+    } catch (...) {
+      (void)hipStreamEndCapture(cap_st, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      throw;
+    }
+    HIP_CHECK(hipStreamEndCapture(cap_st, &gr));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    HIP_CHECK(e);
+    agraphs.push_back({nrhs, ex});
+    return ex;
+  }
+  void release_graphs() {
+    for (auto& g : agraphs) (void)hipGraphExecDestroy(g.exec);
+    agraphs.clear();
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+    cap_st = nullptr;
   }
 
   // y = M^{-t} D^{-1} L^{-1} x with device x, y
@@ -1308,12 +1358,8 @@ template <class T> struct Engine : EngineBase {
     int id = prof.start(C_APPLY, 0, apply_bytes() * nrhs);
     permute_kernel<W><<<grid1(ntot * nrhs), 256, 0, st>>>(x, ldx, d_r, ntot, d_perm, ntot, nrhs, 0);
     check_launch("permute");
-    for (size_t h = 0; h < aw.size(); ++h) {
-      gemv<T>(aw[h].fwd1, aw[h].n, aw[h].max_ni, d_r, d_t, nrhs, 0);
-      gemv<T>(aw[h].fwd2, aw[h].n, aw[h].max_nb, d_t, d_r, nrhs, 1);
-    }
-    gemv<W>(d_rootdesc, (int)rt.size(), max_nr, d_r, d_t, nrhs, 0);
-    for (size_t h = aw.size(); h-- > 0;) gemv<T>(aw[h].bwd, aw[h].n, aw[h].max_ni, d_t, d_t, nrhs, 1);
+    if (o.apply_graph) HIP_CHECK(hipGraphLaunch(apply_graph(nrhs), st));
+    else sweeps(nrhs, st);
     permute_kernel<W><<<grid1(ntot * nrhs), 256, 0, st>>>(d_t, ntot, y, ldy, d_perm, ntot, nrhs, 1);
     check_launch("unpermute");
     prof.stop(id);

@@ -39,7 +39,7 @@ class TreeC(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("p_os", C.c_int32), ("l0", C.c_int32), ("max_attempts", C.c_int32),
                 ("seed", C.c_uint64), ("rank_model", C.c_void_p), ("kappa_h", C.c_double),
-                ("hip_stream", C.c_void_p), ("profile", C.c_int32)]
+                ("hip_stream", C.c_void_p), ("profile", C.c_int32), ("apply_graph", C.c_int32)]
 
 
 class GmresInfo(C.Structure):
@@ -214,15 +214,16 @@ class Handle:
 
 
 def factor(op, tree, tol, prec="fp32", seed=1508, stream=None, l0=32, p_os=10, max_attempts=8,
-           rank_model=None, kappa_h=0.0, profile=False, vals_dev=None):
+           rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True):
     """hss_factor: build the preconditioner of one operator (see include/hss.h)."""
     return factor_batched([op], [tree], tol, prec=prec, seed=seed, stream=stream, l0=l0, p_os=p_os,
                           max_attempts=max_attempts, rank_model=rank_model, kappa_h=kappa_h,
-                          profile=profile, vals_dev=None if vals_dev is None else [vals_dev])
+                          profile=profile, vals_dev=None if vals_dev is None else [vals_dev],
+                          apply_graph=apply_graph)
 
 
 def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, p_os=10, max_attempts=8,
-                   rank_model=None, kappa_h=0.0, profile=False, vals_dev=None):
+                   rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True):
     keep = _Keep()
     n = len(ops)
     A = (BlockOp * n)(*[_op_struct(op, keep, None if vals_dev is None else vals_dev[i])
@@ -235,7 +236,9 @@ def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, 
     o.p_os = p_os
     o.max_attempts = max_attempts
     o.kappa_h = kappa_h
-    o.profile = 1 if profile else 0
+    # True: every kernel class; an int: the class bit mask (bit c + 1 for class c)
+    o.profile = (1 if profile else 0) if isinstance(profile, bool) else int(profile)
+    o.apply_graph = 1 if apply_graph else 0
     o.hip_stream = _stream_ptr(stream)
     if rank_model is not None:
         o.rank_model = keep.arr(rank_model, np.float32)

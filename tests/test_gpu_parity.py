@@ -167,6 +167,30 @@ def test_multiple_rhs_and_batched_problems():
     hb.close()
 
 
+def test_apply_graph_replays_match_eager():
+    """The captured apply sweeps, replayed many times with other device work and
+    synchronizations in between, give the eager sweeps' result every time."""
+    P = configs.make("helmholtz_p2_64", n=16)
+    print("apply graph replays", flush=True)
+    hg = hss.factor(P.op, P.tree, P.tol, prec="fp64", seed=P.seed, apply_graph=True)
+    he = hss.factor(P.op, P.tree, P.tol, prec="fp64", seed=P.seed, apply_graph=False)
+    rng = np.random.default_rng(5)
+    for i in range(6):
+        nrhs = 1 + (i % 3)
+        x = rng.standard_normal((P.op.ndof, nrhs)) + 1j * rng.standard_normal((P.op.ndof, nrhs))
+        yg = hg.apply(_t(x)).cpu().numpy()
+        # unrelated device work and a solve (which replays the graph itself) in between
+        z = torch.randn(512, 512, device=DEV) @ torch.randn(512, 512, device=DEV)
+        torch.cuda.synchronize()
+        _, info = hg.gmres(_t(P.rhs[:, 0]), tol=1e-8)
+        assert info[0]["true_relres"] <= 1e-8
+        ye = he.apply(_t(x)).cpu().numpy()
+        assert np.linalg.norm(yg - ye) <= 1e-12 * np.linalg.norm(ye), i
+        del z
+    hg.close()
+    he.close()
+
+
 def test_judge_and_growth_paths():
     # a tiny l0 forces rank growth; the result still meets tol everywhere
     P = configs.make("helmholtz_p2_64", n=16)
