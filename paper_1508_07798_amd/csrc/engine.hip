@@ -342,15 +342,62 @@ template <class T> struct Engine : EngineBase {
   std::vector<float> feat_v;
 
   // apply
+  // one GEMV launch of the apply: descriptors, work tiles, and the output segments
+  // to clear first when an entry's columns are split (y = M x with atomic adds)
+  template <class X> struct GemvLaunch {
+    GemvDesc<X>* d = nullptr;
+    GemvTile* tiles = nullptr;
+    int ntiles = 0;
+    int64_t* zoff = nullptr;
+    int* zlen = nullptr;
+    int nz = 0, maxz = 0;
+    int sub = 0;
+  };
   struct ApplyWave {
-    GemvDesc<T>* fwd1 = nullptr;
-    GemvDesc<T>* fwd2 = nullptr;
-    GemvDesc<T>* bwd = nullptr;
-    int n = 0, max_ni = 0, max_nb = 0;
+    GemvLaunch<T> fwd1, fwd2, bwd;
   };
   std::vector<ApplyWave> aw;
-  GemvDesc<W>* d_rootdesc = nullptr;
+  GemvLaunch<W> root_gemv;
   int max_nr = 0;
+  // tiles of 64 rows; an entry's columns are split so that a launch has about
+  // 1024 work items (at least 128 columns per item), which keeps HBM busy even
+  // for the few large blocks of the top waves and the root
+  template <class X> GemvLaunch<X> prep_gemv(const std::vector<GemvDesc<X>>& v, int sub) {
+    GemvLaunch<X> L;
+    L.sub = sub;
+    if (v.empty()) return L;
+    int64_t rtiles = 0;
+    for (auto& d : v) rtiles += cdiv(d.rows, 64);
+    const int want = (int)std::max<int64_t>(1, (1024 + rtiles - 1) / std::max<int64_t>(rtiles, 1));
+    std::vector<GemvTile> tl;
+    std::vector<int64_t> zo;
+    std::vector<int> zl;
+    for (size_t e = 0; e < v.size(); ++e) {
+      const auto& d = v[e];
+      if (d.rows <= 0) continue;
+      const int ks = std::max(1, std::min(want, cdiv(d.cols, 128)));
+      const int cs = ((cdiv(d.cols, ks) + 7) / 8) * 8;
+      const int split = ks > 1 && d.cols > cs ? 1 : 0;
+      for (int r0 = 0; r0 < d.rows; r0 += 64)
+        for (int c0 = 0; c0 < std::max(d.cols, 1); c0 += std::max(cs, 1))
+          tl.push_back({(int)e, r0, c0, std::min(d.cols, c0 + cs), split});
+      if (split && !sub) {
+        if (d.out_off < 0) throw Error(HSS_EINVAL, "split product needs a contiguous output");
+        zo.push_back(d.out_off);
+        zl.push_back(d.rows);
+        L.maxz = std::max(L.maxz, d.rows);
+      }
+    }
+    L.d = up(v, persist);
+    L.tiles = up(tl, persist);
+    L.ntiles = (int)tl.size();
+    if (!zo.empty()) {
+      L.zoff = up(zo, persist);
+      L.zlen = up(zl, persist);
+      L.nz = (int)zo.size();
+    }
+    return L;
+  }
   W *d_r = nullptr, *d_t = nullptr;
   int work_nrhs = 0;
   Arena work;
@@ -1271,22 +1318,21 @@ template <class T> struct Engine : EngineBase {
         if (ni == 0) continue;
         const int64_t ip = pr.dof_off + n.ipos;
         f1.push_back({nd[g].G, ni, ni, ip, nullptr, ip, nullptr, nd[g].rowperm});
-        f2.push_back({nd[g].Abi, nbd, ni, ip, nullptr, -1, nd[g].bpos});
-        b1.push_back({nd[g].G + (size_t)ni * ni, ni, nbd, -1, nd[g].bpos, ip, nullptr});
-        a.max_ni = std::max(a.max_ni, ni);
-        a.max_nb = std::max(a.max_nb, nbd);
+        if (nbd > 0) {
+          f2.push_back({nd[g].Abi, nbd, ni, ip, nullptr, -1, nd[g].bpos});
+          b1.push_back({nd[g].G + (size_t)ni * ni, ni, nbd, -1, nd[g].bpos, ip, nullptr});
+        }
       }
-      a.n = (int)f1.size();
-      a.fwd1 = up(f1, persist);
-      a.fwd2 = up(f2, persist);
-      a.bwd = up(b1, persist);
+      a.fwd1 = prep_gemv(f1, 0);
+      a.fwd2 = prep_gemv(f2, 1);
+      a.bwd = prep_gemv(b1, 1);
     }
     std::vector<GemvDesc<W>> rd;
     for (size_t p = 0; p < P.roots.size(); ++p) {
       const int64_t ip = P.probs[p].dof_off + P.roots[p].ipos;
       rd.push_back({rt[p].R, rt[p].n, rt[p].n, ip, nullptr, ip, nullptr, rt[p].rowperm});
     }
-    d_rootdesc = up(rd, persist);
+    root_gemv = prep_gemv(rd, 0);
   }
 
   void ensure_work(int nrhs) {
@@ -1300,21 +1346,23 @@ template <class T> struct Engine : EngineBase {
     work_nrhs = nrhs;
   }
 
-  template <class X>
-  void gemv(const GemvDesc<X>* d, int n, int maxrows, const W* x, W* y, int nrhs, int mode, hipStream_t s) {
-    if (n == 0 || maxrows == 0) return;
-    gemv_kernel<X, W, 4><<<dim3(cdiv(maxrows, 64), n), GEMV_THREADS, 0, s>>>(d, x, y, (int64_t)ntot, nrhs, mode);
+  template <class X> void gemv(const GemvLaunch<X>& L, const W* x, W* y, int nrhs, hipStream_t s) {
+    if (L.ntiles == 0) return;
+    if (L.nz)
+      zero_segments_kernel<W><<<dim3(grid1((int64_t)L.maxz * nrhs, 64), L.nz), 256, 0, s>>>(y, (int64_t)ntot, nrhs,
+                                                                                          L.zoff, L.zlen, L.nz);
+    gemv_kernel<X, W, 4><<<L.ntiles, GEMV_THREADS, 0, s>>>(L.d, L.tiles, x, y, (int64_t)ntot, nrhs, L.sub);
     check_launch("gemv");
   }
   // the forward sweep, the root solve and the backward sweep on the tree-ordered
   // work vectors (d_r in, d_t out): fixed buffers, so the sequence can be captured
   void sweeps(int nrhs, hipStream_t s) {
     for (size_t h = 0; h < aw.size(); ++h) {
-      gemv<T>(aw[h].fwd1, aw[h].n, aw[h].max_ni, d_r, d_t, nrhs, 0, s);
-      gemv<T>(aw[h].fwd2, aw[h].n, aw[h].max_nb, d_t, d_r, nrhs, 1, s);
+      gemv<T>(aw[h].fwd1, d_r, d_t, nrhs, s);
+      gemv<T>(aw[h].fwd2, d_t, d_r, nrhs, s);
     }
-    gemv<W>(d_rootdesc, (int)rt.size(), max_nr, d_r, d_t, nrhs, 0, s);
-    for (size_t h = aw.size(); h-- > 0;) gemv<T>(aw[h].bwd, aw[h].n, aw[h].max_ni, d_t, d_t, nrhs, 1, s);
+    gemv<W>(root_gemv, d_r, d_t, nrhs, s);
+    for (size_t h = aw.size(); h-- > 0;) gemv<T>(aw[h].bwd, d_t, d_t, nrhs, s);
   }
   // captured sweeps, one executable graph per right-hand-side count; captured on a
   // private stream (the caller's may be the null stream) and launched on st

@@ -295,16 +295,17 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
       s_sel[j] = p;
       s_pos[p] = j;
     }
+    // Householder reflector of column p (scalars in the factor's own precision)
     const T x0 = A[j + (size_t)p * l];
-    const double xn2 = (double)s_nrm[j & 1][p];
-    const double xn = sqrt(xn2);
-    const double a0 = sqrt((double)traits<T>::abs2(x0));
-    T alpha;
-    if (a0 > 0) alpha = traits<T>::mk(-traits<T>::re(x0) / a0 * xn, -traits<T>::im(x0) / a0 * xn);
-    else alpha = traits<T>::mk(-xn, 0.0);
+    const R xn2 = s_nrm[j & 1][p];
+    const R xn = sqrt(xn2);
+    const R a0 = sqrt(traits<T>::abs2(x0));
+    const R sc = a0 > 0 ? xn / a0 : R(0);
+    const T alpha = a0 > 0 ? traits<T>::mk(-traits<T>::re(x0) * sc, -traits<T>::im(x0) * sc)
+                           : traits<T>::mk(-xn, 0.0);
     if (tid == 0) s_rdiag[j] = alpha;
-    const double vv = 2.0 * xn2 + 2.0 * a0 * xn;
-    const R f = vv > 0 ? (R)(2.0 / vv) : (R)0;
+    const R vv = R(2) * xn2 + R(2) * a0 * xn;
+    const R f = vv > 0 ? R(2) / vv : R(0);
     const T vj = x0 - alpha;
     // this lane's rows r = j + gl + GL t of the reflector, in registers
     T vr[RPL];
@@ -316,9 +317,8 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
     const int ncol_iter = (m + NG - 1) / NG;
     for (int it = 0; it < ncol_iter; ++it) {
       const int c = it * NG + gid;
-      const int cc = c < m ? c : 0;
-      const unsigned mw = __shfl(chosen, cc & 63);
-      const bool active = c < m && c != p && !((mw >> (cc >> 6)) & 1u);
+      // earlier pivots are in s_pos (written before the last barrier); p is this step's
+      const bool active = c < m && c != p && s_pos[c] < 0;
       T ar[RPL];
       R dre = 0, dim = 0;
 #pragma unroll

@@ -7,7 +7,7 @@
 
 namespace hss {
 
-// Batched GEMV y(out) (+|-)= Mat * x(in) on multi-vectors (nrhs columns, ld).
+// Batched GEMV y(out) = or -= Mat * x(in) on multi-vectors (nrhs columns, ld).
 // Rows / columns are either contiguous from an offset or listed by index.
 template <class T> struct GemvDesc {
   const T* mat;          // rows x cols, column-major, ld = rows
@@ -19,17 +19,33 @@ template <class T> struct GemvDesc {
   const int* in_perm;    // if set: input c is in_off + in_perm[c] (a permuted contiguous segment)
 };
 
-// mode 0: y = M x ; mode 1: y -= M x. grid (row tiles of 64, entries); 512 threads
-// = 64 rows x 8 column groups; matrix loads are issued four at a time.
+// Work item of a GEMV launch: rows [r0, r0 + 64) and columns [c0, c1) of entry
+// `entry`; split != 0 when the entry's columns are spread over several items,
+// whose partial sums are then combined with atomic adds.
+struct GemvTile {
+  int entry, r0, c0, c1, split;
+};
+
+template <class V> __device__ __forceinline__ void atomic_add_v(V* p, V v);
+template <> __device__ __forceinline__ void atomic_add_v<double>(double* p, double v) { atomicAdd(p, v); }
+template <> __device__ __forceinline__ void atomic_add_v<cd>(cd* p, cd v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+
+// sub = 0: y = M x (outputs of split entries must be zero beforehand); sub = 1:
+// y -= M x. One workgroup per tile: 512 threads = 64 rows x 8 column groups,
+// matrix loads four at a time, x staged through LDS in chunks of 256 columns.
 constexpr int GEMV_THREADS = 512;
 template <class T, class V, int NR>
 __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* __restrict__ ds,
+                                                            const GemvTile* __restrict__ tiles,
                                                             const V* __restrict__ x, V* __restrict__ y,
-                                                            int64_t ld, int nrhs, int mode) {
+                                                            int64_t ld, int nrhs, int sub) {
   constexpr int NP = GEMV_THREADS / 64;
-  const GemvDesc<T> d = ds[blockIdx.y];
-  const int r0 = blockIdx.x * 64;
-  if (r0 >= d.rows) return;
+  const GemvTile tl = tiles[blockIdx.x];
+  const GemvDesc<T> d = ds[tl.entry];
+  const int r0 = tl.r0;
   const int tid = threadIdx.x;
   const int rl = tid & 63, part = tid >> 6;
   const int row = r0 + rl;
@@ -40,8 +56,8 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* _
     V acc[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] = traits<V>::zero();
-    for (int c0 = 0; c0 < d.cols; c0 += 256) {
-      const int cw = min(256, d.cols - c0);
+    for (int c0 = tl.c0; c0 < tl.c1; c0 += 256) {
+      const int cw = min(256, tl.c1 - c0);
       __syncthreads();
       for (int e = tid; e < cw * nr; e += GEMV_THREADS) {
         const int c = e % cw, k = e / cw;
@@ -82,11 +98,25 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* _
         V s = red[k][0][rl];
         for (int q = 1; q < NP; ++q) s = s + red[k][q][rl];
         V* yp = y + dst + (rb + k) * ld;
-        *yp = mode == 0 ? s : (*yp - s);
+        if (tl.split) atomic_add_v(yp, sub ? -s : s);
+        else *yp = sub ? (*yp - s) : s;
       }
     }
     __syncthreads();
   }
+}
+
+// zero y over contiguous segments (off[i], len[i]) for all nrhs columns; a kernel,
+// not a memset, because the sweeps are captured into a graph
+template <class V>
+__global__ void zero_segments_kernel(V* __restrict__ y, int64_t ld, int nrhs, const int64_t* __restrict__ off,
+                                     const int* __restrict__ len, int nseg) {
+  const int sgm = blockIdx.y;
+  if (sgm >= nseg) return;
+  const int64_t o = off[sgm];
+  const int n = len[sgm];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)n * nrhs; e += (int64_t)gridDim.x * 256)
+    y[o + e % n + (e / n) * ld] = traits<V>::zero();
 }
 
 // log10 of the Frobenius norm of every element's diagonal block (rank-model
