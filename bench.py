@@ -37,6 +37,10 @@ WORKLOADS = {
     "varpoisson_p3_128": {"mixed": "bf16", "dtype": "f32 (bf16 Schur products)",
                           "desc": "varpoisson_p3_128: -div(a grad u), a = exp(GRF l=0.1, var 1), SIPG p=3, "
                                   "128x128 elements, 262144 dofs, ID tol 1e-5, GMRES(30) to 1e-8"},
+    "helmholtz_batch64": {"mixed": "fp32", "dtype": "c64", "family": "helmholtz_p2_64",
+                          "desc": "helmholtz_batch64: 64 impedance Helmholtz problems, grids U{32..96}, SIPG p=2, "
+                                  "6-10 dofs/wavelength, 4 point sources each, one batched factorization and "
+                                  "solve, ID tol 1e-4, GMRES(30) to 1e-8"},
 }
 
 
@@ -145,8 +149,14 @@ def main():
     from workloads import configs
 
     W = WORKLOADS[args.workload]
-    P = configs.make(args.workload)
     MIX = W["mixed"]
+    def note(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+    note(f"building {args.workload}")
+    probs = configs.make_batch() if args.workload == "helmholtz_batch64" else [configs.make(args.workload)]
+    P = probs[0]
+    note(f"{len(probs)} problem(s), {sum(q.op.ndof for q in probs)} dofs")
     dev = torch.device("cuda:0")
     if args.copy_calib_mib > 0:
         src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
@@ -154,26 +164,33 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    vals = torch.from_numpy(P.op.vals).to(dev)
-    b = torch.from_numpy(np.ascontiguousarray(P.rhs[:, 0])).to(dev)
-    kh = P.kappa / P.op.n if P.kappa else 0.0
+    vals = [torch.from_numpy(q.op.vals).to(dev) for q in probs]
+    batched = len(probs) > 1
+    # a single problem solves its first rhs; the batch solves every rhs of every problem
+    b = torch.from_numpy(np.ascontiguousarray(np.concatenate([q.rhs if batched else q.rhs[:, :1] for q in probs],
+                                                             axis=0))).to(dev)
+    # kappa * h is one feature per handle: the batch takes the mean
+    kh = float(np.mean([q.kappa / q.op.n if q.kappa else 0.0 for q in probs]))
+    tol = probs[0].tol
 
     # the rank model is trained once, before any timing, on smaller seeded problems
     from paper_1508_07798_amd import rank_model
     model = None
     minfo = None
     if not args.no_model:
-        model, minfo = rank_model.fit_default(family=args.workload, prec=MIX)
+        note("training the rank model")
+        model, minfo = rank_model.fit_default(family=W.get("family", args.workload), prec=MIX)
 
     def step(prec, profile, use_model=True):
-        h = hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, vals_dev=vals, profile=profile,
-                       kappa_h=kh, rank_model=model if use_model else None)
-        x, info = h.gmres(b, tol=P.gmres_tol, restart=P.restart)
+        h = hss.factor_batched([q.op for q in probs], [q.tree for q in probs], tol, prec=prec, seed=P.seed,
+                               vals_dev=vals, profile=profile, kappa_h=kh,
+                               rank_model=model if use_model else None)
+        x, info = h.gmres(b, tol=P.gmres_tol, restart=P.restart, nprob=len(probs))
         return h, x, info
 
     def stats(h, info):
         """What the report needs from a handle (queried before it is closed)."""
-        return {"iters": info[0]["iters"], "relres": info[0]["true_relres"],
+        return {"iters": max(i["iters"] for i in info), "relres": max(i["true_relres"] for i in info),
                 "table": class_table(h), "flops_factor": float(h.query("flops_factor")[0]),
                 "t_factor": float(h.query("time_factor_ms")[0]), "t_wait": float(h.query("host_wait_ms")[0]),
                 "phases": h.query("phase_ms"), "max_rank": int(h.query("ranks").max()),
@@ -204,6 +221,7 @@ def main():
     dom = args.roofline_class or max((c for c in warm if c != "gmres"), key=lambda c: warm[c]["ms"])
     cls_bit = 1 << (CLASSES.index(dom) + 1)
     # timed steps: HIP events only around the dominant class's launches
+    note(f"timing {args.steps} steps ({MIX})")
     ms, runs = timed(MIX, args.steps, args.warmup, cls_bit)
     iters = [r["iters"] for r in runs]
     relres = max(r["relres"] for r in runs)
@@ -226,6 +244,7 @@ def main():
     # the same mixed form without the rank model (plain adaptive ID)
     plain = None
     if model is not None:
+        note("timing the plain adaptive form")
         ms_plain, runs_plain = timed(MIX, max(1, args.steps // 2), 1, 0, use_model=False)
         att_m = runs[-1]["attempts"]
         att_p = runs_plain[-1]["attempts"]
@@ -240,6 +259,7 @@ def main():
     fsteps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
     ms64 = iters64 = t_factor64 = None
     if fsteps > 0:
+        note("timing the FP64 form")
         ms64, runs64 = timed("fp64", fsteps, 1, 0)
         iters64 = runs64[-1]["iters"]
         t_factor64 = float(np.mean([r["t_factor"] for r in runs64]))
@@ -251,7 +271,8 @@ def main():
                   f"  frac {e['frac']}", file=sys.stderr)
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not batched:
+        note("timing the oracle on the host")
         cms, citers = cpu_baseline(P)
         cpu = {"value": round(cms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
                "sample": "full workload, one step (factor + GMRES), NumPy/SciPy on one BLAS thread",

@@ -234,8 +234,8 @@ namespace hss {
 void debug_gemm(int scalar, int nb, const void* const* A, const void* const* B, void* const* C, const int32_t* M,
                 const int32_t* N, const int32_t* K, const int32_t* lda, const int32_t* ldb, const int32_t* ldc,
                 const double* al, const double* be, hipStream_t st);
-void debug_gj(int scalar, int nb, void* const* Mat, const int32_t* n, const int32_t* m, int32_t* singular,
-              hipStream_t st);
+void debug_gj(int scalar, int nb, void* const* Mat, const int32_t* n, const int32_t* m, int block,
+              int32_t* singular, hipStream_t st);
 }  // namespace hss
 
 extern "C" {
@@ -257,13 +257,14 @@ hss_status_t hss_debug_gemm(int32_t scalar, int32_t nbatch, const void* const* A
 }
 
 hss_status_t hss_debug_gj(int32_t scalar, int32_t nbatch, void* const* Mat, const int32_t* n, const int32_t* m,
-                          int32_t* singular, void* hip_stream) {
+                          int32_t block, int32_t* singular, void* hip_stream) {
   return guarded([&]() -> hss_status_t {
     if (nbatch < 0 || !Mat || !n || !m || !singular) return fail(HSS_EINVAL, "bad gj arguments");
+    if (block < 0 || block > 128) return fail(HSS_EINVAL, "gj block width must be in [0, 128]");
     for (int b = 0; b < nbatch; ++b)
       if (n[b] < 0 || m[b] < 0) return fail(HSS_EINVAL, "bad gj sizes");
     ensure_device();
-    hss::debug_gj(scalar, nbatch, Mat, n, m, singular, (hipStream_t)hip_stream);
+    hss::debug_gj(scalar, nbatch, Mat, n, m, block, singular, (hipStream_t)hip_stream);
     return HSS_OK;
   });
 }

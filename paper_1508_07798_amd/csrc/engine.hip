@@ -301,6 +301,10 @@ template <class T> struct Engine : EngineBase {
   // LDS kept for the static arrays of the LDS panel kernel (pivot rows of a
   // 32-column complex double panel and the reduction buffers)
   static constexpr int kPanelStaticLds = 24576;
+  // second-level blocking of the Gauss-Jordan elimination: width, and the block size
+  // above which it is used
+  static constexpr int kGjBlock = 128;
+  static constexpr int kGjBlockMin = 512;
   double tol = 0;
   Prof prof;
   Pinned keep;  // pinned host staging, reused after each sync
@@ -555,43 +559,43 @@ template <class T> struct Engine : EngineBase {
                                  std::to_string(rpt));
   }
 
-  // In-place [M_ii | M_ib] -> [M_ii^{-1} | M_ii^{-1} M_ib] for a batch.
-  template <class X>
-  void gauss_jordan(std::vector<GjDesc<X>>& ds, Arena& ar) {
-    if (ds.empty()) return;
-    int nmax = 0, wmax = 0;
-    for (auto& g : ds) nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W);
-    const int sX = (int)sizeof(X);
+  // Panel kernel variant for a batch whose tallest panel has rmax rows.
+  struct GjCfg {
+    int nb, rpt;
+    bool reg, lds;
+    size_t shm;
+  };
+  GjCfg gj_config(int rmax, int sX) const {
+    GjCfg c{};
     // register-resident panel when the tallest panel fits: rows per thread (rpt) and
     // panel width (nb) from a budget of 192 registers for the panel values
     const int words = sX / 4;
-    int rpt = (nmax + GJ_PANEL_THREADS - 1) / GJ_PANEL_THREADS;
-    if (rpt == 5 || rpt == 6 || rpt == 7) rpt = 8;
-    int nb = 32;
-    while (nb > 8 && rpt * nb * words > 192) nb /= 2;
-    bool reg = rpt <= 8 && rpt * nb * words <= 192 && !(sX == 16 && rpt > 6);
-    bool lds = false;
+    c.rpt = (rmax + GJ_PANEL_THREADS - 1) / GJ_PANEL_THREADS;
+    if (c.rpt == 5 || c.rpt == 6 || c.rpt == 7) c.rpt = 8;
+    c.nb = 32;
+    while (c.nb > 8 && c.rpt * c.nb * words > 192) c.nb /= 2;
+    c.reg = c.rpt <= 8 && c.rpt * c.nb * words <= 192 && !(sX == 16 && c.rpt > 6);
     const int64_t avail = lds_max - kPanelStaticLds;
-    if (!reg) {
-      nb = 32;
-      lds = true;
-      while (nb >= 16 && (int64_t)nmax * nb * sX > avail) nb /= 2;
-      if (nb < 16) {
-        nb = 32;
-        lds = false;
+    if (!c.reg) {
+      c.nb = 32;
+      c.lds = true;
+      while (c.nb >= 16 && (int64_t)rmax * c.nb * sX > avail) c.nb /= 2;
+      if (c.nb < 16) {
+        c.nb = 32;
+        c.lds = false;
       }
     }
-    // scratch per box
-    for (auto& g : ds) {
-      g.pinv = ar.get<X>((size_t)nb * nb);
-      g.csave = ar.get<X>((size_t)g.n * nb);
-      g.rbuf = ar.get<X>((size_t)nb * g.W);
-      g.gpanel = lds ? nullptr : ar.get<X>((size_t)g.n * nb);
-      g.mv = ar.get<int>(1 + 4 * (size_t)nb);
-    }
-    GjDesc<X>* dd = up(ds, ar);
-    const int nn = (int)ds.size();
-    const size_t shm = lds ? (size_t)nmax * nb * sX : 0;
+    c.shm = c.lds ? (size_t)rmax * c.nb * sX : 0;
+    return c;
+  }
+
+  // The panel sweep over the pivot columns of a batch of descriptors (uploaded
+  // as dd): panel LU, row movement and scaled pivot rows, trailing GEMM.
+  template <class X>
+  void gj_sweep(const std::vector<GjDesc<X>>& ds, const GjDesc<X>* dd, const GjCfg& c, Arena& ar) {
+    const int nn = (int)ds.size(), nb = c.nb, sX = (int)sizeof(X);
+    int nmax = 0, wmax = 0, rmax = 0;
+    for (auto& g : ds) nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W), rmax = std::max(rmax, g.rows);
     // every panel's trailing-update descriptors, uploaded together
     std::vector<GemmLaunch> upd;
     for (int j0 = 0; j0 < nmax; j0 += nb) {
@@ -599,7 +603,7 @@ template <class T> struct Engine : EngineBase {
       for (auto& g : ds) {
         if (j0 >= g.n) continue;
         int w = std::min(nb, g.n - j0);
-        gd.push_back({g.csave, g.rbuf, g.M, g.n, g.W, w, g.n, w, g.n, j0, j0 + w});
+        gd.push_back({g.csave, g.rbuf, g.M, g.rows, g.W, w, g.rows, w, g.rows, j0, j0 + w});
       }
       upd.push_back(prep_gemm<X>(gd, ar));
     }
@@ -611,23 +615,114 @@ template <class T> struct Engine : EngineBase {
       if (prof.on) {
         for (auto& g : ds) {
           if (j0 >= g.n) continue;
-          const double w = std::min(nb, g.n - j0), R = g.n - j0;
-          for (int c = 0; c < (int)w; ++c) pfl += Flop<X>::mac * (R - c - 1) * (w - c - 1);
-          rby += (2.0 * g.n * w + 3.0 * w * g.W) * sX;
+          const double w = std::min(nb, g.n - j0), R = g.rows - g.poff - j0;
+          for (int cc = 0; cc < (int)w; ++cc) pfl += Flop<X>::mac * (R - cc - 1) * (w - cc - 1);
+          rby += (2.0 * g.rows * w + 3.0 * w * g.W) * sX;
         }
       }
       int id = prof.start(C_GJ_PANEL, pfl, 0);
-      if (reg) launch_panel_reg<X>(dd, nn, j0, nb, rpt, shm);
-      else if (lds && nb == 16) gj_panel_kernel<X, true, 16><<<nn, GJ_PANEL_THREADS, shm, st>>>(dd, j0, nb);
-      else if (lds) gj_panel_kernel<X, true, 32><<<nn, GJ_PANEL_THREADS, shm, st>>>(dd, j0, nb);
+      if (c.reg) launch_panel_reg<X>(dd, nn, j0, nb, c.rpt, c.shm);
+      else if (c.lds && nb == 16) gj_panel_kernel<X, true, 16><<<nn, GJ_PANEL_THREADS, c.shm, st>>>(dd, j0, nb);
+      else if (c.lds) gj_panel_kernel<X, true, 32><<<nn, GJ_PANEL_THREADS, c.shm, st>>>(dd, j0, nb);
       else gj_panel_kernel<X, false, 32><<<nn, GJ_PANEL_THREADS, 0, st>>>(dd, j0, nb);
       prof.stop(id);
       check_launch("gj_panel");
       id = prof.start(C_GJ_ROWS, 0, rby);
-      gj_rows_kernel<X><<<dim3(cdiv(wmax, 64) + cdiv(nmax, 256), nn), 256, 0, st>>>(dd, j0, nb, cdiv(wmax, 64));
+      gj_rows_kernel<X><<<dim3(cdiv(wmax, 64) + cdiv(rmax, 256), nn), 256, 0, st>>>(dd, j0, nb, cdiv(wmax, 64));
       prof.stop(id);
       check_launch("gj_rows");
       run_gemm<X>(upd[pi], m1, p1, C_GJ_UPDATE);
+    }
+  }
+
+  // In-place [M_ii | M_ib] -> [M_ii^{-1} | M_ii^{-1} M_ib] for a batch. Blocks of
+  // more than kGjBlockMin rows take the pivot columns in blocks of wo: each block
+  // is eliminated by the panel sweep on a copy of its columns, then applied to
+  // the other columns with one product of depth wo. block > 0 forces that width.
+  template <class X>
+  void gauss_jordan(std::vector<GjDesc<X>>& ds, Arena& ar, int block = 0) {
+    if (ds.empty()) return;
+    int nmax = 0, wmax = 0;
+    for (auto& g : ds) {
+      g.rows = g.n;
+      g.poff = 0;
+      nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W);
+    }
+    const int sX = (int)sizeof(X);
+    const GjCfg c = gj_config(nmax, sX);
+    const int nb = c.nb;
+    int wo = block > 0 ? std::min(block, GJ_BLOCK_MAX) : (nmax > kGjBlockMin ? kGjBlock : 0);
+    if (wo >= nmax) wo = 0;
+    // scratch per box
+    for (auto& g : ds) {
+      g.pinv = ar.get<X>((size_t)nb * nb);
+      g.csave = ar.get<X>((size_t)g.rows * nb);
+      g.gpanel = c.lds ? nullptr : ar.get<X>((size_t)g.rows * nb);
+      g.mv = ar.get<int>(1 + 4 * (size_t)std::max(nb, wo));
+      if (wo) {
+        g.rbuf = ar.get<X>((size_t)wo * g.W);
+        g.pb = ar.get<X>((size_t)g.rows * wo);
+        g.rp_in = ar.get<int>((size_t)g.rows);
+      } else {
+        g.rbuf = ar.get<X>((size_t)nb * g.W);
+      }
+    }
+    GjDesc<X>* dd = up(ds, ar);
+    if (!wo) {
+      gj_sweep<X>(ds, dd, c, ar);
+      return;
+    }
+    const int nn = (int)ds.size(), nblk = cdiv(nmax, wo);
+    // inner descriptors of every block (the boxes that still have pivot columns
+    // there): the block copy, pivots from row J on, its own row permutation
+    std::vector<GjDesc<X>> inner;
+    std::vector<int> ioff(nblk + 1, 0);
+    std::vector<GemmLaunch> outer;
+    for (int b = 0; b < nblk; ++b) {
+      const int J = b * wo;
+      std::vector<GemmDesc> gd;
+      for (auto& g : ds) {
+        if (J >= g.n) continue;
+        const int wb = std::min(wo, g.n - J);
+        GjDesc<X> h = g;
+        h.M = g.pb;
+        h.n = h.W = wb;
+        h.poff = J;
+        h.rbuf = ar.get<X>((size_t)nb * wb);
+        h.rowperm = g.rp_in;
+        inner.push_back(h);
+        gd.push_back({g.pb, g.rbuf, g.M, g.rows, g.W, wb, g.rows, wb, g.rows, J, J + wb});
+      }
+      ioff[b + 1] = (int)inner.size();
+      outer.push_back(prep_gemm<X>(gd, ar));
+    }
+    GjDesc<X>* di = up(inner, ar);
+    const X p1 = traits<X>::one();
+    for (int b = 0; b < nblk; ++b) {
+      const int J = b * wo;
+      fl();
+      // bytes of the block copy and of the block's pivot rows (read, zeroed, staged)
+      double cby = 0, bby = 0;
+      if (prof.on)
+        for (auto& g : ds) {
+          if (J >= g.n) continue;
+          const double wb = std::min(wo, g.n - J);
+          cby += 2.0 * g.rows * wb * sX;
+          bby += 3.0 * wb * g.W * sX;
+        }
+      int id = prof.start(C_GJ_ROWS, 0, cby);
+      gj_block_copy_kernel<X><<<dim3(std::min(cdiv(nmax * wo, 256), 256), nn), 256, 0, st>>>(dd, J, wo);
+      prof.stop(id);
+      check_launch("gj_block_copy");
+      const std::vector<GjDesc<X>> blk(inner.begin() + ioff[b], inner.begin() + ioff[b + 1]);
+      gj_sweep<X>(blk, di + ioff[b], c, ar);
+      id = prof.start(C_GJ_ROWS, 0, bby);
+      gj_block_moves_kernel<X><<<nn, 256, 0, st>>>(dd, J);
+      check_launch("gj_block_moves");
+      gj_block_rows_kernel<X><<<dim3(cdiv(wmax, GJ_BLOCK_TILE), nn), 256, 0, st>>>(dd, J, wo);
+      prof.stop(id);
+      check_launch("gj_block_rows");
+      run_gemm<X>(outer[b], p1, p1, C_GJ_UPDATE);
     }
   }
 
@@ -1775,7 +1870,8 @@ void debug_gemm(int scalar, int nb, const void* const* A, const void* const* B, 
 }
 
 template <class X>
-void debug_gj_t(int nb, void* const* Mat, const int32_t* n, const int32_t* m, int32_t* singular, hipStream_t st) {
+void debug_gj_t(int nb, void* const* Mat, const int32_t* n, const int32_t* m, int block, int32_t* singular,
+                hipStream_t st) {
   // a throwaway engine instance provides the launch logic
   Plan P;
   P.probs.resize(1);
@@ -1799,7 +1895,7 @@ void debug_gj_t(int nb, void* const* Mat, const int32_t* n, const int32_t* m, in
     g.flag = flags + b;
     ds.push_back(g);
   }
-  eng.template gauss_jordan<X>(ds, ar);
+  eng.template gauss_jordan<X>(ds, ar, block);
   // explicit inverse: undo the pivoted column order through a copy
   if (!ds.empty()) {
     std::vector<X*> outs;
@@ -1825,13 +1921,13 @@ void debug_gj_t(int nb, void* const* Mat, const int32_t* n, const int32_t* m, in
   mark_clean(st);
 }
 
-void debug_gj(int scalar, int nb, void* const* Mat, const int32_t* n, const int32_t* m, int32_t* singular,
-              hipStream_t st) {
+void debug_gj(int scalar, int nb, void* const* Mat, const int32_t* n, const int32_t* m, int block,
+              int32_t* singular, hipStream_t st) {
   switch (scalar) {
-    case 0: debug_gj_t<float>(nb, Mat, n, m, singular, st); break;
-    case 1: debug_gj_t<double>(nb, Mat, n, m, singular, st); break;
-    case 2: debug_gj_t<cf>(nb, Mat, n, m, singular, st); break;
-    case 3: debug_gj_t<cd>(nb, Mat, n, m, singular, st); break;
+    case 0: debug_gj_t<float>(nb, Mat, n, m, block, singular, st); break;
+    case 1: debug_gj_t<double>(nb, Mat, n, m, block, singular, st); break;
+    case 2: debug_gj_t<cf>(nb, Mat, n, m, block, singular, st); break;
+    case 3: debug_gj_t<cd>(nb, Mat, n, m, block, singular, st); break;
     default: throw Error(HSS_EINVAL, "unknown scalar code");
   }
 }

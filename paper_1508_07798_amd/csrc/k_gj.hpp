@@ -26,15 +26,21 @@
 namespace hss {
 
 template <class T> struct GjDesc {
-  T* M;          // n x W, ld = n
-  int n, W;
+  T* M;          // rows x W, ld = rows
+  int n, W;      // n pivot columns (0 .. n-1); their pivot rows are poff .. poff + n - 1
+  int rows, poff;
   T* pinv;       // nb x nb scratch
-  T* csave;      // n x nb scratch
-  T* rbuf;       // nb x W scratch
-  T* gpanel;     // (n x nb) scratch when the panel does not fit in LDS
+  T* csave;      // rows x nb scratch
+  T* rbuf;       // nb x W scratch (wo x W for a block)
+  T* gpanel;     // (rows x nb) scratch when the panel does not fit in LDS
   int* flag;     // set to 1 on an exactly zero pivot
-  int* mv;       // [1 + 4 nb] net row movement of the current panel: count, then (dst, src) pairs
-  int* rowperm;  // [n] net row permutation: original row now at each position
+  int* mv;       // [1 + 4 max(nb, wo)] net row movement of the current panel or block:
+                 // count, then (dst, src) pairs
+  int* rowperm;  // [rows] net row permutation: original row now at each position
+  // second-level blocking: copy of the current block of wo columns (rows x wo)
+  // and the row permutation of its elimination
+  T* pb;
+  int* rp_in;
 };
 
 template <class R> struct RedPair {
@@ -180,7 +186,8 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc
   const GjDesc<T> g = descs[blockIdx.x];
   if (j0 >= g.n) return;
   const int w = min(nb, g.n - j0);
-  const int Rr = g.n - j0;
+  const int base = g.poff + j0;  // first candidate row
+  const int Rr = g.rows - base;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* P = LDS ? (T*)smem_raw : g.gpanel;
   __shared__ R red_v[2][NW];
@@ -194,7 +201,7 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int idx = idx0 + u * NT;
-      v[u] = sel(idx < Rr * w, g.M[(j0 + idx % Rr) + (size_t)(j0 + idx / Rr) * g.n], traits<T>::zero());
+      v[u] = sel(idx < Rr * w, g.M[(base + idx % Rr) + (size_t)(j0 + idx / Rr) * g.rows], traits<T>::zero());
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -313,7 +320,8 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_reg_kernel(const Gj
   const GjDesc<T> g = descs[blockIdx.x];
   if (j0 >= g.n) return;
   const int w = min(nb, g.n - j0);
-  const int Rr = g.n - j0;
+  const int base = g.poff + j0;  // first candidate row
+  const int Rr = g.rows - base;
   __shared__ RedPair<R> s_red[2][NW];
   __shared__ int s_pphys[NB];
   __shared__ T s_lu[NB][NB + 1];  // packed L\U row of the pivot of column c, in order
@@ -326,7 +334,7 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_reg_kernel(const Gj
     const int r = tid + t * NT;
     static_for<0, NB>([&](auto ci) {
       constexpr int cc = decltype(ci)::value;
-      const V v = (r < Rr && cc < w) ? g.M[(j0 + r) + (size_t)(j0 + cc) * g.n] : traits<T>::zero();
+      const V v = (r < Rr && cc < w) ? g.M[(base + r) + (size_t)(j0 + cc) * g.rows] : traits<T>::zero();
       re[t][cc] = traits<T>::re(v);
       im[t][cc] = traits<T>::im(v);
     });
@@ -482,6 +490,7 @@ __global__ __launch_bounds__(256) void gj_rows_kernel(const GjDesc<T>* __restric
   const GjDesc<T> g = descs[blockIdx.y];
   if (j0 >= g.n) return;
   const int w = min(nb, g.n - j0);
+  const int base = g.poff + j0;  // pivot row of panel column 0
   const int tid = threadIdx.x;
   __shared__ int s_mv[2 * 64];
   const int nm = g.mv[0];
@@ -489,34 +498,34 @@ __global__ __launch_bounds__(256) void gj_rows_kernel(const GjDesc<T>* __restric
   if ((int)blockIdx.x >= ntx) {
     // ---- row block: csave rows [r0, r0 + 256)
     const int r0 = ((int)blockIdx.x - ntx) * 256;
-    if (r0 >= g.n) return;
+    if (r0 >= g.rows) return;
     __shared__ int s_src[256];
     s_src[tid] = -1;
     __syncthreads();
     if (tid < nm) {
-      const int dst = j0 + s_mv[2 * tid];
-      if (dst >= r0 && dst < r0 + 256) s_src[dst - r0] = j0 + s_mv[2 * tid + 1];
+      const int dst = base + s_mv[2 * tid];
+      if (dst >= r0 && dst < r0 + 256) s_src[dst - r0] = base + s_mv[2 * tid + 1];
     }
     __syncthreads();
     const int r = r0 + tid;
-    if (r >= g.n) return;
-    const bool pivrow = r >= j0 && r < j0 + w;
+    if (r >= g.rows) return;
+    const bool pivrow = r >= base && r < base + w;
     const int src = s_src[tid] >= 0 ? s_src[tid] : r;
     constexpr int U = 8;
     for (int cb = 0; cb < w; cb += U) {
       R vr[U], vi[U];
       static_for<0, U>([&](auto uu) {
         constexpr int u = decltype(uu)::value;
-        const T x = (cb + u < w && !pivrow) ? g.M[src + (size_t)(j0 + cb + u) * g.n] : traits<T>::zero();
+        const T x = (cb + u < w && !pivrow) ? g.M[src + (size_t)(j0 + cb + u) * g.rows] : traits<T>::zero();
         vr[u] = traits<T>::re(x);
         vi[u] = traits<T>::im(x);
       });
       static_for<0, U>([&](auto uu) {
         constexpr int u = decltype(uu)::value;
         if (cb + u < w) {
-          const T x = pivrow ? (r - j0 == cb + u ? traits<T>::mk(-1.0, 0.0) : traits<T>::zero())
+          const T x = pivrow ? (r - base == cb + u ? traits<T>::mk(-1.0, 0.0) : traits<T>::zero())
                              : traits<T>::mk(vr[u], vi[u]);
-          g.csave[r + (size_t)(cb + u) * g.n] = x;
+          g.csave[r + (size_t)(cb + u) * g.rows] = x;
         }
       });
     }
@@ -546,7 +555,7 @@ __global__ __launch_bounds__(256) void gj_rows_kernel(const GjDesc<T>* __restric
       const int e = nm > 0 ? idx % nm : 0;
       const int col = c0 + (nm > 0 ? idx / nm : 0);
       const bool act = idx < tot && (col < j0 || col >= j0 + w);
-      const T x = act ? g.M[(j0 + s_mv[2 * e + 1]) + (size_t)col * g.n] : traits<T>::zero();
+      const T x = act ? g.M[(base + s_mv[2 * e + 1]) + (size_t)col * g.rows] : traits<T>::zero();
       vr[k] = traits<T>::re(x);
       vi[k] = traits<T>::im(x);
     });
@@ -557,22 +566,22 @@ __global__ __launch_bounds__(256) void gj_rows_kernel(const GjDesc<T>* __restric
       const int e = nm > 0 ? idx % nm : 0;
       const int col = c0 + (nm > 0 ? idx / nm : 0);
       if (idx < tot && (col < j0 || col >= j0 + w))
-        g.M[(j0 + s_mv[2 * e]) + (size_t)col * g.n] = traits<T>::mk(vr[k], vi[k]);
+        g.M[(base + s_mv[2 * e]) + (size_t)col * g.rows] = traits<T>::mk(vr[k], vi[k]);
     });
     if (g.rowperm && blockIdx.x == 0) {
       if (j0 == 0)
-        for (int i = tid; i < g.n; i += 256) g.rowperm[i] = i;
+        for (int i = tid; i < g.rows; i += 256) g.rowperm[i] = i;
       __syncthreads();
-      const int rp = tid < nm ? g.rowperm[j0 + s_mv[2 * tid + 1]] : 0;
+      const int rp = tid < nm ? g.rowperm[base + s_mv[2 * tid + 1]] : 0;
       __syncthreads();
-      if (tid < nm) g.rowperm[j0 + s_mv[2 * tid]] = rp;
+      if (tid < nm) g.rowperm[base + s_mv[2 * tid]] = rp;
     }
   }
   __syncthreads();
   // 2. stage the pivot-row segment, then R' = Pinv * segment; zero the pivot rows
   for (int idx = tid; idx < w * cw; idx += 256) {
     const int i = idx % w, c = idx / w;
-    s_seg[i][c] = g.M[(j0 + i) + (size_t)(c0 + c) * g.n];
+    s_seg[i][c] = g.M[(base + i) + (size_t)(c0 + c) * g.rows];
   }
   __syncthreads();
   for (int idx = tid; idx < w * cw; idx += 256) {
@@ -584,9 +593,125 @@ __global__ __launch_bounds__(256) void gj_rows_kernel(const GjDesc<T>* __restric
     } else {
       v = traits<T>::zero();
       for (int k = 0; k < w; ++k) v = v + sc_mul(s_pinv[i + k * w], s_seg[k][c]);
-      g.M[(j0 + i) + (size_t)gc * g.n] = traits<T>::zero();
+      g.M[(base + i) + (size_t)gc * g.rows] = traits<T>::zero();
     }
     g.rbuf[i + (size_t)gc * w] = v;
+  }
+}
+
+// ------------------------------------------------------------- second-level blocking
+// For large blocks the pivot columns are taken in blocks of wo (64): the block's
+// columns of M (all rows) are copied to pb and eliminated there with the panel
+// kernels above (pivot rows from poff = J on); then the block's net row movement
+// and one product M += pb * rbuf apply the whole block to the other columns. In
+// pb the pivot rows end up holding the inverse of the pivot block and the other
+// rows -A21 A11^{-1}, so with the pivot rows of M moved into rbuf (and zeroed in
+// M) the product is exactly the block's Gauss-Jordan update; the identity in
+// rbuf's block columns (beta = 0 there) writes pb back into M.
+
+constexpr int GJ_BLOCK_MAX = 128;  // widest block (2 GJ_BLOCK_MAX <= 256 moved rows)
+constexpr int GJ_BLOCK_TILE = 16;  // columns per workgroup of gj_block_rows
+
+// pb = M(:, J : J + wb); grid (chunks, box)
+template <class T>
+__global__ __launch_bounds__(256) void gj_block_copy_kernel(const GjDesc<T>* __restrict__ descs, int J, int wo) {
+  const GjDesc<T> g = descs[blockIdx.y];
+  if (J >= g.n) return;
+  const int wb = min(wo, g.n - J);
+  const int64_t tot = (int64_t)g.rows * wb;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
+    g.pb[e] = g.M[(e % g.rows) + (size_t)(J + e / g.rows) * g.rows];
+}
+
+// The block's net row movement from its row permutation rp_in (positions >= J):
+// (dst, src) pairs relative to J into mv, and the matrix's row permutation
+// updated with them (initialised at J = 0). One workgroup per box; a block of wb
+// pivot columns moves at most 2 wb rows.
+template <class T>
+__global__ __launch_bounds__(256) void gj_block_moves_kernel(const GjDesc<T>* __restrict__ descs, int J) {
+  const GjDesc<T> g = descs[blockIdx.x];
+  if (J >= g.n) return;
+  __shared__ int s_cnt;
+  __shared__ int s_dst[2 * GJ_BLOCK_MAX], s_src[2 * GJ_BLOCK_MAX];
+  const int tid = threadIdx.x;
+  if (tid == 0) s_cnt = 0;
+  if (J == 0)
+    for (int i = tid; i < g.rows; i += 256) g.rowperm[i] = i;
+  __syncthreads();
+  for (int i = J + tid; i < g.rows; i += 256) {
+    const int src = g.rp_in[i];
+    if (src != i) {
+      const int k = atomicAdd(&s_cnt, 1);
+      if (k < 2 * GJ_BLOCK_MAX) {
+        s_dst[k] = i;
+        s_src[k] = src;
+      }
+    }
+  }
+  __syncthreads();
+  const int nm = min(s_cnt, 2 * GJ_BLOCK_MAX);
+  const int v = tid < nm ? g.rowperm[s_src[tid]] : 0;
+  __syncthreads();
+  if (tid < nm) {
+    g.rowperm[s_dst[tid]] = v;
+    g.mv[1 + 2 * tid] = s_dst[tid] - J;
+    g.mv[2 + 2 * tid] = s_src[tid] - J;
+  }
+  if (tid == 0) g.mv[0] = nm;
+}
+
+// The block's moves on the columns outside [J, J + wb) (all moved entries of the
+// tile loaded, then stored), then the pivot rows J .. J + wb - 1 of those columns
+// copied to rbuf (wb x W) and zeroed in M; rbuf's block columns get the identity.
+// Grid (GJ_BLOCK_TILE-column tiles, box).
+template <class T>
+__global__ __launch_bounds__(256) void gj_block_rows_kernel(const GjDesc<T>* __restrict__ descs, int J, int wo) {
+  using R = typename traits<T>::real;
+  const GjDesc<T> g = descs[blockIdx.y];
+  if (J >= g.n) return;
+  const int wb = min(wo, g.n - J);
+  const int c0 = blockIdx.x * GJ_BLOCK_TILE;
+  if (c0 >= g.W) return;
+  const int cw = min(GJ_BLOCK_TILE, g.W - c0);
+  const int tid = threadIdx.x;
+  __shared__ int s_mv[4 * GJ_BLOCK_MAX];
+  const int nm = min(g.mv[0], 2 * GJ_BLOCK_MAX);
+  for (int i = tid; i < 2 * nm; i += 256) s_mv[i] = g.mv[1 + i];
+  __syncthreads();
+  {
+    constexpr int PER = 2 * GJ_BLOCK_MAX * GJ_BLOCK_TILE / 256;
+    R vr[PER], vi[PER];
+    const int tot = nm * cw;
+    static_for<0, PER>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      const int idx = tid + k * 256;
+      const int e = nm > 0 ? idx % nm : 0;
+      const int col = c0 + (nm > 0 ? idx / nm : 0);
+      const bool act = idx < tot && (col < J || col >= J + wb);
+      const T x = act ? g.M[(J + s_mv[2 * e + 1]) + (size_t)col * g.rows] : traits<T>::zero();
+      vr[k] = traits<T>::re(x);
+      vi[k] = traits<T>::im(x);
+    });
+    __syncthreads();
+    static_for<0, PER>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      const int idx = tid + k * 256;
+      const int e = nm > 0 ? idx % nm : 0;
+      const int col = c0 + (nm > 0 ? idx / nm : 0);
+      if (idx < tot && (col < J || col >= J + wb))
+        g.M[(J + s_mv[2 * e]) + (size_t)col * g.rows] = traits<T>::mk(vr[k], vi[k]);
+    });
+  }
+  __syncthreads();
+  for (int idx = tid; idx < wb * cw; idx += 256) {
+    const int i = idx % wb, col = c0 + idx / wb;
+    T* mp = g.M + (J + i) + (size_t)col * g.rows;
+    if (col >= J && col < J + wb) {
+      g.rbuf[i + (size_t)col * wb] = col - J == i ? traits<T>::one() : traits<T>::zero();
+    } else {
+      g.rbuf[i + (size_t)col * wb] = *mp;
+      *mp = traits<T>::zero();
+    }
   }
 }
 

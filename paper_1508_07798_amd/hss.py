@@ -336,14 +336,15 @@ def debug_gemm(As, Bs, Cs, alpha=1.0, beta=0.0, stream=None, bf16x3=False):
                             C.c_void_p(_stream_ptr(stream))))
 
 
-def debug_gj(mats, ns, ms, stream=None):
+def debug_gj(mats, ns, ms, block=0, stream=None):
     """In-place blocked Gauss-Jordan on column-major [A | B] blocks (tensors shaped
-    [n + m, n] row-major = the transposed view). Returns the singular flag."""
+    [n + m, n] row-major = the transposed view). block > 0 forces second-level
+    blocks of that many pivot columns. Returns the singular flag."""
     L = lib()
     L.hss_debug_gj.restype = C.c_int
     k = len(mats)
     sing = C.c_int32(0)
     _check(L.hss_debug_gj(_scalar_code(mats[0]), k, (C.c_void_p * k)(*[m.data_ptr() for m in mats]),
-                          (C.c_int32 * k)(*ns), (C.c_int32 * k)(*ms), C.byref(sing),
+                          (C.c_int32 * k)(*ns), (C.c_int32 * k)(*ms), int(block), C.byref(sing),
                           C.c_void_p(_stream_ptr(stream))))
     return sing.value

@@ -70,11 +70,19 @@ def test_batched_gemm_bf16x3():
         assert np.all(np.abs(got - R) <= 4e-5 * Mg + 1e-6), (m, n, k)
 
 
-@pytest.mark.parametrize("name", list(DT))
-def test_batched_gauss_jordan(name):
+GJ_CASES = [(name, 0, ((1, 3), (7, 0), (33, 20), (100, 45), (200, 230))) for name in DT]
+# second-level blocks: forced narrow blocks over ragged sizes, and the automatic
+# choice for blocks above 512 rows (128-column blocks, ragged last block)
+GJ_CASES += [(name, 32, ((1, 3), (7, 0), (33, 20), (100, 45), (200, 230))) for name in DT]
+GJ_CASES += [("float64", 0, ((600, 70), (530, 0), (40, 9))), ("complex64", 0, ((600, 70), (530, 0), (40, 9))),
+             ("float32", 100, ((450, 30), (129, 1)))]
+
+
+@pytest.mark.parametrize("name,block,sizes", GJ_CASES)
+def test_batched_gauss_jordan(name, block, sizes):
     npdt, tdt, tol = DT[name]
+    print(f"gj {name} block={block} sizes={sizes}", flush=True)
     rng = np.random.default_rng(11)
-    sizes = [(1, 3), (7, 0), (33, 20), (100, 45), (200, 230)]
     mats, refs = [], []
     for n, m in sizes:
         # random matrices (pivoting needed) shifted to keep them reasonably conditioned
@@ -85,7 +93,7 @@ def test_batched_gauss_jordan(name):
         A64 = A.astype(np.complex128)
         refs.append((np.linalg.inv(A64), np.linalg.solve(A64, B.astype(np.complex128)) if m else None,
                      np.linalg.cond(A64)))
-    sing = hss.debug_gj(mats, [s[0] for s in sizes], [s[1] for s in sizes])
+    sing = hss.debug_gj(mats, [s[0] for s in sizes], [s[1] for s in sizes], block=block)
     assert sing == 0
     for (n, m), Md, (Ainv, X, cond) in zip(sizes, mats, refs):
         got = Md.cpu().numpy().T
