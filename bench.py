@@ -134,6 +134,8 @@ def main():
                     help="kernel class for the roofline object (default: the dominant one)")
     ap.add_argument("--profile-all", action="store_true", help="print the time of every kernel class")
     ap.add_argument("--no-model", action="store_true", help="plain adaptive ID (no rank model)")
+    ap.add_argument("--markers", action="store_true",
+                    help="spin kernels around the timed steps, to cut a kernel trace to them")
     ap.add_argument("--workload", default="helmholtz_p2_64", choices=sorted(WORKLOADS),
                     help="measured workload (default: the Helmholtz configuration the metric is quoted on)")
     args = ap.parse_args()
@@ -196,13 +198,17 @@ def main():
                 "phases": h.query("phase_ms"), "max_rank": int(h.query("ranks").max()),
                 "attempts": np.asarray(h.query("attempts")), "retries": float(h.query("retries")[0])}
 
-    def timed(prec, steps, warmup, profile, use_model=True):
+    def timed(prec, steps, warmup, profile, use_model=True, markers=False):
         """Each step factors, solves, reads its statistics and frees the handle, so
         that the device memory of one step is reused by the next. HIP events (about
-        10 us of device time per record) time the profiled class in the last step only."""
+        10 us of device time per record) time the profiled class in the last step only.
+        markers: a spin kernel on each side of the timed steps (outside the timed
+        region), so that a kernel trace can be cut to exactly these steps."""
         for _ in range(warmup):
             h, _, _ = step(prec, 0, use_model)
             h.close()
+        if markers:
+            torch.cuda._sleep(1000)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = []
@@ -212,6 +218,9 @@ def main():
             h.close()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
+        if markers:
+            torch.cuda._sleep(1000)
+            torch.cuda.synchronize()
         return ms, out
 
     # one profiled warm-up step names the dominant kernel class (wrapper class gmres excluded)
@@ -222,7 +231,7 @@ def main():
     cls_bit = 1 << (CLASSES.index(dom) + 1)
     # timed steps: HIP events only around the dominant class's launches
     note(f"timing {args.steps} steps ({MIX})")
-    ms, runs = timed(MIX, args.steps, args.warmup, cls_bit)
+    ms, runs = timed(MIX, args.steps, args.warmup, cls_bit, markers=args.markers)
     iters = [r["iters"] for r in runs]
     relres = max(r["relres"] for r in runs)
     tot = runs[-1]["table"][dom]

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhss.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["planner.cpp", "capi.cpp", "engine.hip", "mlp.hip"]
+SOURCES = ["planner.cpp", "capi.cpp", "engine.hip", "mlp.hip", "panel.hip"]
 ARCH = os.environ.get("HSS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -17,6 +17,7 @@
 #include "k_gj.hpp"
 #include "k_hss.hpp"
 #include "k_vec.hpp"
+#include "panel.hpp"
 
 namespace hss {
 
@@ -304,7 +305,7 @@ template <class T> struct Engine : EngineBase {
   // second-level blocking of the Gauss-Jordan elimination: width, and the block size
   // above which it is used
   static constexpr int kGjBlock = 128;
-  static constexpr int kGjBlockMin = 512;
+  static constexpr int kGjBlockMin = 128;
   double tol = 0;
   Prof prof;
   Pinned keep;  // pinned host staging, reused after each sync
@@ -559,14 +560,23 @@ template <class T> struct Engine : EngineBase {
                                  std::to_string(rpt));
   }
 
-  // Panel kernel variant for a batch whose tallest panel has rmax rows.
+  // Panel kernel variant for a batch whose tallest panel has rmax rows: the compact
+  // register-resident kernel where an instantiation holds the rows, else the older
+  // register kernel, else the LDS / global-memory panel kernel.
   struct GjCfg {
     int nb, rpt;
-    bool reg, lds;
+    bool rot, reg, lds;
     size_t shm;
+    PanelShape ps;
   };
-  GjCfg gj_config(int rmax, int sX) const {
+  template <class X> GjCfg gj_config(int rmax) const {
+    const int sX = (int)sizeof(X);
     GjCfg c{};
+    if (panel_rot_config<X>(rmax, c.ps)) {
+      c.rot = true;
+      c.nb = c.ps.nb;
+      return c;
+    }
     // register-resident panel when the tallest panel fits: rows per thread (rpt) and
     // panel width (nb) from a budget of 192 registers for the panel values
     const int words = sX / 4;
@@ -621,7 +631,8 @@ template <class T> struct Engine : EngineBase {
         }
       }
       int id = prof.start(C_GJ_PANEL, pfl, 0);
-      if (c.reg) launch_panel_reg<X>(dd, nn, j0, nb, c.rpt, c.shm);
+      if (c.rot) launch_panel_rot<X>(dd, nn, j0, nb, c.ps, st);
+      else if (c.reg) launch_panel_reg<X>(dd, nn, j0, nb, c.rpt, c.shm);
       else if (c.lds && nb == 16) gj_panel_kernel<X, true, 16><<<nn, GJ_PANEL_THREADS, c.shm, st>>>(dd, j0, nb);
       else if (c.lds) gj_panel_kernel<X, true, 32><<<nn, GJ_PANEL_THREADS, c.shm, st>>>(dd, j0, nb);
       else gj_panel_kernel<X, false, 32><<<nn, GJ_PANEL_THREADS, 0, st>>>(dd, j0, nb);
@@ -649,7 +660,7 @@ template <class T> struct Engine : EngineBase {
       nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W);
     }
     const int sX = (int)sizeof(X);
-    const GjCfg c = gj_config(nmax, sX);
+    const GjCfg c = gj_config<X>(nmax);
     const int nb = c.nb;
     int wo = block > 0 ? std::min(block, GJ_BLOCK_MAX) : (nmax > kGjBlockMin ? kGjBlock : 0);
     if (wo >= nmax) wo = 0;

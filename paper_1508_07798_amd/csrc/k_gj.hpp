@@ -107,7 +107,7 @@ __device__ __forceinline__ void panel_moves(int* mv, const int* pphys, int w) {
 // (forward, then backward substitution), broadcasting every finished entry with
 // readlane. Row entries are read from LDS in batches of 8. A zero diagonal entry
 // leaves its row unscaled (the zero pivot is reported through the flag).
-template <class T, int NB, int LD>
+template <class T, int NB, int LD, int NT = GJ_PANEL_THREADS>
 __device__ __forceinline__ void pivot_block_inverse(const T* lu, int w, T* __restrict__ pinv) {
   using R = typename traits<T>::real;
   const int tid = threadIdx.x, gg = tid >> 5, gl = tid & 31, half = tid & 32;
@@ -122,7 +122,7 @@ __device__ __forceinline__ void pivot_block_inverse(const T* lu, int w, T* __res
     const R b0 = rdlane(traits<T>::im(x), i), b1 = rdlane(traits<T>::im(x), 32 + i);
     return traits<T>::mk(half ? a1 : a0, half ? b1 : b0);
   };
-  for (int j0c = 0; j0c < w; j0c += GJ_PANEL_THREADS / 32) {
+  for (int j0c = 0; j0c < w; j0c += NT / 32) {
     const int j = j0c + gg;
     T x = sel(gl == j, traits<T>::one(), traits<T>::zero());
     static_for<0, NB / 8>([&](auto chi) {
@@ -471,6 +471,346 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_reg_kernel(const Gj
   __syncthreads();
   if (wave == 0) panel_moves(g.mv, s_pphys, w);
   pivot_block_inverse<T, NB, NB + 1>(&s_lu[0][0], w, g.pinv);
+}
+
+// a - b c with four fused multiply-adds for complex operands
+__device__ __forceinline__ float fms4(float a, float b, float c) { return fmaf(-b, c, a); }
+__device__ __forceinline__ double fms4(double a, double b, double c) { return fma(-b, c, a); }
+__device__ __forceinline__ cf fms4(cf a, cf b, cf c) {
+  return {fmaf(-b.x, c.x, fmaf(b.y, c.y, a.x)), fmaf(-b.x, c.y, fmaf(-b.y, c.x, a.y))};
+}
+__device__ __forceinline__ cd fms4(cd a, cd b, cd c) {
+  return {fma(-b.x, c.x, fma(b.y, c.y, a.x)), fma(-b.x, c.y, fma(-b.y, c.x, a.y))};
+}
+// 1 / a for a pivot: hardware reciprocal (about 1 ulp) in single precision,
+// a correctly rounded division in double precision
+__device__ __forceinline__ float pivot_inv(float a) { return __builtin_amdgcn_rcpf(a); }
+__device__ __forceinline__ double pivot_inv(double a) { return 1.0 / a; }
+__device__ __forceinline__ cf pivot_inv(cf a) {
+  const float r = __builtin_amdgcn_rcpf(a.x * a.x + a.y * a.y);
+  return {a.x * r, -a.y * r};
+}
+__device__ __forceinline__ cd pivot_inv(cd a) {
+  const double r = 1.0 / (a.x * a.x + a.y * a.y);
+  return {a.x * r, -a.y * r};
+}
+
+// Wave-wide (value, row) maximum for pivot search: the largest value, then the
+// lowest row index among the lanes holding it; uniform result. Four in-row DPP steps
+// and three cross-row steps through readlane for each of the two reductions.
+template <class R> __device__ __forceinline__ void wave_pivot_max(R& v, int& i) {
+  R m = v;
+  m = fmax(m, dpp_v<0xB1>(m));
+  m = fmax(m, dpp_v<0x4E>(m));
+  m = fmax(m, dpp_v<0x141>(m));
+  m = fmax(m, dpp_v<0x140>(m));
+  m = fmax(fmax(rdlane(m, 0), rdlane(m, 16)), fmax(rdlane(m, 32), rdlane(m, 48)));
+  int k = v == m ? i : 0x7fffffff;
+  k = min(k, dpp_i<0xB1>(k));
+  k = min(k, dpp_i<0x4E>(k));
+  k = min(k, dpp_i<0x141>(k));
+  k = min(k, dpp_i<0x140>(k));
+  k = min(min(rdlane(k, 0), rdlane(k, 16)), min(rdlane(k, 32), rdlane(k, 48)));
+  v = m;
+  i = k;
+}
+
+// Register-resident panel LU with the column loop unrolled at compile time: NT
+// threads, thread tid owns rows tid + t * NT (t < RPT) and keeps their NB columns in
+// registers. Per column: each wave's best candidate (largest modulus, lowest row on
+// ties; a NaN modulus ranks below every number, so a NaN column still yields the
+// lowest free row) goes to LDS with the candidate row itself, one barrier, then
+// every thread reduces the wave partials, reads the pivot row and updates only the
+// columns right of the pivot (compile-time bounds, no branches). Pivots, row
+// movement and Pinv are those of gj_panel_kernel.
+template <class T, int NB, int RPT, int NT>
+__global__ __launch_bounds__(NT) void gj_panel_unr_kernel(const GjDesc<T>* __restrict__ descs, int j0, int nb) {
+  using R = typename traits<T>::real;
+  constexpr bool CPLX = traits<T>::cplx;
+  constexpr int NW = NT / 64;
+  const GjDesc<T> g = descs[blockIdx.x];
+  if (j0 >= g.n) return;
+  const int w = min(nb, g.n - j0);
+  const int base = g.poff + j0;  // first candidate row
+  const int Rr = g.rows - base;  // >= w
+  __shared__ RedPair<R> s_red[2][NW];
+  __shared__ int s_pphys[NB];
+  __shared__ T s_lu[NB][NB + 1];  // packed L\U row of the pivot of column c, in order
+  // candidate pivot row of every wave (real and imaginary parts), double buffered
+  __shared__ R s_cre[2][NW][NB];
+  __shared__ R s_cim[2][NW][CPLX ? NB : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  R re[RPT][NB], im[RPT][NB];
+  // clamped addresses: every load is issued, out-of-range entries are zeroed after
+  static_for<0, RPT>([&](auto tidx) {
+    constexpr int t = decltype(tidx)::value;
+    const int r = tid + t * NT;
+    const int rr = min(r, Rr - 1);
+    static_for<0, NB>([&](auto ci) {
+      constexpr int cc = decltype(ci)::value;
+      const T v = g.M[(base + rr) + (size_t)(j0 + min(cc, w - 1)) * g.rows];
+      const bool keep = r < Rr && cc < w;
+      re[t][cc] = keep ? traits<T>::re(v) : R(0);
+      im[t][cc] = keep ? traits<T>::im(v) : R(0);
+    });
+  });
+  unsigned done = 0;  // bit t: own row t is a pivot row
+  static_for<0, NB>([&](auto cidx) {
+    constexpr int c = decltype(cidx)::value;
+    if (c >= w) return;
+    constexpr int buf = c & 1;
+    R best = -1;
+    int bi = 0x7fffffff;
+    static_for<0, RPT>([&](auto tidx) {
+      constexpr int t = decltype(tidx)::value;
+      const int r = tid + t * NT;
+      R v = re[t][c] * re[t][c] + im[t][c] * im[t][c];
+      v = v == v ? v : R(-0.5);
+      // rows grow with t, so a strict comparison keeps the lowest row on ties
+      const bool take = (r < Rr) & !((done >> t) & 1u) & (v > best);
+      best = take ? v : best;
+      bi = take ? r : bi;
+    });
+    const int mine = bi;
+    wave_pivot_max(best, bi);
+    if (lane == 0) {
+      s_red[buf][wave].v = best;
+      s_red[buf][wave].i = bi;
+    }
+    if (bi == mine && bi < Rr) {
+      // this lane holds the wave's candidate: publish its row (one branch per row
+      // slot, so that the register reads keep constant indices)
+      static_for<0, RPT>([&](auto tidx) {
+        constexpr int t = decltype(tidx)::value;
+        if (bi == tid + t * NT) {
+          static_for<0, NB>([&](auto ci) {
+            constexpr int cc = decltype(ci)::value;
+            s_cre[buf][wave][cc] = re[t][cc];
+            if constexpr (CPLX) s_cim[buf][wave][cc] = im[t][cc];
+          });
+        }
+      });
+    }
+    __syncthreads();
+    RedPair<R> pr[NW];
+    static_for<0, NW>([&](auto kk) { pr[decltype(kk)::value] = s_red[buf][decltype(kk)::value]; });
+    R bv = pr[0].v;
+    int p = pr[0].i;
+    static_for<1, NW>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      const bool take = (pr[k].v > bv) | ((pr[k].v == bv) & (pr[k].i < p));
+      bv = take ? pr[k].v : bv;
+      p = take ? pr[k].i : p;
+    });
+    const int pw_ = (p % NT) >> 6;
+    const R* pre = &s_cre[buf][pw_][0];
+    const R* pim = &s_cim[buf][CPLX ? pw_ : 0][0];
+    if ((p % NT) == tid) done |= 1u << (p / NT);
+    if (tid < NB) s_lu[c][tid] = traits<T>::mk(pre[tid], CPLX ? pim[tid] : R(0));
+    if (tid == 0) s_pphys[c] = p;
+    const T pv = traits<T>::mk(pre[c], CPLX ? pim[c] : R(0));
+    const bool zero = traits<T>::abs2(pv) == 0;
+    if (zero && tid == 0) *g.flag = 1;
+    const T inv = zero ? traits<T>::zero() : pivot_inv(pv);
+    T l[RPT];
+    static_for<0, RPT>([&](auto tidx) {
+      constexpr int t = decltype(tidx)::value;
+      l[t] = sc_mul(traits<T>::mk(re[t][c], im[t][c]), inv);
+      re[t][c] = traits<T>::re(l[t]);
+      im[t][c] = traits<T>::im(l[t]);
+    });
+    static_for<c + 1, NB>([&](auto ci) {
+      constexpr int cc = decltype(ci)::value;
+      const T pw = traits<T>::mk(pre[cc], CPLX ? pim[cc] : R(0));
+      static_for<0, RPT>([&](auto tidx) {
+        constexpr int t = decltype(tidx)::value;
+        const T nv = fms4(traits<T>::mk(re[t][cc], im[t][cc]), l[t], pw);
+        re[t][cc] = traits<T>::re(nv);
+        im[t][cc] = traits<T>::im(nv);
+      });
+    });
+  });
+  __syncthreads();
+  if (wave == 0) panel_moves(g.mv, s_pphys, w);
+  pivot_block_inverse<T, NB, NB + 1, NT>(&s_lu[0][0], w, g.pinv);
+}
+
+// Pinv = A11^{-1} for the pivot block of a panel, A11(c, :) = the original panel
+// row of the pivot of column c (rows in pivot order), by Gauss-Jordan elimination
+// without further interchanges: its pivots are those of the panel's LU. Every
+// thread keeps EPT elements of the w x w block in registers; per step one barrier
+// (the pivot row and column go through double-buffered LDS).
+template <class T, int NB, int NT>
+__device__ __forceinline__ void pivot_block_gj(const GjDesc<T>& g, int j0, int base, int w, const int* pphys,
+                                               T (*s_row)[NB], T (*s_col)[NB]) {
+  constexpr int EPT = (NB * NB + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  T a[EPT];
+  int ei[EPT], ej[EPT];
+  static_for<0, EPT>([&](auto qq) {
+    constexpr int q = decltype(qq)::value;
+    const int e = tid + q * NT;
+    ei[q] = e % NB;
+    ej[q] = e / NB;
+    const bool in = ei[q] < w && ej[q] < w;
+    a[q] = in ? g.M[(base + pphys[in ? ei[q] : 0]) + (size_t)(j0 + (in ? ej[q] : 0)) * g.rows] : traits<T>::zero();
+  });
+  for (int k = 0; k < w; ++k) {
+    const int b = k & 1;
+    static_for<0, EPT>([&](auto qq) {
+      constexpr int q = decltype(qq)::value;
+      if (ei[q] == k && ej[q] < w) s_row[b][ej[q]] = a[q];
+      if (ej[q] == k && ei[q] < w) s_col[b][ei[q]] = a[q];
+    });
+    __syncthreads();
+    const T p = s_row[b][k];
+    const T ip = traits<T>::abs2(p) == 0 ? traits<T>::zero() : pivot_inv(p);
+    static_for<0, EPT>([&](auto qq) {
+      constexpr int q = decltype(qq)::value;
+      const int i = ei[q], j = ej[q];
+      if (i < w && j < w) {
+        const T rk = sc_mul(s_row[b][j], ip);  // scaled pivot row entry
+        const T cik = s_col[b][i];
+        T v;
+        if (i == k) v = j == k ? ip : rk;
+        else v = j == k ? -sc_mul(cik, ip) : fms4(a[q], cik, rk);
+        a[q] = v;
+      }
+    });
+  }
+  static_for<0, EPT>([&](auto qq) {
+    constexpr int q = decltype(qq)::value;
+    if (ei[q] < w && ej[q] < w) g.pinv[ei[q] + ej[q] * w] = a[q];
+  });
+}
+
+// Register-resident panel LU with a compact column loop: NT threads, thread tid
+// owns rows tid + t * NT (t < RPT) and keeps, in slots 0 .. NB - 1, the values of
+// columns c .. c + NB - 1 of its rows (column c of the loop in slot 0). The update of
+// column c shifts every row left by one slot in the same fused multiply-adds, so
+// every register index is a compile-time constant and the loop body has no branch
+// on c. Only the pivots are needed from the panel; Pinv is recomputed from the
+// original pivot rows at the end (pivot_block_gj). Per column: each wave's best
+// candidate (largest modulus, lowest row on ties; a NaN modulus ranks below every
+// number) and its row go to LDS, one barrier, then every thread reduces the wave
+// partials and updates its rows with the pivot row.
+template <class T, int NB, int RPT, int NT>
+__global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __restrict__ descs, int j0, int nb) {
+  using R = typename traits<T>::real;
+  constexpr bool CPLX = traits<T>::cplx;
+  constexpr int NW = NT / 64;
+  const GjDesc<T> g = descs[blockIdx.x];
+  if (j0 >= g.n) return;
+  const int w = min(nb, g.n - j0);
+  const int base = g.poff + j0;  // first candidate row
+  const int Rr = g.rows - base;  // >= w
+  __shared__ RedPair<R> s_red[2][NW];
+  __shared__ int s_pphys[NB];
+  __shared__ R s_cre[2][NW][NB];
+  __shared__ R s_cim[2][NW][CPLX ? NB : 1];
+  __shared__ T s_row[2][NB], s_col[2][NB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  R re[RPT][NB], im[RPT][NB];
+  static_for<0, RPT>([&](auto tidx) {
+    constexpr int t = decltype(tidx)::value;
+    const int r = tid + t * NT;
+    const int rr = min(r, Rr - 1);
+    static_for<0, NB>([&](auto ci) {
+      constexpr int cc = decltype(ci)::value;
+      const T v = g.M[(base + rr) + (size_t)(j0 + min(cc, w - 1)) * g.rows];
+      const bool keep = r < Rr && cc < w;
+      re[t][cc] = keep ? traits<T>::re(v) : R(0);
+      im[t][cc] = keep ? traits<T>::im(v) : R(0);
+    });
+  });
+  unsigned done = 0;  // bit t: own row t is a pivot row
+  for (int c = 0; c < w; ++c) {
+    const int buf = c & 1;
+    R best = -1;
+    int bi = 0x7fffffff;
+    static_for<0, RPT>([&](auto tidx) {
+      constexpr int t = decltype(tidx)::value;
+      const int r = tid + t * NT;
+      R v = re[t][0] * re[t][0] + im[t][0] * im[t][0];
+      v = v == v ? v : R(-0.5);
+      // rows grow with t, so a strict comparison keeps the lowest row on ties
+      const bool take = (r < Rr) & !((done >> t) & 1u) & (v > best);
+      best = take ? v : best;
+      bi = take ? r : bi;
+    });
+    const int mine = bi;
+    wave_pivot_max(best, bi);
+    if (lane == 0) {
+      s_red[buf][wave].v = best;
+      s_red[buf][wave].i = bi;
+    }
+    if (bi == mine && bi < Rr) {
+      // this lane holds the wave's candidate: publish its row (one branch per row
+      // slot, so that the register reads keep constant indices)
+      static_for<0, RPT>([&](auto tidx) {
+        constexpr int t = decltype(tidx)::value;
+        if (bi == tid + t * NT) {
+          static_for<0, NB>([&](auto ci) {
+            constexpr int cc = decltype(ci)::value;
+            s_cre[buf][wave][cc] = re[t][cc];
+            if constexpr (CPLX) s_cim[buf][wave][cc] = im[t][cc];
+          });
+        }
+      });
+    }
+    __syncthreads();
+    RedPair<R> pr[NW];
+    static_for<0, NW>([&](auto kk) { pr[decltype(kk)::value] = s_red[buf][decltype(kk)::value]; });
+    R bv = pr[0].v;
+    int p = pr[0].i;
+    static_for<1, NW>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      const bool take = (pr[k].v > bv) | ((pr[k].v == bv) & (pr[k].i < p));
+      bv = take ? pr[k].v : bv;
+      p = take ? pr[k].i : p;
+    });
+    const int pwv = (p % NT) >> 6;
+    const R* pre = &s_cre[buf][pwv][0];
+    const R* pim = &s_cim[buf][CPLX ? pwv : 0][0];
+    if ((p % NT) == tid) done |= 1u << (p / NT);
+    if (tid == 0) s_pphys[c] = p;
+    // the whole pivot row into registers at once: one LDS round trip per column
+    R prr[NB], pri[NB];
+    static_for<0, NB>([&](auto ci) {
+      constexpr int k = decltype(ci)::value;
+      prr[k] = pre[k];
+      pri[k] = CPLX ? pim[k] : R(0);
+    });
+    __builtin_amdgcn_sched_barrier(0);
+    const T pv = traits<T>::mk(prr[0], pri[0]);
+    const bool zero = traits<T>::abs2(pv) == 0;
+    if (zero && tid == 0) *g.flag = 1;
+    const T inv = zero ? traits<T>::zero() : pivot_inv(pv);
+    T l[RPT];
+    static_for<0, RPT>([&](auto tidx) {
+      constexpr int t = decltype(tidx)::value;
+      l[t] = sc_mul(traits<T>::mk(re[t][0], im[t][0]), inv);
+    });
+    // update and shift: slot k takes column c + 1 + k
+    static_for<0, NB - 1>([&](auto ci) {
+      constexpr int k = decltype(ci)::value;
+      const T pw = traits<T>::mk(prr[k + 1], pri[k + 1]);
+      static_for<0, RPT>([&](auto tidx) {
+        constexpr int t = decltype(tidx)::value;
+        const T nv = fms4(traits<T>::mk(re[t][k + 1], im[t][k + 1]), l[t], pw);
+        re[t][k] = traits<T>::re(nv);
+        im[t][k] = traits<T>::im(nv);
+      });
+    });
+    static_for<0, RPT>([&](auto tidx) {
+      constexpr int t = decltype(tidx)::value;
+      re[t][NB - 1] = R(0);
+      im[t][NB - 1] = R(0);
+    });
+  }
+  __syncthreads();
+  if (wave == 0) panel_moves(g.mv, s_pphys, w);
+  pivot_block_gj<T, NB, NT>(g, j0, base, w, s_pphys, s_row, s_col);
 }
 
 // Row interchanges, pivot-row scaling and the saved panel columns; grid
