@@ -22,6 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def read_counter(d, counter):
+    """(kernel, value) per dispatch in dispatch order. When the run holds bench.py's
+    marker kernels (--markers), the dispatches between the first two markers are kept,
+    plus the calibration copy, which bench.py runs before anything else."""
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not files:
         raise SystemExit(f"no counter_collection.csv under {d}")
@@ -29,13 +32,20 @@ def read_counter(d, counter):
     for fn in files:
         with open(fn) as f:
             for r in csv.DictReader(f):
-                if r.get("Counter_Name") == counter:
-                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
-    return rows
+                if r.get("Counter_Name") == counter or "spin_kernel" in r.get("Kernel_Name", ""):
+                    rows.append((int(r.get("Dispatch_Id", 0) or 0), r["Kernel_Name"],
+                                 float(r["Counter_Value"]) if r.get("Counter_Name") == counter else None))
+    rows.sort(key=lambda x: x[0])
+    marks = [i for i, r in enumerate(rows) if "spin_kernel" in r[1]]
+    copies = [(n, v) for _, n, v in rows if v is not None and ("copyBuffer" in n or "copy" in n.lower())]
+    if len(marks) >= 2:
+        rows = rows[marks[0] + 1:marks[1]]
+    sel = [(n, v) for _, n, v in rows if v is not None and "spin_kernel" not in n]
+    return copies + sel
 
 
 def scaled(rows, regex, copy_mib):
-    copies = [v for name, v in rows if "copyBuffer" in name or "copy" in name.lower()]
+    copies = [v for name, v in rows if "copyBuffer" in name or "copy" in name.lower()]  # calibration
     if not copies:
         raise SystemExit("no copy dispatch found for the calibration")
     ref = max(copies)
@@ -57,6 +67,7 @@ def main():
     ap.add_argument("--json", required=True)
     ap.add_argument("--summary", required=True)
     ap.add_argument("--command", default="")
+    ap.add_argument("--workload", default="helmholtz_p2_64")
     a = ap.parse_args()
     fb, nf, fref, fscale = scaled(read_counter(a.fetch, "FETCH_SIZE"), a.regex, a.copy_mib)
     wb, nw, wref, wscale = scaled(read_counter(a.write, "WRITE_SIZE"), a.regex, a.copy_mib)
@@ -71,7 +82,7 @@ def main():
     with open(a.json, "w") as f:
         json.dump(out, f, indent=1)
     with open(a.summary, "w") as f:
-        f.write(f"# HBM traffic of `{a.cls}` kernels ({a.regex}), helmholtz_p2_64\n\n")
+        f.write(f"# HBM traffic of `{a.cls}` kernels ({a.regex}), {a.workload}\n\n")
         f.write(f"Command:\n\n```\n{a.command}\n```\n\n")
         f.write(f"* dispatches counted: {nf} (FETCH_SIZE), {nw} (WRITE_SIZE)\n")
         f.write(f"* copy calibration: {a.copy_mib} MiB copy reads FETCH_SIZE {fref:.0f} KiB, "
