@@ -4,8 +4,10 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/hss.h"
 #include "common.hpp"
@@ -68,6 +70,71 @@ void ensure_device() {
 }
 }  // namespace
 
+namespace {
+// The planner's output depends on the structure only (block sparsity, q, tree), not
+// on the values. The last plan is kept with a copy of the structure it came from, so
+// that factorizations of new values on the same mesh and tree (a parameter sweep, a
+// sequence of right-hand sides with new coefficients) skip the planner. The copy is
+// compared element by element, never through a hash.
+struct PlanCache {
+  std::mutex mu;
+  bool valid = false;
+  std::vector<int32_t> key;
+  hss::Plan plan;
+};
+PlanCache& plan_cache() {
+  static PlanCache c;
+  return c;
+}
+// Visit the structure arrays in a fixed order (the caller has checked the pointers).
+template <class F> void visit_structure(int nprob, const hss_block_op_t* A, const hss_tree_t* T, F&& f) {
+  const int32_t head[1] = {nprob};
+  f(head, 1);
+  for (int p = 0; p < nprob; ++p) {
+    const hss_block_op_t& a = A[p];
+    const hss_tree_t& t = T[p];
+    const int32_t sz[4] = {a.n_el, a.q, (int32_t)a.dtype, t.n_leaves};
+    f(sz, 4);
+    f(a.row_ptr, (size_t)a.n_el + 1);
+    f(a.col_idx, (size_t)a.row_ptr[a.n_el]);
+    f(t.leaf_node, (size_t)t.n_leaves);
+    f(t.leaf_ptr, (size_t)t.n_leaves + 1);
+    f(t.leaf_elems, (size_t)a.n_el);
+    f(t.elem_xy, 2 * (size_t)a.n_el);
+  }
+}
+hss::Plan plan_for(int nprob, const hss_block_op_t* A, const hss_tree_t* T) {
+  bool ok = nprob >= 1 && A && T;
+  for (int p = 0; ok && p < nprob; ++p)
+    ok = A[p].n_el >= 2 && A[p].row_ptr && A[p].col_idx && A[p].vals && T[p].n_leaves >= 2 && T[p].leaf_node &&
+         T[p].leaf_ptr && T[p].leaf_elems && T[p].elem_xy && A[p].row_ptr[A[p].n_el] >= 0 &&
+         T[p].leaf_ptr[T[p].n_leaves] == A[p].n_el;
+  if (!ok) return hss::make_plan(nprob, A, T);  // reports the error
+  PlanCache& c = plan_cache();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.valid) {
+      size_t off = 0;
+      bool same = true;
+      visit_structure(nprob, A, T, [&](const int32_t* v, size_t n) {
+        if (!same) return;
+        same = off + n <= c.key.size() && std::memcmp(c.key.data() + off, v, n * sizeof(int32_t)) == 0;
+        off += n;
+      });
+      if (same && off == c.key.size()) return c.plan;
+    }
+  }
+  hss::Plan plan = hss::make_plan(nprob, A, T);
+  std::vector<int32_t> key;
+  visit_structure(nprob, A, T, [&](const int32_t* v, size_t n) { key.insert(key.end(), v, v + n); });
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.key = std::move(key);
+  c.plan = plan;
+  c.valid = true;
+  return plan;
+}
+}  // namespace
+
 extern "C" {
 
 void hss_default_opts(hss_opts_t* o) {
@@ -99,7 +166,7 @@ hss_status_t hss_factor_batched(int32_t nprob, const hss_block_op_t* A, const hs
     if (opts.p_os < 1 || opts.l0 < 1 || opts.max_attempts < 1) return fail(HSS_EINVAL, "bad options");
     if (opts.prec != HSS_PREC_FP64 && opts.prec != HSS_PREC_FP32 && opts.prec != HSS_PREC_BF16)
       return fail(HSS_EINVAL, "unknown precision");
-    hss::Plan plan = hss::make_plan(nprob, A, T);
+    hss::Plan plan = plan_for(nprob, A, T);
     for (int p = 0; p < nprob; ++p) check_finite_host(A[p]);
     ensure_device();
     std::unique_ptr<hss_ctx> h(new hss_ctx);

@@ -224,3 +224,28 @@ def test_singular_block_is_reported():
     with pytest.raises(hss.HssError) as ex:
         hss.factor(op, tree, 1e-6, prec="fp64")
     assert ex.value.status == hss.HSS_ESINGULAR
+
+
+def test_plan_reuse_for_new_values():
+    """Factorizations on the same structure reuse the planner's output; a factorization
+    after a structure change plans afresh. Both give the same preconditioner."""
+    P = configs.make("poisson_p1_16", n=16)
+    Q = configs.make("poisson_p1_16", n=12)
+    print("plan reuse", flush=True)
+    op2 = sipg.assemble(16, 1)
+    op2.vals = P.op.vals * 2.0
+    x = np.random.default_rng(3).standard_normal(P.op.ndof)
+    hq = hss.factor(Q.op, Q.tree, Q.tol, prec="fp64", seed=Q.seed)  # another structure
+    hq.close()
+    h1 = hss.factor(op2, P.tree, P.tol, prec="fp64", seed=P.seed)   # planned afresh
+    y1 = h1.apply(_t(x)).cpu().numpy()
+    h1.close()
+    h0 = hss.factor(P.op, P.tree, P.tol, prec="fp64", seed=P.seed)  # same structure
+    y0 = h0.apply(_t(x)).cpu().numpy()
+    h0.close()
+    h2 = hss.factor(op2, P.tree, P.tol, prec="fp64", seed=P.seed)   # same structure again
+    y2 = h2.apply(_t(x)).cpu().numpy()
+    h2.close()
+    assert np.array_equal(y1, y2)
+    # A -> 2A halves the preconditioner
+    assert np.linalg.norm(2.0 * y2 - y0) <= 1e-10 * np.linalg.norm(y0)
