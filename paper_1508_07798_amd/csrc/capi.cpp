@@ -78,9 +78,8 @@ namespace {
 // compared element by element, never through a hash.
 struct PlanCache {
   std::mutex mu;
-  bool valid = false;
   std::vector<int32_t> key;
-  hss::Plan plan;
+  std::shared_ptr<const hss::Plan> plan;  // shared with the engines built on it
 };
 PlanCache& plan_cache() {
   static PlanCache c;
@@ -103,17 +102,17 @@ template <class F> void visit_structure(int nprob, const hss_block_op_t* A, cons
     f(t.elem_xy, 2 * (size_t)a.n_el);
   }
 }
-hss::Plan plan_for(int nprob, const hss_block_op_t* A, const hss_tree_t* T) {
+std::shared_ptr<const hss::Plan> plan_for(int nprob, const hss_block_op_t* A, const hss_tree_t* T) {
   bool ok = nprob >= 1 && A && T;
   for (int p = 0; ok && p < nprob; ++p)
     ok = A[p].n_el >= 2 && A[p].row_ptr && A[p].col_idx && A[p].vals && T[p].n_leaves >= 2 && T[p].leaf_node &&
          T[p].leaf_ptr && T[p].leaf_elems && T[p].elem_xy && A[p].row_ptr[A[p].n_el] >= 0 &&
          T[p].leaf_ptr[T[p].n_leaves] == A[p].n_el;
-  if (!ok) return hss::make_plan(nprob, A, T);  // reports the error
+  if (!ok) return std::make_shared<const hss::Plan>(hss::make_plan(nprob, A, T));  // reports the error
   PlanCache& c = plan_cache();
   {
     std::lock_guard<std::mutex> lk(c.mu);
-    if (c.valid) {
+    if (c.plan) {
       size_t off = 0;
       bool same = true;
       visit_structure(nprob, A, T, [&](const int32_t* v, size_t n) {
@@ -124,13 +123,12 @@ hss::Plan plan_for(int nprob, const hss_block_op_t* A, const hss_tree_t* T) {
       if (same && off == c.key.size()) return c.plan;
     }
   }
-  hss::Plan plan = hss::make_plan(nprob, A, T);
+  auto plan = std::make_shared<const hss::Plan>(hss::make_plan(nprob, A, T));
   std::vector<int32_t> key;
   visit_structure(nprob, A, T, [&](const int32_t* v, size_t n) { key.insert(key.end(), v, v + n); });
   std::lock_guard<std::mutex> lk(c.mu);
   c.key = std::move(key);
   c.plan = plan;
-  c.valid = true;
   return plan;
 }
 }  // namespace
@@ -166,7 +164,7 @@ hss_status_t hss_factor_batched(int32_t nprob, const hss_block_op_t* A, const hs
     if (opts.p_os < 1 || opts.l0 < 1 || opts.max_attempts < 1) return fail(HSS_EINVAL, "bad options");
     if (opts.prec != HSS_PREC_FP64 && opts.prec != HSS_PREC_FP32 && opts.prec != HSS_PREC_BF16)
       return fail(HSS_EINVAL, "unknown precision");
-    hss::Plan plan = plan_for(nprob, A, T);
+    std::shared_ptr<const hss::Plan> plan = plan_for(nprob, A, T);
     for (int p = 0; p < nprob; ++p) check_finite_host(A[p]);
     ensure_device();
     std::unique_ptr<hss_ctx> h(new hss_ctx);

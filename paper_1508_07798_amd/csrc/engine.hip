@@ -295,7 +295,8 @@ template <class T> struct Engine : EngineBase {
   using W = typename traits<T>::wide;
   static constexpr bool CX = traits<T>::cplx;
 
-  Plan P;
+  std::shared_ptr<const Plan> Psp;  // shared with the plan cache: never modified
+  const Plan& P;
   hss_opts_t o;
   hipStream_t st;
   int lds_max = 65536;
@@ -407,7 +408,7 @@ template <class T> struct Engine : EngineBase {
   int work_nrhs = 0;
   Arena work;
 
-  Engine(Plan&& plan, const hss_opts_t& opts) : P(std::move(plan)), o(opts) {
+  Engine(std::shared_ptr<const Plan> plan, const hss_opts_t& opts) : Psp(std::move(plan)), P(*Psp), o(opts) {
     st = (hipStream_t)o.hip_stream;
     persist.st = scratch.st = work.st = st;
     // profile: 0 off, 1 every class, otherwise bit (c + 1) selects class c
@@ -751,89 +752,42 @@ template <class T> struct Engine : EngineBase {
     };
     tol = tol_;
     const int nprob = (int)P.probs.size();
-    // operator upload (FP64)
+    // operator upload (FP64); the index arrays come precomputed with the plan
+    const PlanFlat& F = P.flat;
     {
-      std::vector<int32_t> rp{0}, ci;
-      std::vector<int64_t> elem_dof, seg{0};
-      std::vector<int32_t> dof_elem, dof_prob;
-      for (int p = 0; p < nprob; ++p) {
-        const PProblem& pr = P.probs[p];
-        for (int e = 0; e < pr.n_el; ++e) {
-          for (int b = pr.row_ptr[e]; b < pr.row_ptr[e + 1]; ++b) ci.push_back((int32_t)(pr.el_off + pr.col_idx[b]));
-          rp.push_back((int32_t)ci.size());
-          elem_dof.push_back(pr.dof_off + (int64_t)e * q);
-          for (int k = 0; k < q; ++k) {
-            dof_elem.push_back((int32_t)(pr.el_off + e));
-            dof_prob.push_back(p);
-          }
-        }
-        seg.push_back(pr.dof_off + pr.ndof);
-      }
-      d_row_ptr = up(rp, persist);
-      d_col_idx = up(ci, persist);
-      nnzb = (int64_t)ci.size();
-      d_elem_dof = up(elem_dof, persist);
-      d_seg_off = up(seg, persist);
-      d_dof_elem = up(dof_elem, persist);
-      d_dof_prob = up(dof_prob, persist);
+      d_row_ptr = up(F.row_ptr, persist);
+      d_col_idx = up(F.col_idx, persist);
+      nnzb = (int64_t)F.col_idx.size();
+      d_elem_dof = up(F.elem_dof, persist);
+      d_seg_off = up(F.seg, persist);
+      d_dof_elem = up(F.dof_elem, persist);
+      d_dof_prob = up(F.dof_prob, persist);
       const size_t blk = (size_t)q * q;
-      size_t nnzb = ci.size();
-      d_vals = persist.get<W>(nnzb * blk);
+      d_vals = persist.get<W>((size_t)nnzb * blk);
       for (int p = 0; p < nprob; ++p) {
         const PProblem& pr = P.probs[p];
         size_t nb_p = (size_t)pr.row_ptr[pr.n_el];
         const hipMemcpyKind kind = A[p].vals_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
         HIP_CHECK(hipMemcpyAsync(d_vals + (size_t)pr.blk_off * blk, A[p].vals, nb_p * blk * sizeof(W), kind, st));
       }
-      std::vector<int64_t> perm(ntot);
-      for (int p = 0; p < nprob; ++p) {
-        const PProblem& pr = P.probs[p];
-        for (int64_t t = 0; t < pr.ndof; ++t) perm[pr.dof_off + t] = pr.dof_off + pr.perm[t];
-      }
-      d_perm = up(perm, persist);
+      d_perm = up(F.perm, persist);
     }
     // per box index data and factor storage
     const int nn = (int)P.nodes.size();
     nd.assign(nn, NodeDev{});
     {
-      std::vector<int64_t> gidx_all, bpos_all;
-      std::vector<int32_t> src_all;
-      std::vector<size_t> goff(nn), soff(nn), boff(nn);
-      size_t fsz = 0, psz = 0;
-      std::vector<size_t> foff(nn), aoff(nn), poff(nn);
+      int64_t* dg = up(F.gidx, persist);
+      int32_t* ds = up(F.src, persist);
+      int64_t* db = up(F.bpos, persist);
+      T* fbase = persist.get<T>(std::max<size_t>(F.fsz, 1));
+      int* pbase = persist.get<int>(std::max<size_t>(F.psz, 1));
       for (int g = 0; g < nn; ++g) {
-        const PNode& n = P.nodes[g];
-        const PProblem& pr = P.probs[n.prob];
-        goff[g] = gidx_all.size();
-        for (auto d : n.idof) gidx_all.push_back(pr.dof_off + d);
-        for (auto d : n.bdof) gidx_all.push_back(pr.dof_off + d);
-        soff[g] = src_all.size();
-        if (!n.leaf) {
-          src_all.insert(src_all.end(), n.isrc.begin(), n.isrc.end());
-          src_all.insert(src_all.end(), n.bsrc.begin(), n.bsrc.end());
-        }
-        boff[g] = bpos_all.size();
-        for (auto b : n.bpos) bpos_all.push_back(pr.dof_off + b);
-        const size_t ni = n.idof.size(), nbd = n.bdof.size();
-        foff[g] = fsz;
-        fsz += ((ni * (ni + nbd) + 63) / 64) * 64;
-        aoff[g] = fsz;
-        fsz += ((nbd * ni + 63) / 64) * 64;
-        poff[g] = psz;
-        psz += ((ni + 63) / 64) * 64;
-      }
-      int64_t* dg = up(gidx_all, persist);
-      int32_t* ds = up(src_all, persist);
-      int64_t* db = up(bpos_all, persist);
-      T* fbase = persist.get<T>(std::max<size_t>(fsz, 1));
-      int* pbase = persist.get<int>(std::max<size_t>(psz, 1));
-      for (int g = 0; g < nn; ++g) {
-        nd[g].gidx = dg + goff[g];
-        nd[g].src = P.nodes[g].leaf ? nullptr : ds + soff[g];
-        nd[g].bpos = db + boff[g];
-        nd[g].G = fbase + foff[g];
-        nd[g].Abi = fbase + aoff[g];
-        nd[g].rowperm = pbase + poff[g];
+        nd[g].gidx = dg + F.goff[g];
+        nd[g].src = P.nodes[g].leaf ? nullptr : ds + F.soff[g];
+        nd[g].bpos = db + F.boff[g];
+        nd[g].G = fbase + F.foff[g];
+        nd[g].Abi = fbase + F.aoff[g];
+        nd[g].rowperm = pbase + F.poff[g];
       }
     }
     rank_v.assign(nn, 0);
@@ -1812,7 +1766,7 @@ template <class T> struct Engine : EngineBase {
   }
 };
 
-std::unique_ptr<EngineBase> make_engine(Plan&& plan, const hss_opts_t& opts, bool cplx) {
+std::unique_ptr<EngineBase> make_engine(std::shared_ptr<const Plan> plan, const hss_opts_t& opts, bool cplx) {
   const bool fp64 = opts.prec == HSS_PREC_FP64;
   if (opts.prec == HSS_PREC_BF16 && cplx)
     throw Error(HSS_EUNSUPPORTED, "BF16 Schur products are built for real operators only");
@@ -1884,13 +1838,13 @@ template <class X>
 void debug_gj_t(int nb, void* const* Mat, const int32_t* n, const int32_t* m, int block, int32_t* singular,
                 hipStream_t st) {
   // a throwaway engine instance provides the launch logic
-  Plan P;
-  P.probs.resize(1);
-  P.probs[0].q = 1;
+  auto P = std::make_shared<Plan>();
+  P->probs.resize(1);
+  P->probs[0].q = 1;
   hss_opts_t o;
   std::memset(&o, 0, sizeof(o));
   o.hip_stream = st;
-  Engine<X> eng(std::move(P), o);
+  Engine<X> eng(P, o);
   Arena ar;
   ar.st = st;
   int* flags = ar.get<int>(nb);

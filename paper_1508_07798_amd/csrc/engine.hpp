@@ -20,6 +20,6 @@ struct EngineBase {
   virtual bool query(const std::string& key, std::vector<double>& out) = 0;
 };
 
-std::unique_ptr<EngineBase> make_engine(Plan&& plan, const hss_opts_t& opts, bool cplx);
+std::unique_ptr<EngineBase> make_engine(std::shared_ptr<const Plan> plan, const hss_opts_t& opts, bool cplx);
 
 }  // namespace hss

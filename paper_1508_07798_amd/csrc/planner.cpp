@@ -330,7 +330,63 @@ Plan make_plan(int nprob, const hss_block_op_t* A, const hss_tree_t* T) {
   for (auto& nd : P.nodes) hmax = std::max(hmax, nd.height);
   P.waves.assign(hmax + 1, {});
   for (size_t g = 0; g < P.nodes.size(); ++g) P.waves[P.nodes[g].height].push_back((int)g);
+  flatten(P);
   return P;
+}
+
+void flatten(Plan& P) {
+  PlanFlat& F = P.flat;
+  F = PlanFlat{};
+  const int nprob = (int)P.probs.size();
+  F.row_ptr.push_back(0);
+  F.seg.push_back(0);
+  for (int p = 0; p < nprob; ++p) {
+    const PProblem& pr = P.probs[p];
+    for (int e = 0; e < pr.n_el; ++e) {
+      for (int b = pr.row_ptr[e]; b < pr.row_ptr[e + 1]; ++b)
+        F.col_idx.push_back((int32_t)(pr.el_off + pr.col_idx[b]));
+      F.row_ptr.push_back((int32_t)F.col_idx.size());
+      F.elem_dof.push_back(pr.dof_off + (int64_t)e * pr.q);
+      for (int k = 0; k < pr.q; ++k) {
+        F.dof_elem.push_back((int32_t)(pr.el_off + e));
+        F.dof_prob.push_back(p);
+      }
+    }
+    F.seg.push_back(pr.dof_off + pr.ndof);
+  }
+  F.perm.assign(P.ndof_total, 0);
+  for (int p = 0; p < nprob; ++p) {
+    const PProblem& pr = P.probs[p];
+    for (int64_t t = 0; t < pr.ndof; ++t) F.perm[pr.dof_off + t] = pr.dof_off + pr.perm[t];
+  }
+  const int nn = (int)P.nodes.size();
+  F.goff.resize(nn);
+  F.soff.resize(nn);
+  F.boff.resize(nn);
+  F.foff.resize(nn);
+  F.aoff.resize(nn);
+  F.poff.resize(nn);
+  for (int g = 0; g < nn; ++g) {
+    const PNode& n = P.nodes[g];
+    const PProblem& pr = P.probs[n.prob];
+    F.goff[g] = F.gidx.size();
+    for (auto d : n.idof) F.gidx.push_back(pr.dof_off + d);
+    for (auto d : n.bdof) F.gidx.push_back(pr.dof_off + d);
+    F.soff[g] = F.src.size();
+    if (!n.leaf) {
+      F.src.insert(F.src.end(), n.isrc.begin(), n.isrc.end());
+      F.src.insert(F.src.end(), n.bsrc.begin(), n.bsrc.end());
+    }
+    F.boff[g] = F.bpos.size();
+    for (auto b : n.bpos) F.bpos.push_back(pr.dof_off + b);
+    const size_t ni = n.idof.size(), nbd = n.bdof.size();
+    F.foff[g] = F.fsz;
+    F.fsz += ((ni * (ni + nbd) + 63) / 64) * 64;
+    F.aoff[g] = F.fsz;
+    F.fsz += ((nbd * ni + 63) / 64) * 64;
+    F.poff[g] = F.psz;
+    F.psz += ((ni + 63) / 64) * 64;
+  }
 }
 
 }  // namespace hss

@@ -74,6 +74,25 @@ struct PProblem {
   int max_height = 0;
 };
 
+// Index arrays of a plan in the layout the device uses, built once with the plan
+// (they depend on the structure only).
+struct PlanFlat {
+  // operator, all problems concatenated: element CSR with global element ids, first
+  // dof of each element, problem segment offsets, element and problem of every dof,
+  // and tree position -> global dof
+  std::vector<int32_t> row_ptr, col_idx, dof_elem, dof_prob;
+  std::vector<int64_t> elem_dof, seg, perm;
+  // per box: interior + boundary dofs (global), merge sources, parent positions,
+  // each with its offset into the concatenation
+  std::vector<int64_t> gidx, bpos;
+  std::vector<int32_t> src;
+  std::vector<size_t> goff, soff, boff;
+  // factor storage per box: [A^_ii^-1 | X] at foff, A^_bi at aoff (64-element
+  // aligned, total fsz), row permutation at poff (total psz)
+  std::vector<size_t> foff, aoff, poff;
+  size_t fsz = 0, psz = 0;
+};
+
 struct Plan {
   std::vector<PProblem> probs;
   std::vector<PNode> nodes;
@@ -81,8 +100,12 @@ struct Plan {
   std::vector<PRoot> roots;              // one per problem
   int64_t ndof_total = 0;
   int q_max = 0;
+  PlanFlat flat;
   int find(int prob, int heap) const;
 };
+
+// Fills plan.flat from the rest of the plan.
+void flatten(Plan& plan);
 
 // Builds the plan; throws hss::Error(HSS_EINVAL / HSS_EUNSUPPORTED, msg) on bad input.
 Plan make_plan(int nprob, const hss_block_op_t* A, const hss_tree_t* T);
