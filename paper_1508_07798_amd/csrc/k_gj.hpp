@@ -515,126 +515,6 @@ template <class R> __device__ __forceinline__ void wave_pivot_max(R& v, int& i) 
   i = k;
 }
 
-// Register-resident panel LU with the column loop unrolled at compile time: NT
-// threads, thread tid owns rows tid + t * NT (t < RPT) and keeps their NB columns in
-// registers. Per column: each wave's best candidate (largest modulus, lowest row on
-// ties; a NaN modulus ranks below every number, so a NaN column still yields the
-// lowest free row) goes to LDS with the candidate row itself, one barrier, then
-// every thread reduces the wave partials, reads the pivot row and updates only the
-// columns right of the pivot (compile-time bounds, no branches). Pivots, row
-// movement and Pinv are those of gj_panel_kernel.
-template <class T, int NB, int RPT, int NT>
-__global__ __launch_bounds__(NT) void gj_panel_unr_kernel(const GjDesc<T>* __restrict__ descs, int j0, int nb) {
-  using R = typename traits<T>::real;
-  constexpr bool CPLX = traits<T>::cplx;
-  constexpr int NW = NT / 64;
-  const GjDesc<T> g = descs[blockIdx.x];
-  if (j0 >= g.n) return;
-  const int w = min(nb, g.n - j0);
-  const int base = g.poff + j0;  // first candidate row
-  const int Rr = g.rows - base;  // >= w
-  __shared__ RedPair<R> s_red[2][NW];
-  __shared__ int s_pphys[NB];
-  __shared__ T s_lu[NB][NB + 1];  // packed L\U row of the pivot of column c, in order
-  // candidate pivot row of every wave (real and imaginary parts), double buffered
-  __shared__ R s_cre[2][NW][NB];
-  __shared__ R s_cim[2][NW][CPLX ? NB : 1];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  R re[RPT][NB], im[RPT][NB];
-  // clamped addresses: every load is issued, out-of-range entries are zeroed after
-  static_for<0, RPT>([&](auto tidx) {
-    constexpr int t = decltype(tidx)::value;
-    const int r = tid + t * NT;
-    const int rr = min(r, Rr - 1);
-    static_for<0, NB>([&](auto ci) {
-      constexpr int cc = decltype(ci)::value;
-      const T v = g.M[(base + rr) + (size_t)(j0 + min(cc, w - 1)) * g.rows];
-      const bool keep = r < Rr && cc < w;
-      re[t][cc] = keep ? traits<T>::re(v) : R(0);
-      im[t][cc] = keep ? traits<T>::im(v) : R(0);
-    });
-  });
-  unsigned done = 0;  // bit t: own row t is a pivot row
-  static_for<0, NB>([&](auto cidx) {
-    constexpr int c = decltype(cidx)::value;
-    if (c >= w) return;
-    constexpr int buf = c & 1;
-    R best = -1;
-    int bi = 0x7fffffff;
-    static_for<0, RPT>([&](auto tidx) {
-      constexpr int t = decltype(tidx)::value;
-      const int r = tid + t * NT;
-      R v = re[t][c] * re[t][c] + im[t][c] * im[t][c];
-      v = v == v ? v : R(-0.5);
-      // rows grow with t, so a strict comparison keeps the lowest row on ties
-      const bool take = (r < Rr) & !((done >> t) & 1u) & (v > best);
-      best = take ? v : best;
-      bi = take ? r : bi;
-    });
-    const int mine = bi;
-    wave_pivot_max(best, bi);
-    if (lane == 0) {
-      s_red[buf][wave].v = best;
-      s_red[buf][wave].i = bi;
-    }
-    if (bi == mine && bi < Rr) {
-      // this lane holds the wave's candidate: publish its row (one branch per row
-      // slot, so that the register reads keep constant indices)
-      static_for<0, RPT>([&](auto tidx) {
-        constexpr int t = decltype(tidx)::value;
-        if (bi == tid + t * NT) {
-          static_for<0, NB>([&](auto ci) {
-            constexpr int cc = decltype(ci)::value;
-            s_cre[buf][wave][cc] = re[t][cc];
-            if constexpr (CPLX) s_cim[buf][wave][cc] = im[t][cc];
-          });
-        }
-      });
-    }
-    __syncthreads();
-    RedPair<R> pr[NW];
-    static_for<0, NW>([&](auto kk) { pr[decltype(kk)::value] = s_red[buf][decltype(kk)::value]; });
-    R bv = pr[0].v;
-    int p = pr[0].i;
-    static_for<1, NW>([&](auto kk) {
-      constexpr int k = decltype(kk)::value;
-      const bool take = (pr[k].v > bv) | ((pr[k].v == bv) & (pr[k].i < p));
-      bv = take ? pr[k].v : bv;
-      p = take ? pr[k].i : p;
-    });
-    const int pw_ = (p % NT) >> 6;
-    const R* pre = &s_cre[buf][pw_][0];
-    const R* pim = &s_cim[buf][CPLX ? pw_ : 0][0];
-    if ((p % NT) == tid) done |= 1u << (p / NT);
-    if (tid < NB) s_lu[c][tid] = traits<T>::mk(pre[tid], CPLX ? pim[tid] : R(0));
-    if (tid == 0) s_pphys[c] = p;
-    const T pv = traits<T>::mk(pre[c], CPLX ? pim[c] : R(0));
-    const bool zero = traits<T>::abs2(pv) == 0;
-    if (zero && tid == 0) *g.flag = 1;
-    const T inv = zero ? traits<T>::zero() : pivot_inv(pv);
-    T l[RPT];
-    static_for<0, RPT>([&](auto tidx) {
-      constexpr int t = decltype(tidx)::value;
-      l[t] = sc_mul(traits<T>::mk(re[t][c], im[t][c]), inv);
-      re[t][c] = traits<T>::re(l[t]);
-      im[t][c] = traits<T>::im(l[t]);
-    });
-    static_for<c + 1, NB>([&](auto ci) {
-      constexpr int cc = decltype(ci)::value;
-      const T pw = traits<T>::mk(pre[cc], CPLX ? pim[cc] : R(0));
-      static_for<0, RPT>([&](auto tidx) {
-        constexpr int t = decltype(tidx)::value;
-        const T nv = fms4(traits<T>::mk(re[t][cc], im[t][cc]), l[t], pw);
-        re[t][cc] = traits<T>::re(nv);
-        im[t][cc] = traits<T>::im(nv);
-      });
-    });
-  });
-  __syncthreads();
-  if (wave == 0) panel_moves(g.mv, s_pphys, w);
-  pivot_block_inverse<T, NB, NB + 1, NT>(&s_lu[0][0], w, g.pinv);
-}
-
 // Pinv = A11^{-1} for the pivot block of a panel, A11(c, :) = the original panel
 // row of the pivot of column c (rows in pivot order), by Gauss-Jordan elimination
 // without further interchanges: its pivots are those of the panel's LU. Every
@@ -664,7 +544,9 @@ __device__ __forceinline__ void pivot_block_gj(const GjDesc<T>& g, int j0, int b
     });
     __syncthreads();
     const T p = s_row[b][k];
-    const T ip = traits<T>::abs2(p) == 0 ? traits<T>::zero() : pivot_inv(p);
+    const bool zp = traits<T>::abs2(p) == 0;
+    if (zp && tid == 0) *g.flag = 1;
+    const T ip = zp ? traits<T>::zero() : pivot_inv(p);
     static_for<0, EPT>([&](auto qq) {
       constexpr int q = decltype(qq)::value;
       const int i = ei[q], j = ej[q];
@@ -694,10 +576,18 @@ __device__ __forceinline__ void pivot_block_gj(const GjDesc<T>& g, int j0, int b
 // candidate (largest modulus, lowest row on ties; a NaN modulus ranks below every
 // number) and its row go to LDS, one barrier, then every thread reduces the wave
 // partials and updates its rows with the pivot row.
-template <class T, int NB, int RPT, int NT>
+//
+// S is the arithmetic of the pivot search: T itself, or for double-precision
+// matrices the single-precision type of the same kind, since only the pivot order
+// leaves the loop (every pivot it picks is within a factor 1 - O(2^-24) of the
+// column's largest, so the multipliers stay bounded by 1 + O(2^-24)); the elimination
+// itself (gj_rows, the GEMMs) and Pinv stay in T, and exactly zero pivots are
+// detected in T by pivot_block_gj.
+template <class T, int NB, int RPT, int NT, class S = T>
 __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __restrict__ descs, int j0, int nb) {
-  using R = typename traits<T>::real;
+  using R = typename traits<S>::real;
   constexpr bool CPLX = traits<T>::cplx;
+  static_assert(traits<S>::cplx == traits<T>::cplx, "search type of the same kind");
   constexpr int NW = NT / 64;
   const GjDesc<T> g = descs[blockIdx.x];
   if (j0 >= g.n) return;
@@ -719,8 +609,8 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
       constexpr int cc = decltype(ci)::value;
       const T v = g.M[(base + rr) + (size_t)(j0 + min(cc, w - 1)) * g.rows];
       const bool keep = r < Rr && cc < w;
-      re[t][cc] = keep ? traits<T>::re(v) : R(0);
-      im[t][cc] = keep ? traits<T>::im(v) : R(0);
+      re[t][cc] = keep ? R(traits<T>::re(v)) : R(0);
+      im[t][cc] = keep ? R(traits<T>::im(v)) : R(0);
     });
   });
   unsigned done = 0;  // bit t: own row t is a pivot row
@@ -782,24 +672,24 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
       pri[k] = CPLX ? pim[k] : R(0);
     });
     __builtin_amdgcn_sched_barrier(0);
-    const T pv = traits<T>::mk(prr[0], pri[0]);
-    const bool zero = traits<T>::abs2(pv) == 0;
-    if (zero && tid == 0) *g.flag = 1;
-    const T inv = zero ? traits<T>::zero() : pivot_inv(pv);
-    T l[RPT];
+    const S pv = traits<S>::mk(prr[0], pri[0]);
+    const bool zero = traits<S>::abs2(pv) == 0;
+    if (std::is_same<S, T>::value && zero && tid == 0) *g.flag = 1;
+    const S inv = zero ? traits<S>::zero() : pivot_inv(pv);
+    S l[RPT];
     static_for<0, RPT>([&](auto tidx) {
       constexpr int t = decltype(tidx)::value;
-      l[t] = sc_mul(traits<T>::mk(re[t][0], im[t][0]), inv);
+      l[t] = sc_mul(traits<S>::mk(re[t][0], im[t][0]), inv);
     });
     // update and shift: slot k takes column c + 1 + k
     static_for<0, NB - 1>([&](auto ci) {
       constexpr int k = decltype(ci)::value;
-      const T pw = traits<T>::mk(prr[k + 1], pri[k + 1]);
+      const S pw = traits<S>::mk(prr[k + 1], pri[k + 1]);
       static_for<0, RPT>([&](auto tidx) {
         constexpr int t = decltype(tidx)::value;
-        const T nv = fms4(traits<T>::mk(re[t][k + 1], im[t][k + 1]), l[t], pw);
-        re[t][k] = traits<T>::re(nv);
-        im[t][k] = traits<T>::im(nv);
+        const S nv = fms4(traits<S>::mk(re[t][k + 1], im[t][k + 1]), l[t], pw);
+        re[t][k] = traits<S>::re(nv);
+        im[t][k] = traits<S>::im(nv);
       });
     });
     static_for<0, RPT>([&](auto tidx) {

@@ -13,59 +13,49 @@
 
 namespace hss {
 
+// Arithmetic of the pivot search: single precision for double-precision matrices
+// (gj_panel_rot_kernel explains why the pivot order needs no more).
+template <class X> struct Search { using type = X; };
+template <> struct Search<double> { using type = float; };
+template <> struct Search<cd> { using type = cf; };
+
 template <class X>
 bool panel_rot_config(int rows, PanelShape& s) {
+  // 16-column panels, up to four rows per thread
   if (rows <= 128) {
     s = {16, 1, 128};
     return true;
   }
-  if constexpr (sizeof(X) == 16) {
-    // complex double: 16-column rows take four registers per entry, so 512-thread
-    // 16-column variants would spill; 769 .. 1280 rows go to the kernel with the
-    // column loop unrolled (triangular update), taller panels to 8 columns
-    if (rows <= 256 * 3) {
-      s = {16, (rows + 255) / 256, 256};
-      return true;
-    }
-    if (rows <= 256 * 5) {
-      s = {16, 5, 256, true};
-      return true;
-    }
-    if (rows <= 512 * 5) {
-      s = {8, std::max(3, (rows + 511) / 512), 512};
-      return true;
-    }
-    return false;
-  } else {
-    if (rows <= 256 * 4) {
-      s = {16, (rows + 255) / 256, 256};
-      return true;
-    }
-    if (rows <= 512 * 4) {
-      s = {16, (rows + 511) / 512, 512};
-      return true;
-    }
-    return false;
+  if (rows <= 256 * 4) {
+    s = {16, (rows + 255) / 256, 256};
+    return true;
   }
+  if (rows <= 512 * 4) {
+    s = {16, (rows + 511) / 512, 512};
+    return true;
+  }
+  // real types search in single precision: up to eight rows per thread
+  if (!traits<X>::cplx && rows <= 512 * 8) {
+    const int rpt = (rows + 511) / 512;
+    s = {16, rpt <= 6 ? 6 : 8, 512};
+    return true;
+  }
+  return false;
 }
 
 template <class X>
 void launch_panel_rot(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelShape& s, hipStream_t st) {
+  using S = typename Search<X>::type;
 #define HSS_ROT(NB_, RPT_, NT_)                                                      \
-  if (!s.unrolled && s.nb == NB_ && s.rpt == RPT_ && s.nt == NT_) {                  \
-    gj_panel_rot_kernel<X, NB_, RPT_, NT_><<<nn, NT_, 0, st>>>(dd, j0, nb);          \
+  if (s.nb == NB_ && s.rpt == RPT_ && s.nt == NT_) {                                 \
+    gj_panel_rot_kernel<X, NB_, RPT_, NT_, S><<<nn, NT_, 0, st>>>(dd, j0, nb);       \
     return;                                                                          \
   }
   HSS_ROT(16, 1, 128)
-  HSS_ROT(16, 1, 256) HSS_ROT(16, 2, 256) HSS_ROT(16, 3, 256)
-  if constexpr (sizeof(X) != 16) {
-    HSS_ROT(16, 4, 256) HSS_ROT(16, 3, 512) HSS_ROT(16, 4, 512)
-  } else {
-    HSS_ROT(8, 3, 512) HSS_ROT(8, 4, 512) HSS_ROT(8, 5, 512)
-    if (s.unrolled && s.nb == 16 && s.rpt == 5 && s.nt == 256) {
-      gj_panel_unr_kernel<X, 16, 5, 256><<<nn, 256, 0, st>>>(dd, j0, nb);
-      return;
-    }
+  HSS_ROT(16, 1, 256) HSS_ROT(16, 2, 256) HSS_ROT(16, 3, 256) HSS_ROT(16, 4, 256)
+  HSS_ROT(16, 3, 512) HSS_ROT(16, 4, 512)
+  if constexpr (!traits<X>::cplx) {
+    HSS_ROT(16, 6, 512) HSS_ROT(16, 8, 512)
   }
 #undef HSS_ROT
   throw Error(HSS_EDEVICE, "no panel variant for nb " + std::to_string(s.nb) + ", rpt " + std::to_string(s.rpt) +

@@ -75,7 +75,9 @@ GJ_CASES = [(name, 0, ((1, 3), (7, 0), (33, 20), (100, 45), (200, 230))) for nam
 # choice for blocks above 512 rows (128-column blocks, ragged last block)
 GJ_CASES += [(name, 32, ((1, 3), (7, 0), (33, 20), (100, 45), (200, 230))) for name in DT]
 GJ_CASES += [("float64", 0, ((600, 70), (530, 0), (40, 9))), ("complex64", 0, ((600, 70), (530, 0), (40, 9))),
-             ("float32", 100, ((450, 30), (129, 1)))]
+             ("float32", 100, ((450, 30), (129, 1))),
+             # tall real panels (six and eight rows per thread, single-precision pivot search)
+             ("float64", 0, ((2600, 10), (3900, 0)))]
 
 
 @pytest.mark.parametrize("name,block,sizes", GJ_CASES)
