@@ -1,6 +1,8 @@
 // Shared scalar types, traits and error handling for the HSS library.
 #pragma once
 
+#include <type_traits>
+
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -142,6 +144,14 @@ struct Error : std::runtime_error {
 
 #ifdef __HIPCC__
 namespace hss {
+// compile-time loop: f(std::integral_constant<int, I>) for I in [I0, N)
+template <int I0, int N, class F> __device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I0 < N) {
+    f(std::integral_constant<int, I0>{});
+    static_for<I0 + 1, N>(f);
+  }
+}
+
 // ------------------------------------------------------------------ DPP reductions
 // Cross-lane moves within 16-lane rows of a wave64 (gfx9 DPP encodings):
 // 0xB1 = quad_perm [1,0,3,2], 0x4E = quad_perm [2,3,0,1],

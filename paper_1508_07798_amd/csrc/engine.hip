@@ -640,7 +640,8 @@ template <class T> struct Engine : EngineBase {
       prof.stop(id);
       check_launch("gj_panel");
       id = prof.start(C_GJ_ROWS, 0, rby);
-      gj_rows_kernel<X><<<dim3(cdiv(wmax, 64) + cdiv(rmax, 256), nn), 256, 0, st>>>(dd, j0, nb, cdiv(wmax, 64));
+      gj_rows_kernel<X><<<dim3(cdiv(wmax, 64) + cdiv(rmax, 256), nn), 256, 0, st>>>(dd, j0, nb, cdiv(wmax, 64),
+                                                                                   c.rot ? 1 : 0);
       prof.stop(id);
       check_launch("gj_rows");
       run_gemm<X>(upd[pi], m1, p1, C_GJ_UPDATE);

@@ -178,27 +178,41 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict
     __syncthreads();
   }
 
-  // epilogue: lane holds column lane%16 and four rows of each 16x16 block
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
+  // epilogue: lane holds column lane%16 and four rows of each 16x16 block. All
+  // reads of C are issued before the first store (the stores could alias the
+  // reads as far as the compiler knows, which would serialize read-store pairs).
+  const bool rdc = !(traits<T>::re(beta) == 0 && traits<T>::im(beta) == 0);
+  R cre[2][2][4], cim[2][2][4];
+  static_for<0, 2>([&](auto ii) {
+    static_for<0, 2>([&](auto jj) {
+      constexpr int i = decltype(ii)::value, j = decltype(jj)::value;
       const int col = n0 + wn + j * 16 + li;
-      if (col >= g.N) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
+      const bool keep = col < g.N && (col < g.z0 || col >= g.z1) && rdc;
+      static_for<0, 4>([&](auto vv) {
+        constexpr int v = decltype(vv)::value;
         const int row = m0 + wm + i * 16 + mfma_acc<R>::row(lk, v);
-        if (row >= g.M) continue;
-        T val;
-        if constexpr (CX) val = traits<T>::mk(acc[0][i][j][v], acc[1][i][j][v]);
-        else val = acc[0][i][j][v];
-        T* cp = Cg + row + (size_t)col * g.ldc;
-        T out = sc_mul(alpha, val);
-        const bool keep = col < g.z0 || col >= g.z1;
-        if (keep && !(traits<T>::re(beta) == 0 && traits<T>::im(beta) == 0)) out = out + sc_mul(beta, *cp);
-        *cp = out;
-      }
-    }
+        const T c = (keep && row < g.M) ? Cg[row + (size_t)col * g.ldc] : traits<T>::zero();
+        cre[i][j][v] = traits<T>::re(c);
+        cim[i][j][v] = traits<T>::im(c);
+      });
+    });
+  });
+  static_for<0, 2>([&](auto ii) {
+    static_for<0, 2>([&](auto jj) {
+      constexpr int i = decltype(ii)::value, j = decltype(jj)::value;
+      const int col = n0 + wn + j * 16 + li;
+      static_for<0, 4>([&](auto vv) {
+        constexpr int v = decltype(vv)::value;
+        const int row = m0 + wm + i * 16 + mfma_acc<R>::row(lk, v);
+        if (col < g.N && row < g.M) {
+          T val;
+          if constexpr (CX) val = traits<T>::mk(acc[0][i][j][v], acc[1][i][j][v]);
+          else val = acc[0][i][j][v];
+          Cg[row + (size_t)col * g.ldc] = sc_mul(alpha, val) + sc_mul(beta, traits<T>::mk(cre[i][j][v], cim[i][j][v]));
+        }
+      });
+    });
+  });
 }
 
 // ---------------------------------------------------------------- BF16 x 3
@@ -291,23 +305,31 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmDesc* __rest
       }
     __syncthreads();
   }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
+  // all reads of C before the first store (see gemm_nn_kernel)
+  float cv[2][2][4];
+  static_for<0, 2>([&](auto ii) {
+    static_for<0, 2>([&](auto jj) {
+      constexpr int i = decltype(ii)::value, j = decltype(jj)::value;
       const int col = n0 + wn + j * 16 + li;
-      if (col >= g.N) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
+      const bool keep = col < g.N && (col < g.z0 || col >= g.z1) && beta != 0.f;
+      static_for<0, 4>([&](auto vv) {
+        constexpr int v = decltype(vv)::value;
         const int row = m0 + wm + i * 16 + mfma_acc<float>::row(lk, v);
-        if (row >= g.M) continue;
-        float* cp = Cg + row + (size_t)col * g.ldc;
-        float out = alpha * acc[i][j][v];
-        const bool keep = col < g.z0 || col >= g.z1;
-        if (keep && beta != 0.f) out += beta * *cp;
-        *cp = out;
-      }
-    }
+        cv[i][j][v] = (keep && row < g.M) ? Cg[row + (size_t)col * g.ldc] : 0.f;
+      });
+    });
+  });
+  static_for<0, 2>([&](auto ii) {
+    static_for<0, 2>([&](auto jj) {
+      constexpr int i = decltype(ii)::value, j = decltype(jj)::value;
+      const int col = n0 + wn + j * 16 + li;
+      static_for<0, 4>([&](auto vv) {
+        constexpr int v = decltype(vv)::value;
+        const int row = m0 + wm + i * 16 + mfma_acc<float>::row(lk, v);
+        if (col < g.N && row < g.M) Cg[row + (size_t)col * g.ldc] = alpha * acc[i][j][v] + beta * cv[i][j][v];
+      });
+    });
+  });
 }
 
 }  // namespace hss

@@ -55,13 +55,6 @@ template <class R> __device__ inline void argmax_pair(R& v, int& i, R v2, int i2
   }
 }
 
-// compile-time loop: f(std::integral_constant<int, I>) for I in [I0, N)
-template <int I0, int N, class F> __device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (I0 < N) {
-    f(std::integral_constant<int, I0>{});
-    static_for<I0 + 1, N>(f);
-  }
-}
 
 constexpr int GJ_PANEL_THREADS = 512;
 
@@ -70,7 +63,11 @@ constexpr int GJ_PANEL_THREADS = 512;
 // are not pivots fill, in increasing order, the positions >= w whose rows became
 // pivots (every such pairing is a valid partial-pivoting order). Writes
 // mv = [count, (dst, src), ...] with positions relative to the panel start.
-__device__ __forceinline__ void panel_moves(int* mv, const int* pphys, int w) {
+// With rowperm set (wave 0 only, after rowperm's initialisation is visible), the
+// same moves are applied to the row permutation: all of this wave's loads precede
+// its stores, so cycles of moves need no staging.
+__device__ __forceinline__ void panel_moves(int* mv, const int* pphys, int w, int* rowperm = nullptr,
+                                            int base = 0) {
   const int lane = threadIdx.x & 63;
   const int pc = lane < w ? pphys[lane] : -1;
   unsigned pivlow = 0;  // bit r0: row r0 < w is a pivot
@@ -99,6 +96,12 @@ __device__ __forceinline__ void panel_moves(int* mv, const int* pphys, int w) {
     mv[2 + 2 * (n1 + kd)] = lane;
   }
   if (lane == 0) mv[0] = n1 + __popcll(bd);
+  if (rowperm) {
+    const int v1 = mov ? rowperm[base + pc] : 0;
+    const int v2 = disp ? rowperm[base + lane] : 0;
+    if (mov) rowperm[base + lane] = v1;
+    if (disp) rowperm[base + dst] = v2;
+  }
 }
 
 // Pinv = (L11 U11)^{-1} from the packed L\U rows of the pivot block in LDS
@@ -698,8 +701,11 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
       im[t][NB - 1] = R(0);
     });
   }
+  // the row permutation is updated here (gj_rows_kernel is told to leave it)
+  if (g.rowperm && j0 == 0)
+    for (int i = tid; i < g.rows; i += NT) g.rowperm[i] = i;
   __syncthreads();
-  if (wave == 0) panel_moves(g.mv, s_pphys, w);
+  if (wave == 0) panel_moves(g.mv, s_pphys, w, g.rowperm, base);
   pivot_block_gj<T, NB, NT>(g, j0, base, w, s_pphys, s_row, s_col);
 }
 
@@ -715,7 +721,7 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
 // the other rows M - csave R', and the panel columns -csave Pinv / Pinv.
 template <class T>
 __global__ __launch_bounds__(256) void gj_rows_kernel(const GjDesc<T>* __restrict__ descs,
-                                                      int j0, int nb, int ntx) {
+                                                      int j0, int nb, int ntx, int rp_done) {
   using R = typename traits<T>::real;
   const GjDesc<T> g = descs[blockIdx.y];
   if (j0 >= g.n) return;
@@ -773,47 +779,48 @@ __global__ __launch_bounds__(256) void gj_rows_kernel(const GjDesc<T>* __restric
     if (i < w * w) s_pinv[i] = g.pinv[i];
   });
   __syncthreads();
-  // 1. the panel's row interchanges as one permutation of at most 2 nb rows: every
-  //    moved entry of the tile (outside the panel columns) is loaded, then all are stored
-  {
-    constexpr int PER = 64 * 64 / 256;
-    R vr[PER], vi[PER];
-    const int tot = nm * cw;
-    static_for<0, PER>([&](auto kk) {
-      constexpr int k = decltype(kk)::value;
-      const int idx = tid + k * 256;
-      const int e = nm > 0 ? idx % nm : 0;
-      const int col = c0 + (nm > 0 ? idx / nm : 0);
-      const bool act = idx < tot && (col < j0 || col >= j0 + w);
-      const T x = act ? g.M[(base + s_mv[2 * e + 1]) + (size_t)col * g.rows] : traits<T>::zero();
-      vr[k] = traits<T>::re(x);
-      vi[k] = traits<T>::im(x);
-    });
-    __syncthreads();
-    static_for<0, PER>([&](auto kk) {
-      constexpr int k = decltype(kk)::value;
-      const int idx = tid + k * 256;
-      const int e = nm > 0 ? idx % nm : 0;
-      const int col = c0 + (nm > 0 ? idx / nm : 0);
-      if (idx < tot && (col < j0 || col >= j0 + w))
-        g.M[(base + s_mv[2 * e]) + (size_t)col * g.rows] = traits<T>::mk(vr[k], vi[k]);
-    });
-    if (g.rowperm && blockIdx.x == 0) {
-      if (j0 == 0)
-        for (int i = tid; i < g.rows; i += 256) g.rowperm[i] = i;
-      __syncthreads();
-      const int rp = tid < nm ? g.rowperm[base + s_mv[2 * tid + 1]] : 0;
-      __syncthreads();
-      if (tid < nm) g.rowperm[base + s_mv[2 * tid]] = rp;
-    }
-  }
-  __syncthreads();
-  // 2. stage the pivot-row segment, then R' = Pinv * segment; zero the pivot rows
+  // 1. loads, all from M as it is before the step: the rows that the moves carry
+  //    below the pivot block (dst >= w; every other move ends in a pivot position,
+  //    whose row is replaced by R'), and the pivot rows' segment from wherever the
+  //    pivot rows sit now
+  constexpr int PER = 64 * 64 / 256;  // up to 2 nb = 64 moves of 64 columns
+  R vr[PER], vi[PER];
+  const int tot = nm * cw;
+  static_for<0, PER>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    const int idx = tid + k * 256;
+    const int e = nm > 0 ? idx % nm : 0;
+    const int col = c0 + (nm > 0 ? idx / nm : 0);
+    const bool act = idx < tot && s_mv[2 * e] >= w && (col < j0 || col >= j0 + w);
+    const T x = act ? g.M[(base + s_mv[2 * e + 1]) + (size_t)col * g.rows] : traits<T>::zero();
+    vr[k] = traits<T>::re(x);
+    vi[k] = traits<T>::im(x);
+  });
   for (int idx = tid; idx < w * cw; idx += 256) {
     const int i = idx % w, c = idx / w;
-    s_seg[i][c] = g.M[(base + i) + (size_t)(c0 + c) * g.rows];
+    int src = i;  // the pivot of column i sits at base + src before the moves
+    for (int e = 0; e < nm; ++e)
+      if (s_mv[2 * e] == i) src = s_mv[2 * e + 1];
+    s_seg[i][c] = g.M[(base + src) + (size_t)(c0 + c) * g.rows];
+  }
+  if (!rp_done && g.rowperm && blockIdx.x == 0) {
+    if (j0 == 0)
+      for (int i = tid; i < g.rows; i += 256) g.rowperm[i] = i;
+    __syncthreads();
+    const int rp = tid < nm ? g.rowperm[base + s_mv[2 * tid + 1]] : 0;
+    __syncthreads();
+    if (tid < nm) g.rowperm[base + s_mv[2 * tid]] = rp;
   }
   __syncthreads();
+  // 2. stores: the carried rows, R' = Pinv * segment into rbuf, zeros in the pivot rows
+  static_for<0, PER>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    const int idx = tid + k * 256;
+    const int e = nm > 0 ? idx % nm : 0;
+    const int col = c0 + (nm > 0 ? idx / nm : 0);
+    if (idx < tot && s_mv[2 * e] >= w && (col < j0 || col >= j0 + w))
+      g.M[(base + s_mv[2 * e]) + (size_t)col * g.rows] = traits<T>::mk(vr[k], vi[k]);
+  });
   for (int idx = tid; idx < w * cw; idx += 256) {
     const int i = idx % w, c = idx / w;
     const int gc = c0 + c;
