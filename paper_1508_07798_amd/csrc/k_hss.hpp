@@ -210,17 +210,28 @@ __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restric
         for (int q = 0; q < 4; ++q) acc[a][q] = acc[a][q] + sc_mul(sv[a], ov[q]);
     }
   }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  // Y first for all 16 outputs, then the stores (a store the compiler cannot
+  // separate from the next load would serialize the read-store pairs)
+  T yv[4][4];
+  static_for<0, 4>([&](auto aa) {
+    constexpr int a = decltype(aa)::value;
     const int r = r0 + ty * 4 + a;
-    if (r >= m) continue;
-    const int row = s_cand[r];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    const int row = s_cand[r < m ? r : 0];
+    static_for<0, 4>([&](auto qq) {
+      constexpr int q = decltype(qq)::value;
       const int c = c0 + tx * 4 + q;
-      if (c < l) h.Zt[c + (size_t)r * l] = b.Y[row + (size_t)c * n] - acc[a][q];
-    }
-  }
+      yv[a][q] = (r < m && c < l) ? b.Y[row + (size_t)c * n] : traits<T>::zero();
+    });
+  });
+  static_for<0, 4>([&](auto aa) {
+    constexpr int a = decltype(aa)::value;
+    const int r = r0 + ty * 4 + a;
+    static_for<0, 4>([&](auto qq) {
+      constexpr int q = decltype(qq)::value;
+      const int c = c0 + tx * 4 + q;
+      if (r < m && c < l) h.Zt[c + (size_t)r * l] = yv[a][q] - acc[a][q];
+    });
+  });
   if (tid == 0 && r0 == 0 && c0 == 0) *h.k = m;  // provisional: number of candidates (read by cpqr)
 }
 
@@ -411,7 +422,19 @@ __global__ __launch_bounds__(256) void utall_kernel(const CompBox<T>* __restrict
   const int r = tl.r0 + rl;
   if (h.left < 0) {
     if (r < nt)
-      for (int c = cg; c < k; c += 4) h.Ut[r + (size_t)c * nt] = h.U[r + (size_t)c * h.zcap];
+      for (int c0 = cg; c0 < k; c0 += 32) {  // eight loads in flight, then the stores
+        T v[8];
+        static_for<0, 8>([&](auto tt) {
+          constexpr int t = decltype(tt)::value;
+          const int c = c0 + 4 * t;
+          v[t] = c < k ? h.U[r + (size_t)c * h.zcap] : traits<T>::zero();
+        });
+        static_for<0, 8>([&](auto tt) {
+          constexpr int t = decltype(tt)::value;
+          const int c = c0 + 4 * t;
+          if (c < k) h.Ut[r + (size_t)c * nt] = v[t];
+        });
+      }
     return;
   }
   const HssDesc<T> a = hs[h.left], bb = hs[h.right];
