@@ -140,8 +140,8 @@ def main():
                     help="measured workload (default: the Helmholtz configuration the metric is quoted on)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the path would shard by subtree, one GPU per subtree).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -41,7 +41,7 @@ typedef enum {
   HSS_ESINGULAR = -3,    /* a pivot of some A^_ii (or of the root) is exactly zero    */
   HSS_ENOCONV = -4,      /* GMRES did not reach tol within maxit                      */
   HSS_EDEVICE = -5,      /* a HIP runtime call failed (no GPU, launch failure, ...)   */
-  HSS_EUNSUPPORTED = -6  /* valid request outside what this build implements          */
+  HSS_EUNSUPPORTED = -6  /* valid request outside what this library implements        */
 } hss_status_t;
 
 typedef enum { HSS_R64 = 0, HSS_C128 = 1 } hss_dtype_t;
