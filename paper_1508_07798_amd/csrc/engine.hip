@@ -1596,15 +1596,19 @@ template <class T> struct Engine : EngineBase {
         combine_kernel<W><<<grid1(vlen), 256, 0, st>>>(Vb, vlen, j + 1, Hj2, m + 1, d_dof_prob, nprob, Wv, ntot,
                                                        ntot, nrhs, -1.0, 1);
         check_launch("combine");
-        std::vector<double> hn;
-        norms(Wv, hn);
-        h2d(nrmd, hn);
+        // ||w|| stays on the device for the scaling; the host reads it with the
+        // Hessenberg column (one synchronization per Arnoldi step)
+        dots(Wv, 1, Wv, nrmw, 1, 0);
+        norm_finish_kernel<W><<<cdiv(ns, 256), 256, 0, st>>>(nrmw, nrmd, ns);
+        check_launch("norm_finish");
         scale_kernel<W><<<grid1(vlen), 256, 0, st>>>(Wv, ntot, ntot, nrhs, nrmd, d_dof_prob, nprob,
                                                      Vb + (size_t)(j + 1) * vlen);
         check_launch("scale");
         std::vector<W> h1((size_t)ns * (m + 1)), h2((size_t)ns * (m + 1));
+        std::vector<double> hn(ns);
         HIP_CHECK(hipMemcpyAsync(h1.data(), Hj, sizeof(W) * ns * (m + 1), hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipMemcpyAsync(h2.data(), Hj2, sizeof(W) * ns * (m + 1), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipMemcpyAsync(hn.data(), nrmd, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
         sync();
         ++total_steps;
         bool any_act = false;

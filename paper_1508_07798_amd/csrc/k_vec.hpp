@@ -246,4 +246,12 @@ __global__ void scale_kernel(V* __restrict__ w, int64_t ld, int64_t n, int nrhs,
   }
 }
 
+// nrm[s] = sqrt(max(0, re(dot[s]))): the norms that scale_kernel divides by, kept on
+// the device (the host reads them later with the Hessenberg column)
+template <class V>
+__global__ void norm_finish_kernel(const V* __restrict__ dot, double* __restrict__ nrm, int ns) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s < ns) nrm[s] = sqrt(fmax(0.0, (double)traits<V>::re(dot[s])));
+}
+
 }  // namespace hss
