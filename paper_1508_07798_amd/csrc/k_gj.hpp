@@ -518,6 +518,43 @@ template <class R> __device__ __forceinline__ void wave_pivot_max(R& v, int& i) 
   i = k;
 }
 
+// Single-precision pivot search with one reduction: the key of a candidate holds the
+// modulus (a non-negative float; -0.5 for NaN, -1 for no candidate) in the high word
+// as an order-preserving unsigned integer and the complement of the row in the low
+// word, so the largest key is the largest modulus with the lowest row.
+__device__ __forceinline__ uint64_t pivot_key(float v, int row) {
+  const uint32_t u = __float_as_uint(v);
+  const uint32_t hi = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((uint64_t)hi << 32) | (uint64_t)(~(uint32_t)row);
+}
+__device__ __forceinline__ int key_row(uint64_t k) { return (int)(~(uint32_t)k); }
+template <int CTRL> __device__ __forceinline__ uint64_t dpp_u64(uint64_t k) {
+  const uint32_t lo = (uint32_t)dpp_i<CTRL>((int)(uint32_t)k);
+  const uint32_t hi = (uint32_t)dpp_i<CTRL>((int)(uint32_t)(k >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+// wave-wide maximum of the keys, uniform: four in-row DPP steps, then the four rows
+__device__ __forceinline__ uint64_t wave_max_key(uint64_t k) {
+  uint64_t o;
+  o = dpp_u64<0xB1>(k);
+  k = o > k ? o : k;
+  o = dpp_u64<0x4E>(k);
+  k = o > k ? o : k;
+  o = dpp_u64<0x141>(k);
+  k = o > k ? o : k;
+  o = dpp_u64<0x140>(k);
+  k = o > k ? o : k;
+  uint64_t r[4];
+  static_for<0, 4>([&](auto qq) {
+    constexpr int q = decltype(qq)::value;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, 16 * q);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), 16 * q);
+    r[q] = ((uint64_t)hi << 32) | lo;
+  });
+  const uint64_t a = r[0] > r[1] ? r[0] : r[1], b = r[2] > r[3] ? r[2] : r[3];
+  return a > b ? a : b;
+}
+
 // Pinv = A11^{-1} for the pivot block of a panel, A11(c, :) = the original panel
 // row of the pivot of column c (rows in pivot order), by Gauss-Jordan elimination
 // without further interchanges: its pivots are those of the panel's LU. Every
@@ -598,6 +635,8 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
   const int base = g.poff + j0;  // first candidate row
   const int Rr = g.rows - base;  // >= w
   __shared__ RedPair<R> s_red[2][NW];
+  __shared__ uint64_t s_key[2][NW];
+  constexpr bool KEYS = std::is_same<R, float>::value;  // one 64-bit reduction
   __shared__ int s_pphys[NB];
   __shared__ R s_cre[2][NW][NB];
   __shared__ R s_cim[2][NW][CPLX ? NB : 1];
@@ -632,10 +671,16 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
       bi = take ? r : bi;
     });
     const int mine = bi;
-    wave_pivot_max(best, bi);
-    if (lane == 0) {
-      s_red[buf][wave].v = best;
-      s_red[buf][wave].i = bi;
+    if constexpr (KEYS) {
+      const uint64_t key = wave_max_key(pivot_key(best, bi));
+      bi = key_row(key);
+      if (lane == 0) s_key[buf][wave] = key;
+    } else {
+      wave_pivot_max(best, bi);
+      if (lane == 0) {
+        s_red[buf][wave].v = best;
+        s_red[buf][wave].i = bi;
+      }
     }
     if (bi == mine && bi < Rr) {
       // this lane holds the wave's candidate: publish its row (one branch per row
@@ -652,16 +697,26 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
       });
     }
     __syncthreads();
-    RedPair<R> pr[NW];
-    static_for<0, NW>([&](auto kk) { pr[decltype(kk)::value] = s_red[buf][decltype(kk)::value]; });
-    R bv = pr[0].v;
-    int p = pr[0].i;
-    static_for<1, NW>([&](auto kk) {
-      constexpr int k = decltype(kk)::value;
-      const bool take = (pr[k].v > bv) | ((pr[k].v == bv) & (pr[k].i < p));
-      bv = take ? pr[k].v : bv;
-      p = take ? pr[k].i : p;
-    });
+    int p;
+    if constexpr (KEYS) {
+      uint64_t kmax = s_key[buf][0];
+      static_for<1, NW>([&](auto kk) {
+        const uint64_t o = s_key[buf][decltype(kk)::value];
+        kmax = o > kmax ? o : kmax;
+      });
+      p = key_row(kmax);
+    } else {
+      RedPair<R> pr[NW];
+      static_for<0, NW>([&](auto kk) { pr[decltype(kk)::value] = s_red[buf][decltype(kk)::value]; });
+      R bv = pr[0].v;
+      p = pr[0].i;
+      static_for<1, NW>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        const bool take = (pr[k].v > bv) | ((pr[k].v == bv) & (pr[k].i < p));
+        bv = take ? pr[k].v : bv;
+        p = take ? pr[k].i : p;
+      });
+    }
     const int pwv = (p % NT) >> 6;
     const R* pre = &s_cre[buf][pwv][0];
     const R* pim = &s_cim[buf][CPLX ? pwv : 0][0];
