@@ -229,7 +229,10 @@ def main():
             torch.cuda.synchronize()
         return ms, out
 
-    # one profiled warm-up step names the dominant kernel class (wrapper class gmres excluded)
+    # one plain step loads every kernel's code and builds the first apply graph, then one
+    # profiled warm-up step names the dominant kernel class (wrapper class gmres excluded)
+    h, _, _ = step(MIX, 0)
+    h.close()
     h, _, _ = step(MIX, 1)
     warm = class_table(h)
     h.close()
