@@ -3,6 +3,7 @@
 // Kept in a translation unit of its own so that it compiles beside the engine.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "../../include/hss.h"
