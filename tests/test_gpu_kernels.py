@@ -77,7 +77,10 @@ GJ_CASES += [(name, 32, ((1, 3), (7, 0), (33, 20), (100, 45), (200, 230))) for n
 GJ_CASES += [("float64", 0, ((600, 70), (530, 0), (40, 9))), ("complex64", 0, ((600, 70), (530, 0), (40, 9))),
              ("float32", 100, ((450, 30), (129, 1))),
              # tall real panels (six and eight rows per thread, single-precision pivot search)
-             ("float64", 0, ((2600, 10), (3900, 0)))]
+             ("float64", 0, ((2600, 10), (3900, 0))),
+             # complex double at root sizes (single-precision search, 256 and 512 threads)
+             ("complex128", 0, ((1152, 20), (900, 0))),
+             ("float32", 0, ((2000, 5), (1030, 3)))]
 
 
 @pytest.mark.parametrize("name,block,sizes", GJ_CASES)
