@@ -119,3 +119,26 @@ def test_gauss_jordan_needs_pivoting_and_flags_singular():
     assert np.allclose(M.cpu().numpy().T, np.linalg.inv(A), atol=1e-10)
     Z = _dev(np.zeros((5, 5)), torch.float64)
     assert hss.debug_gj([Z], [5], [0]) == 1
+
+
+def test_gauss_jordan_near_ties_in_double():
+    """Double-precision panels pick pivots on a single-precision copy: rows whose
+    moduli agree to single precision (a relative gap of 1e-12) may be taken in either
+    order, and the inverse is still exact to double-precision rounding."""
+    rng = np.random.default_rng(21)
+    n = 300
+    base = rng.standard_normal((n, n))
+    A = base.copy()
+    # every column gets a near-tie: two rows whose entries differ by a factor 1 + 1e-12,
+    # both larger than the rest of the column
+    for j in range(n):
+        r1, r2 = rng.choice(n, 2, replace=False)
+        big = 10.0 + rng.random()
+        A[r1, j] = big
+        A[r2, j] = -big * (1.0 + 1e-12)
+    A += np.sqrt(n) * np.eye(n)
+    M = _dev(A, torch.float64)
+    assert hss.debug_gj([M], [n], [0]) == 0
+    Ainv = np.linalg.inv(A)
+    err = np.abs(M.cpu().numpy().T - Ainv).max() / np.abs(Ainv).max()
+    assert err <= 1e-13 * np.linalg.cond(A) * 50, err
