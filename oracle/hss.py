@@ -17,6 +17,14 @@ and column bases coincide and V = U), visits the HSS nodes children first:
           smallest k with ||R22||_F <= threshold; J = R[perm[:k]],
           T = R11^{-1} R12, U[perm[:k]] = I, U[perm[k:]] = T^T, so that
           Z ~= U Z(J, :).
+  bounded P Section 1 asks for an interpolation matrix whose entries do not
+          exceed 2 in modulus. While max |T| > 2 the skeleton column i and
+          the free column j of the largest |T_ij| trade places (ties: the
+          lowest skeleton position i, then the lowest candidate index of j;
+          the incoming column takes position i) and T is formed again from
+          a QR without pivoting of the reordered columns (Gu and Eisenstat's
+          strong RRQR with f = 2). Every such swap multiplies |det R11| by at
+          least |T_ij| > 2, so the loop ends; k does not change.
 Generators: leaf diagonal blocks D = S(tau, tau); sibling blocks
 B_ab = S(J_a, J_b). The approximant is S~(a, b) = Ut_a B_ab Ut_b^T with the
 tall bases Ut (leaf: U; parent: diag(Ut_a, Ut_b) U).
@@ -26,7 +34,8 @@ the norm): relative Frobenius error per node, ||S - S~||_F <= tol ||S||_F.
 Per-ID threshold on the true block error: delta = tol ||S||_F / sqrt(2 n_id);
 on the samples it is delta * sqrt(l) (E||E Omega||_F^2 = l ||E||_F^2). A
 node whose measured error misses tol is redone with delta / 4; an ID that
-needs more than l - p_os rows is redone with l doubled.
+needs more than l - p_os rows is redone with l doubled. A node whose measured
+error meets tol is accepted as it is.
 
 Test infrastructure only.
 """
@@ -47,35 +56,58 @@ class RowID:
     k: int
     skel: np.ndarray        # indices into the candidate list, pivot order
     U: np.ndarray           # |R| x k interpolation matrix
-    resid: float            # ||R22||_F of the sampled matrix
+    resid: float            # ||R22||_F of the sampled matrix (after the swaps)
     exhausted: bool         # needed more rows than the samples can certify
-    tmax: float             # max |T|
+    tmax: float             # max |T| (at most 2 after the swaps)
+    swaps: int = 0          # strong-RRQR swaps taken
 
 
-def row_id(Z: np.ndarray, thresh: float, l: int) -> RowID:
-    """Row interpolative decomposition of Z (|R| x l) by CPQR of Z^T."""
-    m = Z.shape[0]
-    if m == 0:
-        return RowID(0, np.zeros(0, dtype=np.int64), np.zeros((0, 0), Z.dtype), 0.0, False, 0.0)
-    _, R, perm = sla.qr(Z.T, mode="economic", pivoting=True)
+MAX_SWAPS = 64
+
+
+def _tail_norms(R: np.ndarray) -> np.ndarray:
+    """tail[k] = ||R[k:, k:]||_F for k = 0..r (tail[r] = 0: the remaining columns
+    lie in the span of the first r)."""
     r = R.shape[0]
-    # tail[k] = ||R[k:, k:]||_F for k = 0..r (tail[r] = 0: the rest of the columns
-    # lies in the span of the first r)
     tail = np.zeros(r + 1)
     for k in range(r - 1, -1, -1):
         tail[k] = np.sqrt(tail[k + 1] ** 2 + np.sum(np.abs(R[k, k:]) ** 2)
                           + np.sum(np.abs(R[k + 1:, k]) ** 2))
-    k = next(kk for kk in range(r + 1) if tail[kk] <= thresh)
+    return tail
+
+
+def row_id(Z: np.ndarray, thresh: float, l: int) -> RowID:
+    """Row interpolative decomposition of Z (|R| x l) by CPQR of Z^T, then the
+    swaps that bound the interpolation coefficients by 2."""
+    m = Z.shape[0]
+    if m == 0:
+        return RowID(0, np.zeros(0, dtype=np.int64), np.zeros((0, 0), Z.dtype), 0.0, False, 0.0)
+    _, R, perm = sla.qr(Z.T, mode="economic", pivoting=True)
+    tail = _tail_norms(R)
+    k = next(kk for kk in range(R.shape[0] + 1) if tail[kk] <= thresh)
     exhausted = (k < m) and (k + P_OS > l)
     if k == 0:
         U = np.zeros((m, 0), dtype=Z.dtype)
         return RowID(0, np.zeros(0, dtype=np.int64), U, tail[0], exhausted, 0.0)
     T = sla.solve_triangular(R[:k, :k], R[:k, k:], lower=False)
+    resid = tail[k]
+    swaps = 0
+    while T.size and np.max(np.abs(T)) > 2.0 and swaps < MAX_SWAPS:
+        aT = np.abs(T)
+        ii, jj = np.nonzero(aT == aT.max())
+        best = min(zip(ii.tolist(), jj.tolist()), key=lambda ij: (ij[0], perm[k + ij[1]]))
+        i, j = best
+        perm = perm.copy()
+        perm[i], perm[k + j] = perm[k + j], perm[i]
+        R = sla.qr(Z.T[:, perm], mode="economic")[1]
+        T = sla.solve_triangular(R[:k, :k], R[:k, k:], lower=False)
+        resid = float(np.linalg.norm(R[k:, k:]))
+        swaps += 1
     U = np.zeros((m, k), dtype=np.result_type(Z.dtype, T.dtype))
     U[perm[:k], :] = np.eye(k)
     U[perm[k:], :] = T.T
     tmax = float(np.max(np.abs(T))) if T.size else 0.0
-    return RowID(k, perm[:k].astype(np.int64), U, tail[k], exhausted, tmax)
+    return RowID(k, perm[:k].astype(np.int64), U, resid, exhausted, tmax, swaps)
 
 
 @dataclasses.dataclass
@@ -175,12 +207,11 @@ def compress_adaptive(S: np.ndarray, tree: HssNode, tol: float, omega_fn, l0: in
     for att in range(1, max_attempts + 1):
         delta = scale * tol * nrm / np.sqrt(2.0 * n_id)
         res = compress(S, tree, delta, omega_fn(l))
+        if res.err <= tol:
+            return CompressLog(att, l, scale, res, False)
         if res.exhausted and l < l_cap:
             l = min(2 * l, l_cap)
-            continue
-        if res.err > tol:
+        else:
             scale /= 4.0
-            continue
-        return CompressLog(att, l, scale, res, False)
     return CompressLog(max_attempts, l, scale,
                        HssResult(S.copy(), 0.0, res.ranks if res else [], 0, False, 0.0, n_id), True)

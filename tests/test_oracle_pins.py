@@ -9,10 +9,18 @@
   * LDM^t: with tol = 0 the inverse factorization applied to b equals
     A^{-1} b and GMRES converges in one iteration.
   * ID: ||Z - U Z(J,:)||_F equals ||R22||_F; exact reproduction of
-    low-rank matrices; the error is never below the SVD tail.
+    low-rank matrices; the error is never below the SVD tail. On Kahan's
+    matrix, where column pivoting alone leaves interpolation coefficients
+    far above 2, the swaps bring every |T_ij| to at most 2 (the bound
+    Section 1 puts on P), T is the least-squares interpolation of the free
+    columns by the skeleton columns (numpy.linalg.lstsq), and |det R11|
+    grows by more than 2 per swap.
   * HSS: tol -> 0 reproduces S; skeleton entries are reproduced exactly;
     off-diagonal blocks have the recorded rank; the judge bound holds.
   * GMRES: with P = I it converges in at most N steps to the dense solve.
+    Restarted GMRES(m): every cycle's iterate equals the minimiser of the
+    residual over x_c + M^{-1} K_m(A M^{-1}, r_c), computed independently by
+    numpy.linalg.lstsq on an explicit Krylov basis.
   * MLP: back-propagation matches central differences; the first Adam step
     has the closed form -lr * sign(g).
 """
@@ -167,6 +175,57 @@ def test_row_id_identity_and_low_rank():
         assert e <= thr
 
 
+def _kahan(n, c, cplx=False):
+    """Kahan's matrix diag(s^i) (I - c * strict upper ones), s^2 + c^2 = 1, with
+    columns scaled by (1 - 1e-6)^j so that column pivoting keeps the natural
+    order; complex: unit-modulus phases on the off-diagonal entries."""
+    s = np.sqrt(1 - c * c)
+    R = np.triu(-c * np.ones((n, n)), 1) + np.eye(n)
+    if cplx:
+        ph = np.exp(1j * 0.7 * np.subtract.outer(np.arange(n), np.arange(n)))
+        R = np.where(np.eye(n, dtype=bool), 1.0, R * ph)
+    return np.diag(s ** np.arange(n)) @ R @ np.diag((1 - 1e-6) ** np.arange(n))
+
+
+@pytest.mark.parametrize("n,c,k,cplx", [(10, 0.6, 9, False), (10, 0.6, 9, True), (30, 0.285, 29, False),
+                                        (24, 0.5, 20, True)])
+def test_row_id_strong_rrqr_swaps_bound_p(n, c, k, cplx):
+    C = _kahan(n, c, cplx)
+    Z = C.T.copy()                     # row ID of Z = column ID of C
+    _, R, perm = sla.qr(C, mode="economic", pivoting=True)
+    T0 = sla.solve_triangular(R[:k, :k], R[:k, k:])
+    assert np.max(np.abs(T0)) > 2.0    # column pivoting alone breaks the bound on P
+    # a threshold between ||R[k:, k:]|| and ||R[k-1:, k-1:]|| selects rank k
+    thr = 0.5 * (np.linalg.norm(R[k:, k:]) + np.linalg.norm(R[k - 1:, k - 1:]))
+    rid = ohss.row_id(Z, thr, n)
+    assert rid.k == k and rid.swaps >= 1
+    assert rid.tmax <= 2.0
+    J = rid.skel
+    Jc = np.setdiff1d(np.arange(n), J)
+    assert np.allclose(rid.U[J], np.eye(k), atol=0)
+    assert np.max(np.abs(rid.U[Jc])) <= 2.0
+    # T is the least-squares interpolation of the free columns by the skeleton
+    Tls = np.linalg.lstsq(C[:, J], C[:, Jc], rcond=None)[0]
+    assert np.allclose(rid.U[Jc].T, Tls, rtol=0, atol=1e-10 * max(1.0, np.abs(Tls).max()))
+    # error identity with the final skeleton, and the determinant growth
+    e = np.linalg.norm(Z - rid.U @ Z[J])
+    assert abs(e - rid.resid) <= 1e-12 * np.linalg.norm(Z)
+    assert e >= np.sqrt(np.sum(np.linalg.svd(Z, compute_uv=False)[k:] ** 2)) * (1 - 1e-9)
+    d0 = abs(np.prod(np.diag(R[:k, :k])))
+    d1 = abs(np.prod(np.diag(np.linalg.qr(C[:, J], mode="r"))))
+    assert d1 > d0 * 2.0 ** rid.swaps
+
+
+def test_row_id_without_large_coefficients_takes_no_swap():
+    rng = np.random.default_rng(12)
+    Z = rng.standard_normal((30, 40)) * np.logspace(0, -8, 30)[:, None]
+    rid = ohss.row_id(Z, 1e-4 * np.linalg.norm(Z), 40)
+    _, R, perm = sla.qr(Z.T, mode="economic", pivoting=True)
+    T0 = sla.solve_triangular(R[:rid.k, :rid.k], R[:rid.k, rid.k:])
+    if np.max(np.abs(T0)) <= 2.0:
+        assert rid.swaps == 0 and np.array_equal(np.sort(rid.skel), np.sort(perm[:rid.k]))
+
+
 def _kernel_matrix(n, cplx=False):
     x = np.sort(np.random.default_rng(3).uniform(0, 1, n))
     K = 1.0 / (1.0 + 30.0 * np.abs(x[:, None] - x[None, :]))
@@ -223,6 +282,44 @@ def test_gmres_identity_preconditioner_textbook():
         top = c * a + s * bb
         bot = -np.conj(s) * a + c * bb
         assert abs(bot) < 1e-14 and abs(abs(top) - np.hypot(abs(a), abs(bb))) < 1e-14
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_gmres_restart_cycles_are_least_squares_minimisers(cplx):
+    rng = np.random.default_rng(13)
+    n, m, cycles = 40, 5, 4
+    A = np.diag(np.linspace(1.0, 8.0, n)) + 1.5 * np.triu(rng.standard_normal((n, n)), 1) / np.sqrt(n)
+    Minv = np.eye(n) + 0.2 * rng.standard_normal((n, n)) / np.sqrt(n)
+    if cplx:
+        A = A + 0.5j * np.diag(rng.standard_normal(n))
+        Minv = Minv + 0.1j * rng.standard_normal((n, n)) / np.sqrt(n)
+    b = rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+    res = og.gmres(lambda v: A @ v, lambda v: Minv @ v, b, tol=1e-15, restart=m, maxit=m * cycles)
+    assert res.iters == m * cycles and res.restarts == cycles and not res.converged
+    # independent: x_{c+1} = x_c + M^{-1} Q y, Q an orthonormal basis of K_m(A M^{-1}, r_c),
+    # y the least-squares minimiser of ||r_c - A M^{-1} Q y||
+    x = np.zeros(n, dtype=res.x.dtype)
+    AM = A @ Minv
+    for c in range(cycles):
+        r = b - A @ x
+        K = np.empty((n, m), dtype=res.x.dtype)
+        K[:, 0] = r / np.linalg.norm(r)
+        for j in range(1, m):
+            w = AM @ K[:, j - 1]
+            K[:, j] = w / np.linalg.norm(w)
+        Q = np.linalg.qr(K)[0]
+        y = np.linalg.lstsq(AM @ Q, r, rcond=None)[0]
+        x = x + Minv @ (Q @ y)
+        # the rotated residual at the cycle's last step is the true residual there
+        assert abs(res.history[m * (c + 1) - 1] - np.linalg.norm(b - A @ x) / np.linalg.norm(b)) <= 1e-9
+    assert np.linalg.norm(res.x - x) <= 1e-9 * np.linalg.norm(x)
+    assert abs(res.true_relres - np.linalg.norm(b - A @ x) / np.linalg.norm(b)) <= 1e-9
+
+
+def test_gmres_zero_rhs_returns_zero():
+    A = np.eye(4) * 2.0
+    res = og.gmres(lambda v: A @ v, lambda v: v, np.zeros(4), tol=1e-8, x0=np.ones(4))
+    assert res.iters == 0 and np.array_equal(res.x, np.zeros(4)) and res.true_relres == 0.0
 
 
 def test_mlp_gradients_central_differences():

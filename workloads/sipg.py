@@ -159,108 +159,119 @@ def assemble(n: int, p: int, pde: str = "poisson", coef: np.ndarray | None = Non
     Ky = np.kron(K1, M1)
     Mv = h * h * np.kron(M1, M1)
 
-    def xface(X):   # face normal to x: traces vary along j (y)
-        return np.kron(M1, X)
-
-    def yface(X):   # face normal to y: traces vary along i (x)
-        return np.kron(X, M1)
-
-    # Interior-face blocks for a face with unit normal pointing from the
-    # minus side (value trace e_m, derivative trace d_m along the normal)
-    # to the plus side.  jump [u] = u- - u+, average {a du/dn}.
-    def face_blocks(am, ap, sig, em, dm, ep, dp, scale_d):
-        # scale_d: the 1/h of the normal derivative times the face length h = 1
-        js = {0: 1.0, 1: -1.0}
-        e = {0: em, 1: ep}
-        d = {0: dm * scale_d, 1: dp * scale_d}
-        a = {0: am, 1: ap}
-        out = {}
-        for s in (0, 1):          # test side (row)
-            for t in (0, 1):      # trial side (col)
-                X = (-(a[t] / 2.0) * js[s] * np.outer(e[s], d[t])
-                     - (a[s] / 2.0) * js[t] * np.outer(d[s], e[t])
-                     + sig * h * js[s] * js[t] * np.outer(e[s], e[t]))
-                out[(s, t)] = X
-        return out
-
-    blocks: dict[tuple[int, int], np.ndarray] = {}
-
-    def add(r, c, B):
-        if (r, c) in blocks:
-            blocks[(r, c)] = blocks[(r, c)] + B
+    # Interior-face blocks for a face with unit normal pointing from the minus
+    # side (value trace e1, derivative trace d1 along the normal) to the plus
+    # side (e0, d0): jump [u] = u- - u+, average {a du/dn}. Face matrices act on
+    # the traces; a face normal to x spreads them with kron(M1, X), a face
+    # normal to y with kron(X, M1).
+    # Per-element and per-face scalars as arrays; every block entry is formed by
+    # the same sequence of floating-point operations as a one-face-at-a-time
+    # loop, and each element's diagonal block accumulates its contributions in
+    # a fixed order: volume, left face, right face, lower face, upper face, then
+    # the domain-boundary faces (left, right, bottom, top).
+    def kron_faces(Mfix, X, normal_x):
+        # np.kron(M1, X) (faces normal to x) or np.kron(X, M1) (normal to y) for a
+        # stack of face matrices X [F, p+1, p+1]
+        F = X.shape[0]
+        if normal_x:
+            K = Mfix[None, :, None, :, None] * X[:, None, :, None, :]
         else:
-            blocks[(r, c)] = B.astype(dt, copy=True)
+            K = X[:, :, None, :, None] * Mfix[None, None, :, None, :]
+        return K.reshape(F, q, q)
 
-    for ey in range(n):
-        for ex in range(n):
-            e = ex + n * ey
-            a = coef[ey, ex]
-            V = a * (ax * Kx + ay * Ky)
-            if pde == "helmholtz":
-                V = V - kappa * kappa * Mv
-            elif reaction != 0.0:
-                V = V + reaction * Mv
-            add(e, e, V)
+    def face_stack(am, ap, sig, s, t):
+        # block (test side s, trial side t) of every face; sides 0 = minus, 1 = plus
+        js = {0: 1.0, 1: -1.0}
+        e = {0: e1, 1: e0}
+        d = {0: d1, 1: d0}
+        a = {0: am, 1: ap}
+        c1 = -(a[t] / 2.0) * js[s]
+        c2 = (a[s] / 2.0) * js[t]
+        c3 = sig * h * js[s] * js[t]
+        return (c1[:, None, None] * np.outer(e[s], d[t])[None]
+                - c2[:, None, None] * np.outer(d[s], e[t])[None]
+                + c3[:, None, None] * np.outer(e[s], e[t])[None])
 
-    # vertical faces (normal +x): between (ex, ey) and (ex+1, ey)
-    for ey in range(n):
-        for ex in range(n - 1):
-            m = ex + n * ey
-            pl = m + 1
-            am, ap = coef[ey, ex] * ax, coef[ey, ex + 1] * ax
-            sig = sig0 * max(coef[ey, ex], coef[ey, ex + 1])
-            fb = face_blocks(am, ap, sig, e1, d1, e0, d0, 1.0)
-            add(m, m, xface(fb[(0, 0)]))
-            add(m, pl, xface(fb[(0, 1)]))
-            add(pl, m, xface(fb[(1, 0)]))
-            add(pl, pl, xface(fb[(1, 1)]))
-    # horizontal faces (normal +y): between (ex, ey) and (ex, ey+1)
-    for ey in range(n - 1):
-        for ex in range(n):
-            m = ex + n * ey
-            pl = m + n
-            am, ap = coef[ey, ex] * ay, coef[ey + 1, ex] * ay
-            sig = sig0 * max(coef[ey, ex], coef[ey + 1, ex])
-            fb = face_blocks(am, ap, sig, e1, d1, e0, d0, 1.0)
-            add(m, m, yface(fb[(0, 0)]))
-            add(m, pl, yface(fb[(0, 1)]))
-            add(pl, m, yface(fb[(1, 0)]))
-            add(pl, pl, yface(fb[(1, 1)]))
+    # volume
+    acoef = coef.reshape(-1)                                   # element e = ex + n*ey
+    diag = acoef[:, None, None] * (ax * Kx + ay * Ky)[None]
+    if pde == "helmholtz":
+        diag = diag - (kappa * kappa * Mv)[None]
+    elif reaction != 0.0:
+        diag = diag + (reaction * Mv)[None]
+    diag = diag.astype(dt).reshape(n, n, q, q)                # [ey, ex]
+    right = up = None
+    if n > 1:
+        # vertical faces between (ex, ey) and (ex + 1, ey): arrays [n, n - 1] flattened
+        am = (coef[:, :-1] * ax).reshape(-1)
+        ap = (coef[:, 1:] * ax).reshape(-1)
+        sig = sig0 * np.maximum(coef[:, :-1], coef[:, 1:]).reshape(-1)
+        fx = {st: kron_faces(M1, face_stack(am, ap, sig, *st), True).reshape(n, n - 1, q, q)
+              for st in ((0, 0), (0, 1), (1, 0), (1, 1))}
+        # horizontal faces between (ex, ey) and (ex, ey + 1): arrays [n - 1, n]
+        am = (coef[:-1, :] * ay).reshape(-1)
+        ap = (coef[1:, :] * ay).reshape(-1)
+        sig = sig0 * np.maximum(coef[:-1, :], coef[1:, :]).reshape(-1)
+        fy = {st: kron_faces(M1, face_stack(am, ap, sig, *st), False).reshape(n - 1, n, q, q)
+              for st in ((0, 0), (0, 1), (1, 0), (1, 1))}
+        diag[:, 1:] += fx[(1, 1)]
+        diag[:, :-1] += fx[(0, 0)]
+        diag[1:, :] += fy[(1, 1)]
+        diag[:-1, :] += fy[(0, 0)]
+        right = (fx[(0, 1)], fx[(1, 0)])   # blocks (e, e+1) and (e+1, e)
+        up = (fy[(0, 1)], fy[(1, 0)])      # blocks (e, e+n) and (e+n, e)
 
     # domain-boundary faces
-    def bnd(e, c, a, ev, dv, normal_sign, face):
-        # c: element coefficient (penalty scale), a: coefficient along the normal
+    def bnd_stack(cvec, avec, ev, dv, normal_sign, normal_x):
+        F = cvec.size
         if pde == "helmholtz":
-            X = -1j * kappa * h * np.outer(ev, ev)
+            X = np.broadcast_to((-1j * kappa * h * np.outer(ev, ev))[None], (F, p + 1, p + 1))
         else:
-            sig = sig0 * c
+            sig = sig0 * cvec
             dd = normal_sign * dv
-            X = -a * np.outer(ev, dd) - a * np.outer(dd, ev) + sig * h * np.outer(ev, ev)
-        add(e, e, xface(X) if face in "lr" else yface(X))
+            X = (-avec[:, None, None] * np.outer(ev, dd)[None]
+                 - avec[:, None, None] * np.outer(dd, ev)[None]
+                 + (sig * h)[:, None, None] * np.outer(ev, ev)[None])
+        return kron_faces(M1, np.ascontiguousarray(X), normal_x)
 
-    for ey in range(n):
-        bnd(0 + n * ey, coef[ey, 0], coef[ey, 0] * ax, e0, d0, -1.0, "l")
-        bnd(n - 1 + n * ey, coef[ey, n - 1], coef[ey, n - 1] * ax, e1, d1, +1.0, "r")
-    for ex in range(n):
-        bnd(ex, coef[0, ex], coef[0, ex] * ay, e0, d0, -1.0, "b")
-        bnd(ex + n * (n - 1), coef[n - 1, ex], coef[n - 1, ex] * ay, e1, d1, +1.0, "t")
+    diag[:, 0] += bnd_stack(coef[:, 0], coef[:, 0] * ax, e0, d0, -1.0, True)
+    diag[:, n - 1] += bnd_stack(coef[:, n - 1], coef[:, n - 1] * ax, e1, d1, +1.0, True)
+    diag[0, :] += bnd_stack(coef[0, :], coef[0, :] * ay, e0, d0, -1.0, False)
+    diag[n - 1, :] += bnd_stack(coef[n - 1, :], coef[n - 1, :] * ay, e1, d1, +1.0, False)
 
+    # block rows in ascending column order: e - n, e - 1, e, e + 1, e + n
     n_el = n * n
-    rows: list[list[int]] = [[] for _ in range(n_el)]
-    for (r, c) in blocks:
-        rows[r].append(c)
+    ey, ex = np.divmod(np.arange(n_el), n)
+    has = [ey > 0, ex > 0, np.ones(n_el, bool), ex < n - 1, ey < n - 1]
+    offs = [-n, -1, 0, 1, n]
+    counts = np.sum(has, axis=0)
     row_ptr = np.zeros(n_el + 1, dtype=np.int32)
-    col_idx = []
-    vals = []
-    for r in range(n_el):
-        cs = sorted(rows[r])
-        row_ptr[r + 1] = row_ptr[r] + len(cs)
-        for c in cs:
-            col_idx.append(c)
-            vals.append(blocks[(r, c)].T)  # store column-major
-    return BlockOperator(n=n, p=p, q=q, row_ptr=row_ptr,
-                         col_idx=np.asarray(col_idx, dtype=np.int32),
-                         vals=np.ascontiguousarray(np.asarray(vals, dtype=dt)), h=h)
+    row_ptr[1:] = np.cumsum(counts)
+    nnzb = int(row_ptr[-1])
+    col_idx = np.empty(nnzb, dtype=np.int32)
+    vals = np.empty((nnzb, q, q), dtype=dt)
+    slot = row_ptr[:-1].astype(np.int64).copy()
+    for k, (hk, off) in enumerate(zip(has, offs)):
+        e = np.nonzero(hk)[0]
+        if e.size == 0:
+            continue
+        pos = slot[e]
+        col_idx[pos] = e + off
+        eyk, exk = ey[e], ex[e]
+        if off == 0:
+            B = diag[eyk, exk]
+        elif off == 1:
+            B = right[0][eyk, exk]
+        elif off == -1:
+            B = right[1][eyk, exk - 1]
+        elif off == n:
+            B = up[0][eyk, exk]
+        else:
+            B = up[1][eyk - 1, exk]
+        vals[pos] = np.transpose(B, (0, 2, 1))   # store column-major
+        slot[e] += 1
+    return BlockOperator(n=n, p=p, q=q, row_ptr=row_ptr, col_idx=col_idx,
+                         vals=np.ascontiguousarray(vals), h=h)
 
 
 def load_vector(n: int, p: int, f) -> np.ndarray:
