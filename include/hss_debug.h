@@ -37,6 +37,20 @@ hss_status_t hss_debug_gemm(int32_t scalar, int32_t nbatch, const void* const* A
 hss_status_t hss_debug_gj(int32_t scalar, int32_t nbatch, void* const* Mat, const int32_t* n,
                           const int32_t* m, int32_t block, int32_t* singular, void* hip_stream);
 
+/* Row interpolative decomposition of one candidate set (Section 1: the ID with
+ * interpolation coefficients bounded by 2 in modulus), as the compression runs it
+ * on every HSS node: column-pivoted Householder QR of Z^T truncated at the first k
+ * with ||R22||_F <= thresh, then strong-RRQR swaps while max |T| > 2.
+ *   Zt     device, l x m column-major: Z^T for the m candidate rows of Z (m x l),
+ *          i.e. Z in row-major order; not modified. 1 <= m <= 1024, 1 <= l <= 512.
+ *   p_os   oversampling used for the "samples exhausted" test (k + p_os > l).
+ *   k      host: the rank.   skel  host [m]: the first k entries are the skeleton
+ *          rows in skeleton order.   U  device, m x min(l, m) column-major (ld m):
+ *          Z ~= U(:, 0:k) Z(skel, :); U(skel(i), i) = 1.
+ *   tmax   host: max |T| after the swaps. */
+hss_status_t hss_debug_row_id(int32_t scalar, const void* Zt, int32_t m, int32_t l, double thresh, int32_t p_os,
+                              int32_t* k, int32_t* skel, void* U, float* tmax, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

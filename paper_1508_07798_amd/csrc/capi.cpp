@@ -301,6 +301,8 @@ void debug_gemm(int scalar, int nb, const void* const* A, const void* const* B, 
                 const double* al, const double* be, hipStream_t st);
 void debug_gj(int scalar, int nb, void* const* Mat, const int32_t* n, const int32_t* m, int block,
               int32_t* singular, hipStream_t st);
+void debug_row_id(int scalar, const void* Zt, int m, int l, double thresh, int p_os, int32_t* k, int32_t* skel,
+                  void* U, float* tmax, hipStream_t st);
 }  // namespace hss
 
 extern "C" {
@@ -330,6 +332,18 @@ hss_status_t hss_debug_gj(int32_t scalar, int32_t nbatch, void* const* Mat, cons
       if (n[b] < 0 || m[b] < 0) return fail(HSS_EINVAL, "bad gj sizes");
     ensure_device();
     hss::debug_gj(scalar, nbatch, Mat, n, m, block, singular, (hipStream_t)hip_stream);
+    return HSS_OK;
+  });
+}
+
+hss_status_t hss_debug_row_id(int32_t scalar, const void* Zt, int32_t m, int32_t l, double thresh, int32_t p_os,
+                              int32_t* k, int32_t* skel, void* U, float* tmax, void* hip_stream) {
+  return guarded([&]() -> hss_status_t {
+    if (!Zt || !k || !skel || !U || !tmax) return fail(HSS_EINVAL, "bad row id arguments");
+    if (m < 1 || m > 1024 || l < 1 || l > 512 || p_os < 0 || !(thresh >= 0) || !std::isfinite(thresh))
+      return fail(HSS_EINVAL, "row id sizes out of range");
+    ensure_device();
+    hss::debug_row_id(scalar, Zt, m, l, thresh, p_os, k, skel, U, tmax, (hipStream_t)hip_stream);
     return HSS_OK;
   });
 }

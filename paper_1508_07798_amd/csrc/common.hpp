@@ -181,13 +181,14 @@ __device__ __forceinline__ double rdlane(double v, int l) {
 }
 __device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
-// sum over aligned groups of GL (2, 4, 8 or 16) lanes
+// sum over aligned groups of GL (2, 4, 8, 16 or 32) lanes
 template <int GL, class R> __device__ __forceinline__ R group_sum(R v) {
-  static_assert(GL == 2 || GL == 4 || GL == 8 || GL == 16, "group width");
+  static_assert(GL == 2 || GL == 4 || GL == 8 || GL == 16 || GL == 32, "group width");
   v = v + dpp_v<0xB1>(v);
   if (GL >= 4) v = v + dpp_v<0x4E>(v);
   if (GL >= 8) v = v + dpp_v<0x141>(v);
   if (GL >= 16) v = v + dpp_v<0x140>(v);
+  if (GL >= 32) v = v + __shfl_xor(v, 16, 64);
   return v;
 }
 // sum over the whole wave, uniform result (rows combined in a fixed order)

@@ -307,6 +307,9 @@ template <class T> struct Engine : EngineBase {
   // above which it is used
   static constexpr int kGjBlock = 128;
   static constexpr int kGjBlockMin = 128;
+  // largest sample count of the randomized ID (a box whose ID needs more rows keeps
+  // its dense complement once its attempts are spent)
+  static constexpr int kLcapMax = 512;
   double tol = 0;
   Prof prof;
   Pinned keep;  // pinned host staging, reused after each sync
@@ -426,9 +429,9 @@ template <class T> struct Engine : EngineBase {
       if (pr.q != q) throw Error(HSS_EINVAL, "all problems of a batch must share q");
     ntot = P.ndof_total;
     if (lds_max > 65536) {
-      HIP_CHECK(hipFuncSetAttribute((const void*)cpqr_kernel<T, true, 8, 8>,
+      HIP_CHECK(hipFuncSetAttribute((const void*)cpqr_kernel<T, true, 8, 8, 512, 64>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
-      HIP_CHECK(hipFuncSetAttribute((const void*)cpqr_kernel<T, true, 16, 16>,
+      HIP_CHECK(hipFuncSetAttribute((const void*)cpqr_kernel<T, true, 16, 16, 512, 256>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
       for (const void* f : {(const void*)gj_panel_kernel<T, true, 16>, (const void*)gj_panel_kernel<T, true, 32>,
                             (const void*)gj_panel_kernel<W, true, 16>, (const void*)gj_panel_kernel<W, true, 32>})
@@ -1094,6 +1097,30 @@ template <class T> struct Engine : EngineBase {
   }
 
   // ---------------------------------------------------------------- compression
+  // where the CPQR of one HSS height keeps its working copy: LDS when the largest
+  // l x m of the height fits, else a global copy Zw per node
+  bool cpqr_in_lds(int lmax, int zmax) const {
+    const size_t cap = (size_t)(lds_max > 65536 ? 65536 : 32768);
+    return lmax <= 256 && zmax <= 512 && (size_t)lmax * zmax * sizeof(T) <= cap;
+  }
+  // the CPQR variant for sample counts up to lmax and candidate counts up to zmax
+  void cpqr_launch(const CompBox<T>* dbx, const HssDesc<T>* dhs, const int* dl, unsigned g, int lmax, int zmax,
+                   bool in_lds, int p_os) {
+    const size_t shm = (size_t)lmax * zmax * sizeof(T);
+    if (lmax <= 64 && zmax <= 512) {
+      if (in_lds) cpqr_kernel<T, true, 8, 8, 512, 64><<<g, 256, shm, st>>>(dbx, dhs, dl, p_os);
+      else cpqr_kernel<T, false, 8, 8, 512, 64><<<g, 256, 0, st>>>(dbx, dhs, dl, p_os);
+    } else if (lmax <= 256 && zmax <= 512) {
+      if (in_lds) cpqr_kernel<T, true, 16, 16, 512, 256><<<g, 256, shm, st>>>(dbx, dhs, dl, p_os);
+      else cpqr_kernel<T, false, 16, 16, 512, 256><<<g, 256, 0, st>>>(dbx, dhs, dl, p_os);
+    } else {
+      if (lmax > kLcapMax || zmax > 2 * kLcapMax) throw Error(HSS_EINVAL, "ID sample count above the supported maximum");
+      constexpr int GLb = sizeof(T) >= 16 ? 32 : 16, RPLb = kLcapMax / GLb;
+      cpqr_kernel<T, false, GLb, RPLb, 2 * kLcapMax, kLcapMax><<<g, 256, 0, st>>>(dbx, dhs, dl, p_os);
+    }
+    check_launch("cpqr");
+  }
+
   void compress_wave(const std::vector<int>& wv, const std::vector<T*>& Sp, Arena& tmp) {
     const int nb_boxes = (int)wv.size();
     // symmetrise and take ||S||_F^2 for every box
@@ -1131,7 +1158,7 @@ template <class T> struct Engine : EngineBase {
         continue;
       }
       todo.push_back(i);
-      int lcap = std::min(all[i].n + o.p_os, 256);
+      int lcap = std::min(all[i].n + o.p_os, kLcapMax);
       lcur[i] = std::min(std::max(predicted_l(wv[i]), 4), lcap);
     }
     // the norms are read at the first judge sync (no wait here)
@@ -1216,15 +1243,26 @@ template <class T> struct Engine : EngineBase {
           for (int c0 = 0; c0 < nc; c0 += tw)
             for (int r0 = 0; r0 < na_; r0 += 64) tiles.push_back({(int)t, r0, c0});
         }
+      // per HSS height: the largest candidate count, and where the CPQR keeps its
+      // working copy (LDS when the largest l x zcap of the height fits, else a
+      // global copy Zw per node, allocated here before the descriptors go up)
+      const int nh = (int)byh.size();
+      std::vector<int> zmax(nh, 0);
+      std::vector<char> in_lds(nh, 0);
+      for (int hh = 0; hh < nh; ++hh) {
+        if (byh[hh].empty()) continue;
+        for (int t : byh[hh]) zmax[hh] = std::max(zmax[hh], hs[t].zcap);
+        in_lds[hh] = cpqr_in_lds(lmax, zmax[hh]);
+        if (!in_lds[hh])
+          for (int t : byh[hh]) hs[t].Zw = at.get<T>((size_t)bx[hs[t].box].l * hs[t].zcap);
+      }
       // every list of this attempt is uploaded before its first launch (one copy)
       auto* dbx = up(bx, at);
       auto* dhs = up(hs, at);
-      const int nh = (int)byh.size();
       std::vector<int*> d_lvl(nh, nullptr);
       std::vector<HTile*> d_stl(nh, nullptr), d_utl(nh, nullptr);
       std::vector<unsigned> n_stl(nh, 0), n_utl(nh, 0);
       std::vector<double> sfl(nh, 0.0);
-      std::vector<int> zmax(nh, 0);
       for (int hh = 0; hh < nh; ++hh) {
         if (byh[hh].empty()) continue;
         d_lvl[hh] = up(byh[hh], at);
@@ -1235,7 +1273,6 @@ template <class T> struct Engine : EngineBase {
             for (int c0 = 0; c0 < bx[d.box].l; c0 += 64) stl.push_back({t, r0, c0});
           for (int r0 = 0; r0 < d.hi - d.lo; r0 += 64) utl.push_back({t, r0, 0});
           sfl[hh] += Flop<T>::mac * (double)d.zcap * (d.hi - d.lo) * bx[d.box].l;
-          zmax[hh] = std::max(zmax[hh], d.zcap);
         }
         d_stl[hh] = up(stl, at);
         d_utl[hh] = up(utl, at);
@@ -1261,25 +1298,13 @@ template <class T> struct Engine : EngineBase {
         if (byh[hh].empty()) continue;
         int id = prof.start(C_SAMPLE, sfl[hh], 0);
         fl();
-        sample_kernel<T><<<n_stl[hh], 256, 0, st>>>(dbx, dhs, d_stl[hh]);
+        if (zmax[hh] <= 512) sample_kernel<T, 512><<<n_stl[hh], 256, 0, st>>>(dbx, dhs, d_stl[hh]);
+        else sample_kernel<T, 1024><<<n_stl[hh], 256, 0, st>>>(dbx, dhs, d_stl[hh]);
         prof.stop(id);
         check_launch("sample");
         id = prof.start(C_ID, 0, 0);
-        {
-          const size_t shm = (size_t)lmax * zmax[hh] * sizeof(T);
-          const unsigned g = (unsigned)byh[hh].size();
-          const bool in_lds = shm <= (size_t)(lds_max > 65536 ? 65536 : 32768);
-          int* dl = d_lvl[hh];
-          if (lmax <= 64) {
-            if (in_lds) cpqr_kernel<T, true, 8, 8><<<g, 256, shm, st>>>(dbx, dhs, dl, o.p_os);
-            else cpqr_kernel<T, false, 8, 8><<<g, 256, 0, st>>>(dbx, dhs, dl, o.p_os);
-          } else {
-            if (in_lds) cpqr_kernel<T, true, 16, 16><<<g, 256, shm, st>>>(dbx, dhs, dl, o.p_os);
-            else cpqr_kernel<T, false, 16, 16><<<g, 256, 0, st>>>(dbx, dhs, dl, o.p_os);
-          }
-        }
+        cpqr_launch(dbx, dhs, d_lvl[hh], (unsigned)byh[hh].size(), lmax, zmax[hh], in_lds[hh], o.p_os);
         prof.stop(id);
-        check_launch("cpqr");
       }
       for (int hh = 0; hh < nh; ++hh) {
         if (byh[hh].empty()) continue;
@@ -1320,7 +1345,7 @@ template <class T> struct Engine : EngineBase {
         att[i] += 1;
         const double e = nrm[i] > 0 ? std::sqrt(err[a] / nrm[i]) : 0.0;
         const bool exhausted = flh[a] & 1;
-        const int lcap = std::min(all[i].n + o.p_os, 256);
+        const int lcap = std::min(all[i].n + o.p_os, kLcapMax);
         rank_v[g] = flh[na + a];
         float tm;
         std::memcpy(&tm, &flh[2 * na + a], sizeof(float));
@@ -1328,13 +1353,13 @@ template <class T> struct Engine : EngineBase {
         err_v[g] = e;
         l_v[g] = lcur[i];
         attempts_v[g] = att[i];
+        // accept a box whose measured error meets tol; otherwise grow the sample
+        // when an ID ran out of rows, else tighten the per-ID threshold
         bool retry = false;
-        if (exhausted && lcur[i] < lcap) {
-          lcur[i] = std::min(2 * lcur[i], lcap);
+        if (e > tol) {
           retry = true;
-        } else if (e > tol) {
-          scale[i] /= 4.0;
-          retry = true;
+          if (exhausted && lcur[i] < lcap) lcur[i] = std::min(2 * lcur[i], lcap);
+          else scale[i] /= 4.0;
         }
         if (retry && att[i] >= o.max_attempts) {
           fallback_boxes.push_back(i);
@@ -1546,8 +1571,17 @@ template <class T> struct Engine : EngineBase {
     norms(B, bnorm);
     std::vector<int> iters(ns, 0), restarts(ns, 0), done(ns, 0);
     std::vector<double> relres(ns, 0.0);
+    bool any_zero = false;
     for (int s = 0; s < ns; ++s)
-      if (bnorm[s] == 0) done[s] = 1;
+      if (bnorm[s] == 0) done[s] = 1, any_zero = true;
+    if (any_zero) {
+      // b = 0: the solution is x = 0 whatever the initial guess
+      std::vector<double> keepx(ns);
+      for (int s = 0; s < ns; ++s) keepx[s] = bnorm[s] == 0 ? 0.0 : 1.0;
+      h2d(nrmd, keepx);
+      scale_kernel<W><<<grid1(vlen), 256, 0, st>>>(X, ntot, ntot, nrhs, nrmd, d_dof_prob, nprob, X);
+      check_launch("scale");
+    }
     using C = std::complex<double>;
     auto toC = [](W v) { return C(traits<W>::re(v), traits<W>::im(v)); };
     int total_steps = 0;
@@ -1889,6 +1923,77 @@ void debug_gj_t(int nb, void* const* Mat, const int32_t* n, const int32_t* m, in
   for (int v : f) *singular |= v;
   ar.release();
   mark_clean(st);
+}
+
+template <class X>
+void debug_row_id_t(const void* Zt, int m, int l, double thresh, int p_os, int32_t* k, int32_t* skel, void* U,
+                    float* tmax, hipStream_t st) {
+  auto P = std::make_shared<Plan>();
+  P->probs.resize(1);
+  P->probs[0].q = 1;
+  hss_opts_t o;
+  std::memset(&o, 0, sizeof(o));
+  o.hip_stream = st;
+  Engine<X> eng(P, o);
+  Arena ar;
+  ar.st = st;
+  // one box whose HSS tree is a single leaf of m candidates; with ||S||_F^2 = 2 and
+  // one ID the kernel's threshold tol_scale * sqrt(2) / sqrt(2) * sqrt(l) is thresh
+  std::vector<double> nrm{2.0};
+  std::vector<int> z3(3, 0), cand(m), kk{m};
+  for (int i = 0; i < m; ++i) cand[i] = i;
+  CompBox<X> b{};
+  b.n = m;
+  b.l = l;
+  b.n_id = 1;
+  b.tol_scale = thresh / std::sqrt((double)l);
+  b.nrm2 = eng.up(nrm, ar);
+  int* flags = eng.up(z3, ar);
+  b.flags = flags;
+  b.kmax = flags + 1;
+  b.tmax = (float*)(flags + 2);
+  const int kc = std::min(l, m);
+  HssDesc<X> d{};
+  d.box = 0;
+  d.lo = 0;
+  d.hi = m;
+  d.left = d.right = -1;
+  d.zcap = m;
+  d.cand = eng.up(cand, ar);
+  d.skel = ar.get<int>(m);
+  d.k = eng.up(kk, ar);
+  d.Zt = (X*)Zt;
+  d.U = ar.get<X>((size_t)m * kc);
+  const bool in_lds = eng.cpqr_in_lds(l, m);
+  if (!in_lds) d.Zw = ar.get<X>((size_t)l * m);
+  std::vector<CompBox<X>> bv{b};
+  std::vector<HssDesc<X>> hv{d};
+  std::vector<int> lst{0};
+  auto* dbx = eng.up(bv, ar);
+  auto* dhs = eng.up(hv, ar);
+  int* dl = eng.up(lst, ar);
+  eng.fl();
+  eng.cpqr_launch(dbx, dhs, dl, 1, l, m, in_lds, p_os);
+  std::vector<int> fl(3);
+  HIP_CHECK(hipMemcpyAsync(fl.data(), flags, sizeof(int) * 3, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(k, d.k, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(skel, d.skel, sizeof(int) * m, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(U, d.U, sizeof(X) * (size_t)m * kc, hipMemcpyDeviceToDevice, st));
+  eng.sync();
+  std::memcpy(tmax, &fl[2], sizeof(float));
+  ar.release();
+  mark_clean(st);
+}
+
+void debug_row_id(int scalar, const void* Zt, int m, int l, double thresh, int p_os, int32_t* k, int32_t* skel,
+                  void* U, float* tmax, hipStream_t st) {
+  switch (scalar) {
+    case 0: debug_row_id_t<float>(Zt, m, l, thresh, p_os, k, skel, U, tmax, st); break;
+    case 1: debug_row_id_t<double>(Zt, m, l, thresh, p_os, k, skel, U, tmax, st); break;
+    case 2: debug_row_id_t<cf>(Zt, m, l, thresh, p_os, k, skel, U, tmax, st); break;
+    case 3: debug_row_id_t<cd>(Zt, m, l, thresh, p_os, k, skel, U, tmax, st); break;
+    default: throw Error(HSS_EINVAL, "unknown scalar code");
+  }
 }
 
 void debug_gj(int scalar, int nb, void* const* Mat, const int32_t* n, const int32_t* m, int block,

@@ -615,19 +615,14 @@ __device__ __forceinline__ void pivot_block_gj(const GjDesc<T>& g, int j0, int b
 // original pivot rows at the end (pivot_block_gj). Per column: each wave's best
 // candidate (largest modulus, lowest row on ties; a NaN modulus ranks below every
 // number) and its row go to LDS, one barrier, then every thread reduces the wave
-// partials and updates its rows with the pivot row.
-//
-// S is the arithmetic of the pivot search: T itself, or for double-precision
-// matrices the single-precision type of the same kind, since only the pivot order
-// leaves the loop (every pivot it picks is within a factor 1 - O(2^-24) of the
-// column's largest, so the multipliers stay bounded by 1 + O(2^-24)); the elimination
-// itself (gj_rows, the GEMMs) and Pinv stay in T, and exactly zero pivots are
-// detected in T by pivot_block_gj.
-template <class T, int NB, int RPT, int NT, class S = T>
+// partials and updates its rows with the pivot row. The search and the
+// elimination run in the matrix's own precision, so the pivots are those of
+// partial pivoting in that precision.
+template <class T, int NB, int RPT, int NT>
 __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __restrict__ descs, int j0, int nb) {
+  using S = T;
   using R = typename traits<S>::real;
   constexpr bool CPLX = traits<T>::cplx;
-  static_assert(traits<S>::cplx == traits<T>::cplx, "search type of the same kind");
   constexpr int NW = NT / 64;
   const GjDesc<T> g = descs[blockIdx.x];
   if (j0 >= g.n) return;
@@ -732,7 +727,7 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
     __builtin_amdgcn_sched_barrier(0);
     const S pv = traits<S>::mk(prr[0], pri[0]);
     const bool zero = traits<S>::abs2(pv) == 0;
-    if (std::is_same<S, T>::value && zero && tid == 0) *g.flag = 1;
+    if (zero && tid == 0) *g.flag = 1;
     const S inv = zero ? traits<S>::zero() : pivot_inv(pv);
     S l[RPT];
     static_for<0, RPT>([&](auto tidx) {

@@ -77,7 +77,8 @@ template <class T> struct HssDesc {
   int* cand;          // [zcap] candidate indices into S
   int* skel;          // [zcap] skeleton (first k entries)
   int* k;             // rank
-  T* Zt;              // l x zcap workspace (samples, then QR)
+  T* Zt;              // l x zcap samples Z^T (kept through the CPQR)
+  T* Zw;              // l x zcap working copy for the CPQR when it does not fit in LDS
   T* U;               // zcap x l interpolation matrix (ld = zcap)
   T* Ut;              // (hi - lo) x l tall basis (ld = hi - lo)
 };
@@ -135,7 +136,7 @@ struct HTile {
 // candidates, then Z = Y(R, :) - S(R, tau) Omega(tau, :) written transposed
 // (Zt, l x m). 4 x 4 outputs per thread; the product over tau runs in slabs of
 // 16 staged through LDS. Tiles beyond the candidate count exit.
-template <class T>
+template <class T, int MCAP>
 __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restrict__ bx,
                                                      const HssDesc<T>* __restrict__ hs,
                                                      const HTile* __restrict__ tiles) {
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restric
   const HTile tl = tiles[blockIdx.x];
   const HssDesc<T> h = hs[tl.hnode];
   const CompBox<T> b = bx[h.box];
-  __shared__ int s_cand[512];
+  __shared__ int s_cand[MCAP];
   __shared__ int s_m;
   __shared__ T Sg[64][KC + 1];
   __shared__ T Og[KC][65];
@@ -236,157 +237,205 @@ __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restric
 }
 
 // One workgroup per HSS node: truncated CPQR of Zt (l x m) -> k, skeleton, U.
-// The matrix sits in LDS when it fits (LDS = true), else it is used in place.
-// Columns are never moved: the pivot of step j is a physical column chosen
-// from exact trailing norms; every wave takes the same decision from the
-// same LDS data (bit-identical butterfly reductions), so one barrier per step
-// suffices. Groups of gl lanes apply the reflector to one column each and
-// produce that column's trailing norm for the next step. Reductions run in the
-// real type of the factor (FP32 for the FP32 path).
+// The working copy sits in LDS when it fits (LDS = true), else in the node's
+// global scratch Zw; Zt itself keeps the samples. Columns are never moved: the
+// pivot of step j is a physical column chosen from exact trailing norms; every
+// wave takes the same decision from the same LDS data (bit-identical butterfly
+// reductions), so one barrier per step suffices. Groups of GL lanes apply the
+// reflector to one column each and produce that column's trailing norm for the
+// next step. Reductions run in the real type of the factor.
+//
+// Bounded interpolation coefficients (Section 1: no entry of P above 2 in
+// modulus): after T = R11^{-1} R12 is formed, while max |T| > 2 the skeleton
+// column i and the free column c of the largest |T(i, c)| (ties: lowest i, then
+// lowest candidate index c) trade places, the incoming column taking skeleton
+// position i, and the QR is redone without pivoting in that column order (a
+// strong-RRQR swap with f = 2; each multiplies |det R11| by more than 2, so the
+// loop ends; at most kMaxSwaps are taken). k does not change.
+//
 // GL lanes per column group; each lane holds up to RPL rows of the reflector and
-// of the column it updates in registers (GL * RPL >= l).
-template <class T, bool LDS, int GL, int RPL>
+// of the column it updates in registers (GL * RPL >= l). MCAP bounds the number
+// of candidates m, KCAP the sample count l (and so the rank).
+constexpr int kMaxSwaps = 64;
+template <class T, bool LDS, int GL, int RPL, int MCAP, int KCAP>
 __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict__ bx,
                                                    const HssDesc<T>* __restrict__ hs,
                                                    const int* __restrict__ list, int p_os) {
   using R = typename traits<T>::real;
+  static_assert(GL * RPL >= KCAP, "reflector rows per group");
+  static_assert(MCAP <= 64 * 32, "pivot bit mask");
   const HssDesc<T> h = hs[list[blockIdx.x]];
   const CompBox<T> b = bx[h.box];
   const int l = b.l;
   const int m = *h.k;
   constexpr int NG = 256 / GL;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* A = LDS ? (T*)smem_raw : h.Zt;  // l x m, ld = l
-  __shared__ R s_nrm[2][512];  // double buffered: read at step j, written for step j + 1
-  __shared__ int s_sel[256];
-  __shared__ int s_pos[512];   // column -> skeleton position, or -1
-  __shared__ T s_rdiag[256];
+  T* A = LDS ? (T*)smem_raw : h.Zw;  // l x m, ld = l
+  __shared__ R s_nrm[2][MCAP];  // double buffered: read at step j, written for step j + 1
+  __shared__ int s_sel[KCAP];
+  __shared__ int s_pos[MCAP];   // column -> skeleton position, or -1
+  __shared__ T s_rdiag[KCAP];
   __shared__ int s_k;
+  __shared__ unsigned s_tm;
+  __shared__ unsigned long long s_key;
   const int tid = threadIdx.x, lane = tid & 63;
   const int gid = tid / GL, gl = tid % GL;
-  if (LDS)
-    for (int e = tid; e < l * m; e += 256) A[e] = h.Zt[e];
-  for (int c = tid; c < m; c += 256) s_pos[c] = -1;
-  __syncthreads();
-  for (int c0 = 0; c0 < m; c0 += NG) {
-    const int c = c0 + gid;
-    R s2 = 0;
-    if (c < m)
-      for (int r = gl; r < l; r += GL) s2 += traits<T>::abs2(A[r + (size_t)c * l]);
-    s2 = group_sum<GL>(s2);
-    if (c < m && gl == 0) s_nrm[0][c] = s2;
-  }
-  __syncthreads();
   const double thresh = b.tol_scale * sqrt(*b.nrm2) / sqrt(2.0 * (double)max(b.n_id, 1)) * sqrt((double)l);
   const int kcap = min(l, m);
-  unsigned chosen = 0;  // bit t: column lane + 64 t was a pivot (identical in every wave)
   int k = kcap;
-  for (int j = 0; j < kcap; ++j) {
-    R best = -1, tot = 0;
-    int bi = 0x7fffffff;
-    for (int t = 0; lane + 64 * t < m; ++t) {
-      if ((chosen >> t) & 1u) continue;
-      const int c = lane + 64 * t;
-      const R v = s_nrm[j & 1][c];
-      tot += v;
-      if (v > best) {
-        best = v;
-        bi = c;
+  float tm = 0.f;
+  for (int pass = 0, swaps = 0;; ++pass) {
+    const bool forced = pass > 0;  // pivot order given by s_sel
+    for (int e = tid; e < l * m; e += 256) A[e] = h.Zt[e];
+    for (int c = tid; c < m; c += 256) s_pos[c] = -1;
+    if (tid == 0) s_tm = 0u;
+    __syncthreads();
+    for (int c0 = 0; c0 < m; c0 += NG) {
+      const int c = c0 + gid;
+      R s2 = 0;
+      if (c < m)
+        for (int r = gl; r < l; r += GL) s2 += traits<T>::abs2(A[r + (size_t)c * l]);
+      s2 = group_sum<GL>(s2);
+      if (c < m && gl == 0) s_nrm[0][c] = s2;
+    }
+    __syncthreads();
+    unsigned chosen = 0;  // bit t: column lane + 64 t was a pivot (identical in every wave)
+    const int jend = forced ? k : kcap;
+    for (int j = 0; j < jend; ++j) {
+      int p;
+      if (!forced) {
+        R best = -1, tot = 0;
+        int bi = 0x7fffffff;
+        for (int t = 0; lane + 64 * t < m; ++t) {
+          if ((chosen >> t) & 1u) continue;
+          const int c = lane + 64 * t;
+          const R v = s_nrm[j & 1][c];
+          tot += v;
+          if (v > best) {
+            best = v;
+            bi = c;
+          }
+        }
+        tot = wave_sum(tot);
+        wave_argmax(best, bi);
+        if (sqrt((double)tot) <= thresh || bi >= m) {
+          k = j;
+          break;
+        }
+        p = bi;
+        if ((p & 63) == lane) chosen |= 1u << (p >> 6);
+        if (tid == 0) s_sel[j] = p;
+      } else {
+        p = s_sel[j];
       }
-    }
-    tot = wave_sum(tot);
-    wave_argmax(best, bi);
-    if (sqrt((double)tot) <= thresh || bi >= m) {
-      k = j;
-      break;
-    }
-    const int p = bi;
-    if ((p & 63) == lane) chosen |= 1u << (p >> 6);
-    if (tid == 0) {
-      s_sel[j] = p;
-      s_pos[p] = j;
-    }
-    // Householder reflector of column p (scalars in the factor's own precision)
-    const T x0 = A[j + (size_t)p * l];
-    const R xn2 = s_nrm[j & 1][p];
-    const R xn = sqrt(xn2);
-    const R a0 = sqrt(traits<T>::abs2(x0));
-    const R sc = a0 > 0 ? xn / a0 : R(0);
-    const T alpha = a0 > 0 ? traits<T>::mk(-traits<T>::re(x0) * sc, -traits<T>::im(x0) * sc)
-                           : traits<T>::mk(-xn, 0.0);
-    if (tid == 0) s_rdiag[j] = alpha;
-    const R vv = R(2) * xn2 + R(2) * a0 * xn;
-    const R f = vv > 0 ? R(2) / vv : R(0);
-    const T vj = x0 - alpha;
-    // this lane's rows r = j + gl + GL t of the reflector, in registers
-    T vr[RPL];
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int r = j + gl + GL * t;
-      vr[t] = r < l ? (r == j ? vj : A[r + (size_t)p * l]) : traits<T>::zero();
-    }
-    const int ncol_iter = (m + NG - 1) / NG;
-    for (int it = 0; it < ncol_iter; ++it) {
-      const int c = it * NG + gid;
-      // earlier pivots are in s_pos (written before the last barrier); p is this step's
-      const bool active = c < m && c != p && s_pos[c] < 0;
-      T ar[RPL];
-      R dre = 0, dim = 0;
+      if (tid == 0) s_pos[p] = j;
+      // Householder reflector of column p (scalars in the factor's own precision)
+      const T x0 = A[j + (size_t)p * l];
+      const R xn2 = s_nrm[j & 1][p];
+      const R xn = sqrt(xn2);
+      const R a0 = sqrt(traits<T>::abs2(x0));
+      const R sc = a0 > 0 ? xn / a0 : R(0);
+      const T alpha = a0 > 0 ? traits<T>::mk(-traits<T>::re(x0) * sc, -traits<T>::im(x0) * sc)
+                             : traits<T>::mk(-xn, 0.0);
+      if (tid == 0) s_rdiag[j] = alpha;
+      const R vv = R(2) * xn2 + R(2) * a0 * xn;
+      const R f = vv > 0 ? R(2) / vv : R(0);
+      const T vj = x0 - alpha;
+      // this lane's rows r = j + gl + GL t of the reflector, in registers
+      T vr[RPL];
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int r = j + gl + GL * t;
-        ar[t] = (active && r < l) ? A[r + (size_t)c * l] : traits<T>::zero();
-        const T pr = sc_mul(traits<T>::conj(vr[t]), ar[t]);
-        dre += traits<T>::re(pr);
-        dim += traits<T>::im(pr);
+        vr[t] = r < l ? (r == j ? vj : A[r + (size_t)p * l]) : traits<T>::zero();
       }
-      dre = group_sum<GL>(dre);
-      if (traits<T>::cplx) dim = group_sum<GL>(dim);
-      R s2 = 0;
-      if (active) {
-        const T fw = traits<T>::mk(dre * f, dim * f);
+      const int ncol_iter = (m + NG - 1) / NG;
+      for (int it = 0; it < ncol_iter; ++it) {
+        const int c = it * NG + gid;
+        // earlier pivots are in s_pos (written before the last barrier); p is this step's
+        const bool active = c < m && c != p && s_pos[c] < 0;
+        T ar[RPL];
+        R dre = 0, dim = 0;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
           const int r = j + gl + GL * t;
-          if (r < l) {
-            const T nv = sc_fms(ar[t], fw, vr[t]);
-            A[r + (size_t)c * l] = nv;
-            if (r > j) s2 += traits<T>::abs2(nv);
+          ar[t] = (active && r < l) ? A[r + (size_t)c * l] : traits<T>::zero();
+          const T pr = sc_mul(traits<T>::conj(vr[t]), ar[t]);
+          dre += traits<T>::re(pr);
+          dim += traits<T>::im(pr);
+        }
+        dre = group_sum<GL>(dre);
+        if (traits<T>::cplx) dim = group_sum<GL>(dim);
+        R s2 = 0;
+        if (active) {
+          const T fw = traits<T>::mk(dre * f, dim * f);
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const int r = j + gl + GL * t;
+            if (r < l) {
+              const T nv = sc_fms(ar[t], fw, vr[t]);
+              A[r + (size_t)c * l] = nv;
+              if (r > j) s2 += traits<T>::abs2(nv);
+            }
           }
         }
+        s2 = group_sum<GL>(s2);
+        if (active && gl == 0) s_nrm[(j + 1) & 1][c] = s2;
       }
-      s2 = group_sum<GL>(s2);
-      if (active && gl == 0) s_nrm[(j + 1) & 1][c] = s2;
+      __syncthreads();
     }
+    if (!forced) {
+      if (tid == 0) s_k = k;
+      __syncthreads();
+      k = s_k;
+    }
+    // T = R11^{-1} R12, one group per free column: back substitution in axpy form
+    // (x_i final -> broadcast -> subtract R(0:i, i) x_i); rows are spread over the lanes.
+    tm = 0.f;
+    for (int c0 = 0; c0 < m; c0 += NG) {
+      const int c = c0 + gid;
+      const bool act = c < m && s_pos[c] < 0;
+      T* col = A + (size_t)(act ? c : 0) * l;
+      for (int i = k - 1; i >= 0; --i) {
+        const int src = i % GL;
+        T xi = traits<T>::zero();
+        if (act && gl == src) {
+          const T d = s_rdiag[i];
+          xi = traits<T>::abs2(d) > 0 ? sc_mul(col[i], sc_inv(d)) : traits<T>::zero();
+          col[i] = xi;
+          tm = fmaxf(tm, (float)sqrt((double)traits<T>::abs2(xi)));
+        }
+        const R xr = __shfl(traits<T>::re(xi), src, GL);
+        const R xim = __shfl(traits<T>::im(xi), src, GL);
+        const T xv = traits<T>::mk(xr, xim);
+        if (act)
+          for (int r = gl; r < i; r += GL) col[r] = sc_fms(col[r], A[r + (size_t)s_sel[i] * l], xv);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) tm = fmaxf(tm, __shfl_xor(tm, off));
+    if (lane == 0) atomicMax(&s_tm, __float_as_uint(tm));  // non-negative: bit order = value order
+    if (tid == 0) s_key = 0ull;
+    __syncthreads();
+    tm = __uint_as_float(s_tm);
+    if (!(tm > 2.f) || swaps >= kMaxSwaps) break;
+    // the swap: largest |T(i, c)|, then the lowest i, then the lowest c
+    unsigned long long key = 0ull;
+    for (int e = tid; e < k * m; e += 256) {
+      const int i = e % k, c = e / k;
+      if (s_pos[c] >= 0) continue;
+      const float v = (float)sqrt((double)traits<T>::abs2(A[i + (size_t)c * l]));
+      const unsigned long long kk = ((unsigned long long)__float_as_uint(v) << 32) |
+                                    (unsigned long long)(~(unsigned)(i * MCAP + c));
+      key = kk > key ? kk : key;
+    }
+    atomicMax(&s_key, key);
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned idx = ~(unsigned)(s_key & 0xffffffffull);
+      s_sel[idx / MCAP] = (int)(idx % MCAP);
+    }
+    ++swaps;
     __syncthreads();
   }
-  if (tid == 0) s_k = k;
-  __syncthreads();
-  k = s_k;
-  // T = R11^{-1} R12, one group per free column: back substitution in axpy form
-  // (x_i final -> broadcast -> subtract R(0:i, i) x_i); rows are spread over the lanes.
-  float tm = 0.f;
-  for (int c0 = 0; c0 < m; c0 += NG) {
-    const int c = c0 + gid;
-    const bool act = c < m && s_pos[c] < 0;
-    T* col = A + (size_t)(act ? c : 0) * l;
-    for (int i = k - 1; i >= 0; --i) {
-      const int src = i % GL;
-      T xi = traits<T>::zero();
-      if (act && gl == src) {
-        const T d = s_rdiag[i];
-        xi = traits<T>::abs2(d) > 0 ? sc_mul(col[i], sc_inv(d)) : traits<T>::zero();
-        col[i] = xi;
-        tm = fmaxf(tm, (float)sqrt((double)traits<T>::abs2(xi)));
-      }
-      const R xr = __shfl(traits<T>::re(xi), src, GL);
-      const R xim = __shfl(traits<T>::im(xi), src, GL);
-      const T xv = traits<T>::mk(xr, xim);
-      if (act)
-        for (int r = gl; r < i; r += GL) col[r] = sc_fms(col[r], A[r + (size_t)s_sel[i] * l], xv);
-    }
-  }
-  __syncthreads();
   // U (m x k, ld zcap): row sel[i] = e_i, free row c = T(:, c)^T
   for (int e = tid; e < m * k; e += 256) {
     const int c = e % m, i = e / m;
@@ -397,8 +446,7 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
     h.U[c + (size_t)i * h.zcap] = v;
   }
   for (int i = tid; i < k; i += 256) h.skel[i] = h.cand[s_sel[i]];
-  for (int off = 32; off > 0; off >>= 1) tm = fmaxf(tm, __shfl_xor(tm, off));
-  if (lane == 0) atomicMax((int*)b.tmax, __float_as_int(tm));
+  if (tid == 0) atomicMax((int*)b.tmax, __float_as_int(tm));
   __syncthreads();
   if (tid == 0) {
     *h.k = k;

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <string>
+#include <type_traits>
 
 #include "../../include/hss.h"
 #include "common.hpp"
@@ -13,29 +14,26 @@
 
 namespace hss {
 
-// Arithmetic of the pivot search: single precision for double-precision matrices
-// (gj_panel_rot_kernel explains why the pivot order needs no more).
-template <class X> struct Search { using type = X; };
-template <> struct Search<double> { using type = float; };
-template <> struct Search<cd> { using type = cf; };
-
+// Panel shapes held in registers: 16 columns (8 for complex double, whose values
+// take four registers each), up to four rows per thread on 128, 256 or 512
+// threads, and for single precision up to eight rows per thread. The pivot search
+// runs in the matrix's own precision.
 template <class X>
 bool panel_rot_config(int rows, PanelShape& s) {
-  // 16-column panels, up to four rows per thread
+  const int nb = std::is_same<X, cd>::value ? 8 : 16;
   if (rows <= 128) {
-    s = {16, 1, 128};
+    s = {nb, 1, 128};
     return true;
   }
   if (rows <= 256 * 4) {
-    s = {16, (rows + 255) / 256, 256};
+    s = {nb, (rows + 255) / 256, 256};
     return true;
   }
   if (rows <= 512 * 4) {
-    s = {16, (rows + 511) / 512, 512};
+    s = {nb, (rows + 511) / 512, 512};
     return true;
   }
-  // real types search in single precision: up to eight rows per thread
-  if (!traits<X>::cplx && rows <= 512 * 8) {
+  if (std::is_same<X, float>::value && rows <= 512 * 8) {
     const int rpt = (rows + 511) / 512;
     s = {16, rpt <= 6 ? 6 : 8, 512};
     return true;
@@ -45,16 +43,21 @@ bool panel_rot_config(int rows, PanelShape& s) {
 
 template <class X>
 void launch_panel_rot(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelShape& s, hipStream_t st) {
-  using S = typename Search<X>::type;
 #define HSS_ROT(NB_, RPT_, NT_)                                                      \
   if (s.nb == NB_ && s.rpt == RPT_ && s.nt == NT_) {                                 \
-    gj_panel_rot_kernel<X, NB_, RPT_, NT_, S><<<nn, NT_, 0, st>>>(dd, j0, nb);       \
+    gj_panel_rot_kernel<X, NB_, RPT_, NT_><<<nn, NT_, 0, st>>>(dd, j0, nb);          \
     return;                                                                          \
   }
-  HSS_ROT(16, 1, 128)
-  HSS_ROT(16, 1, 256) HSS_ROT(16, 2, 256) HSS_ROT(16, 3, 256) HSS_ROT(16, 4, 256)
-  HSS_ROT(16, 3, 512) HSS_ROT(16, 4, 512)
-  if constexpr (!traits<X>::cplx) {
+  if constexpr (std::is_same<X, cd>::value) {
+    HSS_ROT(8, 1, 128)
+    HSS_ROT(8, 1, 256) HSS_ROT(8, 2, 256) HSS_ROT(8, 3, 256) HSS_ROT(8, 4, 256)
+    HSS_ROT(8, 3, 512) HSS_ROT(8, 4, 512)
+  } else {
+    HSS_ROT(16, 1, 128)
+    HSS_ROT(16, 1, 256) HSS_ROT(16, 2, 256) HSS_ROT(16, 3, 256) HSS_ROT(16, 4, 256)
+    HSS_ROT(16, 3, 512) HSS_ROT(16, 4, 512)
+  }
+  if constexpr (std::is_same<X, float>::value) {
     HSS_ROT(16, 6, 512) HSS_ROT(16, 8, 512)
   }
 #undef HSS_ROT

@@ -348,3 +348,23 @@ def debug_gj(mats, ns, ms, block=0, stream=None):
                           (C.c_int32 * k)(*ns), (C.c_int32 * k)(*ms), int(block), C.byref(sing),
                           C.c_void_p(_stream_ptr(stream))))
     return sing.value
+
+
+def debug_row_id(Z, thresh, p_os=10, stream=None):
+    """Row ID of a CUDA tensor Z (m x l, row-major) as the compression computes it
+    for one HSS node. Returns (k, skeleton indices, U (m x k, numpy), max |T|)."""
+    import torch
+    L = lib()
+    L.hss_debug_row_id.restype = C.c_int
+    m, l = Z.shape
+    Zc = Z.contiguous()
+    kc = min(l, m)
+    U = torch.empty((kc, m), dtype=Z.dtype, device=Z.device)  # column-major m x kc
+    k = C.c_int32(0)
+    skel = (C.c_int32 * m)()
+    tm = C.c_float(0)
+    _check(L.hss_debug_row_id(_scalar_code(Z), C.c_void_p(Zc.data_ptr()), m, l, C.c_double(thresh), p_os,
+                              C.byref(k), skel, C.c_void_p(U.data_ptr()), C.byref(tm),
+                              C.c_void_p(_stream_ptr(stream))))
+    kk = k.value
+    return kk, np.array(skel[:kk], dtype=np.int64), U.cpu().numpy().T[:, :kk], tm.value

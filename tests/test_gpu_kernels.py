@@ -1,6 +1,7 @@
 """Kernel-level GPU checks through the C ABI (hss_debug.h): the batched MFMA
 GEMM and the batched Gauss-Jordan elimination against NumPy on ragged,
-multi-tile shapes for every scalar type."""
+multi-tile shapes for every scalar type, and the row ID of one HSS node
+against the oracle's (including the strong-RRQR swaps on Kahan's matrix)."""
 import numpy as np
 import pytest
 
@@ -76,9 +77,9 @@ GJ_CASES = [(name, 0, ((1, 3), (7, 0), (33, 20), (100, 45), (200, 230))) for nam
 GJ_CASES += [(name, 32, ((1, 3), (7, 0), (33, 20), (100, 45), (200, 230))) for name in DT]
 GJ_CASES += [("float64", 0, ((600, 70), (530, 0), (40, 9))), ("complex64", 0, ((600, 70), (530, 0), (40, 9))),
              ("float32", 100, ((450, 30), (129, 1))),
-             # tall real panels (six and eight rows per thread, single-precision pivot search)
+             # tall double panels (beyond the register-resident kernel)
              ("float64", 0, ((2600, 10), (3900, 0))),
-             # complex double at root sizes (single-precision search, 256 and 512 threads)
+             # complex double at root sizes (8-column panels, 256 and 512 threads)
              ("complex128", 0, ((1152, 20), (900, 0))),
              ("float32", 0, ((2000, 5), (1030, 3)))]
 
@@ -122,23 +123,132 @@ def test_gauss_jordan_needs_pivoting_and_flags_singular():
 
 
 def test_gauss_jordan_near_ties_in_double():
-    """Double-precision panels pick pivots on a single-precision copy: rows whose
-    moduli agree to single precision (a relative gap of 1e-12) may be taken in either
-    order, and the inverse is still exact to double-precision rounding."""
+    """Columns whose two largest candidates differ by a relative 1e-12 after the
+    earlier updates: either order is a valid partial-pivoting choice and the inverse
+    is exact to double-precision rounding."""
     rng = np.random.default_rng(21)
     n = 300
-    base = rng.standard_normal((n, n))
-    A = base.copy()
-    # every column gets a near-tie: two rows whose entries differ by a factor 1 + 1e-12,
-    # both larger than the rest of the column
+    A = rng.standard_normal((n, n))
+    # a near-tie in every column between two rows larger than the rest of the column;
+    # no diagonal shift, so the pair stays the column maximum through the updates
     for j in range(n):
         r1, r2 = rng.choice(n, 2, replace=False)
-        big = 10.0 + rng.random()
+        big = 1e3 * (10.0 + rng.random())
         A[r1, j] = big
         A[r2, j] = -big * (1.0 + 1e-12)
-    A += np.sqrt(n) * np.eye(n)
     M = _dev(A, torch.float64)
     assert hss.debug_gj([M], [n], [0]) == 0
     Ainv = np.linalg.inv(A)
     err = np.abs(M.cpu().numpy().T - Ainv).max() / np.abs(Ainv).max()
     assert err <= 1e-13 * np.linalg.cond(A) * 50, err
+
+
+def test_gauss_jordan_double_cancellation_is_not_singular():
+    """After the first elimination step the second column's entry in row 1 cancels
+    exactly in double precision (3x - (x/2) 6 = 0) but not in single precision; a
+    nonsingular matrix (cond ~ 3e10) must not be reported singular."""
+    x = 1.0 + 2.0 ** -24 + 2.0 ** -26
+    A = np.array([[2.0, 6.0, 0.0], [x, 3.0 * x, 1.0], [0.0, 1e-9, 1.0]])
+    for name in ("float64", "complex128"):
+        npdt, tdt, tol = DT[name]
+        M = _dev(A.astype(npdt), tdt)
+        assert hss.debug_gj([M], [3], [0]) == 0, name
+        Ainv = np.linalg.inv(A)
+        err = np.abs(M.cpu().numpy().T - Ainv).max() / np.abs(Ainv).max()
+        assert err <= 1e-13 * np.linalg.cond(A), (name, err)
+
+
+@pytest.mark.parametrize("scale", [1e-25, 1e20])
+def test_gauss_jordan_scaled_double_blocks(scale):
+    """Pivot order and elimination of double blocks far outside single precision's
+    range of squared moduli: the inverse scales exactly."""
+    rng = np.random.default_rng(23)
+    sizes = ((40, 3), (300, 0), (1100, 4))
+    for name in ("float64", "complex128"):
+        npdt, tdt, tol = DT[name]
+        mats, refs = [], []
+        for n, m in sizes:
+            A = _rand(rng, (n, n), npdt)
+            B = _rand(rng, (n, m), npdt)
+            mats.append(_dev(np.concatenate([A, B], axis=1) * scale, tdt))
+            A64 = A.astype(np.complex128)
+            refs.append((np.linalg.inv(A64) / scale, np.linalg.solve(A64, B.astype(np.complex128)),
+                         np.linalg.cond(A64)))
+        assert hss.debug_gj(mats, [s[0] for s in sizes], [s[1] for s in sizes]) == 0
+        for (n, m), Md, (Ainv, X, cond) in zip(sizes, mats, refs):
+            got = Md.cpu().numpy().T
+            e1 = np.abs(got[:, :n] - Ainv).max() / np.abs(Ainv).max()
+            assert e1 <= tol * cond * 50, (name, n, e1)
+            if m:
+                e2 = np.abs(got[:, n:] - X).max() / np.abs(X).max()
+                assert e2 <= tol * cond * 50, (name, n, e2)
+
+
+def _kahan(n, c, cplx=False):
+    s = np.sqrt(1 - c * c)
+    R = np.triu(-c * np.ones((n, n)), 1) + np.eye(n)
+    if cplx:
+        ph = np.exp(1j * 0.7 * np.subtract.outer(np.arange(n), np.arange(n)))
+        R = np.where(np.eye(n, dtype=bool), 1.0, R * ph)
+    return np.diag(s ** np.arange(n)) @ R @ np.diag((1 - 1e-6) ** np.arange(n))
+
+
+ROWID_CASES = [("float64", 10, 0.6, 9), ("complex128", 10, 0.6, 9), ("float64", 30, 0.285, 29),
+               ("complex128", 24, 0.5, 20), ("float32", 10, 0.6, 9), ("complex64", 10, 0.6, 9)]
+
+
+@pytest.mark.parametrize("name,n,c,k", ROWID_CASES)
+def test_row_id_swaps_match_oracle_on_kahan(name, n, c, k):
+    """Column pivoting alone leaves |T| far above 2 on Kahan's matrix; the kernel's
+    swaps must give the oracle's skeleton and interpolation matrix (|T| <= 2)."""
+    import scipy.linalg as sla
+    from oracle import hss as ohss
+    npdt, tdt, tol = DT[name]
+    print(f"row id kahan {name} n={n} k={k}", flush=True)
+    cplx = np.issubdtype(npdt, np.complexfloating)
+    C = _kahan(n, c, cplx)
+    Z = C.T.copy()
+    _, R, _ = sla.qr(C, mode="economic", pivoting=True)
+    thr = 0.5 * (np.linalg.norm(R[k:, k:]) + np.linalg.norm(R[k - 1:, k - 1:]))
+    ref = ohss.row_id(Z, thr, n)
+    assert ref.k == k and ref.swaps >= 1
+    kk, skel, U, tmax = hss.debug_row_id(torch.from_numpy(Z.astype(npdt)).cuda(), thr, p_os=0)
+    assert kk == k
+    assert tmax <= 2.0
+    assert np.abs(U).max() <= 2.0 + 1e-5
+    assert np.allclose(U[skel, np.arange(k)], 1.0, atol=0)
+    if npdt in (np.float64, np.complex128):
+        # same skeleton set: the interpolation matrices agree (up to the skeleton order)
+        assert sorted(skel.tolist()) == sorted(ref.skel.tolist())
+        order = [list(skel).index(j) for j in ref.skel]
+        assert np.abs(U[:, order] - ref.U).max() <= 1e-10
+    else:
+        # single precision may settle on another skeleton with |T| <= 2; its error is
+        # that of a rank-k ID of Z
+        e = np.linalg.norm(Z - U @ Z[skel])
+        assert e <= 4.0 * ref.resid + 1e-5 * np.linalg.norm(Z)
+
+
+@pytest.mark.parametrize("name", ["float32", "complex64", "float64"])
+def test_row_id_random_low_rank_matches_oracle(name):
+    """A sampled low-rank block as the compression sees it (more candidates than
+    samples, and a wide sample above 256 columns): same rank, the same skeleton and
+    an interpolation error equal to the oracle's within the precision."""
+    from oracle import hss as ohss
+    npdt, tdt, tol = DT[name]
+    cplx = np.issubdtype(npdt, np.complexfloating)
+    rng = np.random.default_rng(31)
+    for m, l, r in ((90, 40, 12), (300, 320, 60), (700, 400, 150)):
+        print(f"row id random {name} m={m} l={l} r={r}", flush=True)
+        G = rng.standard_normal((m, r)) * np.logspace(0, -7, r)[None, :]
+        H = rng.standard_normal((r, l))
+        if cplx:
+            G = G + 1j * rng.standard_normal((m, r)) * np.logspace(0, -7, r)[None, :]
+        Z = (G @ H).astype(npdt)
+        thr = 1e-4 * np.linalg.norm(Z)
+        ref = ohss.row_id(Z.astype(np.complex128 if cplx else np.float64), thr, l)
+        kk, skel, U, tmax = hss.debug_row_id(torch.from_numpy(Z).cuda(), thr, p_os=10)
+        assert abs(kk - ref.k) <= (0 if npdt == np.float64 else 1), (m, kk, ref.k)
+        assert tmax <= 2.0
+        e = np.linalg.norm(Z - U @ Z[skel]) / np.linalg.norm(Z)
+        assert e <= max(2.0 * ref.resid / np.linalg.norm(Z), 1e-5), (m, e)
