@@ -200,6 +200,19 @@ hss_status_t hss_mlp_grad(const float* weights, const float* x, const float* tar
 hss_status_t hss_mlp_train(float* weights, const float* x, const float* target, int32_t n,
                            int32_t steps, float lr, float* loss_hist, void* hip_stream);
 
+/* hss_mlp_grad_noalloc -- hss_mlp_grad without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc). The gradient pass keeps its
+ * activations and partial terms in a fixed device array of the library
+ * (HSS_MLP_NOALLOC_MAX_N samples, about 8.5 MB, held on every device the library
+ * runs on until the process ends); grad and loss are as in hss_mlp_grad.
+ * Returns HSS_EINVAL for n < 1 or n > HSS_MLP_NOALLOC_MAX_N. Every call on one
+ * device uses the same array, so calls that overlap on one device (other
+ * streams, other threads) race; serialize them. */
+#define HSS_MLP_NOALLOC_MAX_N 8192
+hss_status_t hss_mlp_grad_noalloc(const float* weights, const float* x, const float* target, int32_t n,
+                                  float* grad, double* loss, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,6 +19,9 @@ void mlp_forward(const float* w, const float* x, int n, float* y, hipStream_t st
 void mlp_grad(const float* w, const float* x, const float* t, int n, float* grad, double* loss, hipStream_t st);
 void mlp_train(float* w, const float* x, const float* t, int n, int steps, float lr, float* loss_hist,
                hipStream_t st);
+void mlp_grad_noalloc(const float* w, const float* x, const float* t, int n, float* grad, double* loss,
+                      hipStream_t st);
+int mlp_noalloc_max_n();
 }  // namespace hss
 
 struct hss_ctx {
@@ -277,6 +280,19 @@ hss_status_t hss_mlp_grad(const float* w, const float* x, const float* t, int32_
     if (!w || !x || !t || !grad || !loss || n < 1) return fail(HSS_EINVAL, "bad mlp arguments");
     ensure_device();
     hss::mlp_grad(w, x, t, n, grad, loss, (hipStream_t)stream);
+    return HSS_OK;
+  });
+}
+
+hss_status_t hss_mlp_grad_noalloc(const float* w, const float* x, const float* t, int32_t n, float* grad,
+                                  double* loss, void* stream) {
+  return guarded([&]() -> hss_status_t {
+    if (!w || !x || !t || !grad || !loss || n < 1) return fail(HSS_EINVAL, "bad mlp arguments");
+    if (n > HSS_MLP_NOALLOC_MAX_N || n > hss::mlp_noalloc_max_n())
+      return fail(HSS_EINVAL, "hss_mlp_grad_noalloc takes at most " + std::to_string(HSS_MLP_NOALLOC_MAX_N) +
+                                  " samples");
+    ensure_device();
+    hss::mlp_grad_noalloc(w, x, t, n, grad, loss, (hipStream_t)stream);
     return HSS_OK;
   });
 }

@@ -1,7 +1,12 @@
 // Rank-predictor MLP entry points (forward, gradient, Adam training).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+#include <string>
 #include <vector>
+
+#include "../../include/hss.h"
 
 #include "common.hpp"
 #include "k_mlp.hpp"
@@ -9,15 +14,19 @@
 namespace hss {
 
 namespace {
-struct MlpWork {
-  float *a1, *a2, *dz1, *dz2, *dy, *r2, *y, *grad, *m, *v, *loss;
-  std::vector<void*> owned;
-  explicit MlpWork(int n, bool adam) {
+// Device buffers of one gradient pass (activations, back-propagated terms, the
+// prediction, the gradient, the loss) and, for training, Adam's moments.
+struct MlpBufs {
+  float *a1 = nullptr, *a2 = nullptr, *dz1 = nullptr, *dz2 = nullptr, *dy = nullptr, *r2 = nullptr,
+        *y = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr, *loss = nullptr;
+  // carve the buffers for n samples out of consecutive floats starting at base
+  // (returns the floats used); grad may point elsewhere
+  size_t carve(float* base, int n, bool adam) {
+    size_t off = 0;
     auto get = [&](size_t cnt) {
-      void* p = nullptr;
-      HIP_CHECK(hipMalloc(&p, std::max<size_t>(cnt, 1) * sizeof(float)));
-      owned.push_back(p);
-      return (float*)p;
+      float* p = base + off;
+      off += (std::max<size_t>(cnt, 1) + 63) & ~size_t(63);  // 256-byte aligned pieces
+      return p;
     };
     a1 = get((size_t)n * MLP_H);
     a2 = get((size_t)n * MLP_H);
@@ -30,18 +39,54 @@ struct MlpWork {
     loss = get(1);
     m = adam ? get(MLP_NP) : nullptr;
     v = adam ? get(MLP_NP) : nullptr;
-  }
-  ~MlpWork() {
-    for (void* p : owned) (void)hipFree(p);
+    return off;
   }
 };
+// the buffers in one device allocation of the library
+struct MlpWork : MlpBufs {
+  void* mem = nullptr;
+  MlpWork(int n, bool adam) {
+    const size_t floats = carve(nullptr, n, adam);
+    HIP_CHECK(hipMalloc(&mem, floats * sizeof(float)));
+    carve((float*)mem, n, adam);
+  }
+  ~MlpWork() {
+    if (mem) (void)hipFree(mem);
+  }
+};
+
+// The allocation-free gradient keeps its buffers in a fixed device array: the
+// gradient pass for up to kMlpNoAllocMaxN samples. The array's device address is
+// looked up once per device (hipGetSymbolAddress, with that device current) and
+// kept; host code uses only that address, never the array's name.
+constexpr int kMlpNoAllocMaxN = 8192;
+constexpr size_t kMlpScratchFloats = 4 * ((size_t)kMlpNoAllocMaxN * MLP_H + 64) + 3 * ((size_t)kMlpNoAllocMaxN + 64) +
+                                     (MLP_NP + 64) + 64;
+__device__ __align__(256) float scratch[kMlpScratchFloats];
+std::mutex g_scratch_mu;
+std::vector<float*> g_scratch_ptr;  // per device ordinal
+
+float* scratch_address() {
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error(HSS_EDEVICE, std::string("device address of the MLP scratch array: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (float*)p;
+  }
+  return g_scratch_ptr[dev];
+}
 
 void check(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(-5, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-void grad_pass(const float* w, const float* x, const float* t, int n, MlpWork& wk, hipStream_t st) {
+void grad_pass(const float* w, const float* x, const float* t, int n, const MlpBufs& wk, hipStream_t st) {
   const int blocks = (n + 255) / 256;
   mlp_forward_kernel<<<blocks, 256, 0, st>>>(w, x, n, wk.a1, wk.a2, wk.y);
   check("mlp_forward");
@@ -64,6 +109,26 @@ void mlp_grad(const float* w, const float* x, const float* t, int n, float* grad
   MlpWork wk(n, false);
   grad_pass(w, x, t, n, wk, st);
   HIP_CHECK(hipMemcpyAsync(grad, wk.grad, sizeof(float) * MLP_NP, hipMemcpyDeviceToDevice, st));
+  float l = 0;
+  HIP_CHECK(hipMemcpyAsync(&l, wk.loss, sizeof(float), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  *loss = l;
+}
+
+int mlp_noalloc_max_n() { return kMlpNoAllocMaxN; }
+
+// The gradient of mlp_grad with every buffer in the fixed device array: no device
+// allocation. Calls on one device share the array, so calls that overlap on one
+// device race; the kernels overwrite every buffer they read, nothing needs clearing.
+void mlp_grad_noalloc(const float* w, const float* x, const float* t, int n, float* grad, double* loss,
+                      hipStream_t st) {
+  if (n > kMlpNoAllocMaxN)
+    throw Error(HSS_EINVAL, "hss_mlp_grad_noalloc takes at most " + std::to_string(kMlpNoAllocMaxN) + " samples");
+  MlpBufs wk;
+  const size_t used = wk.carve(scratch_address(), n, false);
+  if (used > kMlpScratchFloats) throw Error(HSS_EINVAL, "MLP scratch array too small");
+  wk.grad = grad;  // the caller's output
+  grad_pass(w, x, t, n, wk, st);
   float l = 0;
   HIP_CHECK(hipMemcpyAsync(&l, wk.loss, sizeof(float), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));

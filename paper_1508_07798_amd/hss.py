@@ -23,7 +23,7 @@ MLP_NPARAMS = 4801
 
 EXPORTS = ["hss_default_opts", "hss_factor", "hss_factor_batched", "hss_apply", "gmres_solve", "hss_query",
            "hss_destroy", "hss_last_error", "hss_plan_create", "hss_plan_query", "hss_plan_destroy",
-           "hss_mlp_forward", "hss_mlp_grad", "hss_mlp_train"]
+           "hss_mlp_forward", "hss_mlp_grad", "hss_mlp_train", "hss_mlp_grad_noalloc"]
 
 
 class BlockOp(C.Structure):
@@ -87,6 +87,8 @@ def lib():
         L.hss_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.hss_mlp_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                    C.POINTER(C.c_double), C.c_void_p]
+        L.hss_mlp_grad_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                           C.POINTER(C.c_double), C.c_void_p]
         L.hss_mlp_train.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_float,
                                     C.c_void_p, C.c_void_p]
         _lib = L
@@ -293,6 +295,18 @@ def mlp_grad(w, x, t, stream=None):
     _check(lib().hss_mlp_grad(w.data_ptr(), x.contiguous().data_ptr(), t.contiguous().data_ptr(), x.shape[0],
                               g.data_ptr(), C.byref(loss), _stream_ptr(stream)))
     return g, loss.value
+
+
+MLP_NOALLOC_MAX_N = 8192
+
+
+def mlp_grad_noalloc(w, x, t, grad, stream=None):
+    """hss_mlp_grad_noalloc: the gradient into the caller's tensor ``grad``
+    (MLP_NPARAMS floats on the device); the library allocates nothing. Returns the loss."""
+    loss = C.c_double(0)
+    _check(lib().hss_mlp_grad_noalloc(w.data_ptr(), x.contiguous().data_ptr(), t.contiguous().data_ptr(),
+                                      x.shape[0], grad.data_ptr(), C.byref(loss), _stream_ptr(stream)))
+    return loss.value
 
 
 def mlp_train(w, x, t, steps, lr=1e-2, stream=None):
