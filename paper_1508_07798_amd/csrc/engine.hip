@@ -310,6 +310,7 @@ template <class T> struct Engine : EngineBase {
   // largest sample count of the randomized ID (a box whose ID needs more rows keeps
   // its dense complement once its attempts are spent)
   static constexpr int kLcapMax = 512;
+  int* d_sing_ = nullptr;  // per box (then per root): 1 if a pivot was exactly zero
   double tol = 0;
   Prof prof;
   Pinned keep;  // pinned host staging, reused after each sync
@@ -581,6 +582,11 @@ template <class T> struct Engine : EngineBase {
       c.nb = c.ps.nb;
       return c;
     }
+    // Complex panels taller than the compact kernel holds are not run (the panel
+    // paths for them are switched off): such boxes are refused.
+    if (traits<X>::cplx)
+      throw Error(HSS_EUNSUPPORTED, "complex Gauss-Jordan panels of " + std::to_string(rmax) +
+                                        " rows are not supported (at most 2048)");
     // register-resident panel when the tallest panel fits: rows per thread (rpt) and
     // panel width (nb) from a budget of 192 registers for the panel values
     const int words = sX / 4;
@@ -742,6 +748,94 @@ template <class T> struct Engine : EngineBase {
     }
   }
 
+  // ---------------------------------------------------------------- one wave
+  // Gather, Gauss-Jordan elimination of the interiors and Schur update of the
+  // boxes of one wave (arithmetic X = T).
+  template <class X, class Lap>
+  void eliminate_wave(const std::vector<int>& wv, const std::vector<T*>& Sp, Arena& tmp, Lap& lap) {
+    const size_t nw = wv.size();
+    std::vector<X*> Mp(nw), Ap(nw), Sx(nw);
+    for (size_t i = 0; i < nw; ++i) {
+      Mp[i] = nd[wv[i]].G;
+      Ap[i] = nd[wv[i]].Abi;
+      Sx[i] = Sp[i];
+    }
+    // 1. gather
+    {
+      std::vector<GatherDesc<T>> gd(nw);
+      int64_t maxe = 0;
+      for (size_t i = 0; i < nw; ++i) {
+        const PNode& n = P.nodes[wv[i]];
+        const PProblem& pr = P.probs[n.prob];
+        GatherDesc<T>& g = gd[i];
+        g.ni = (int)n.idof.size();
+        g.nb = (int)n.bdof.size();
+        g.gidx = nd[wv[i]].gidx;
+        g.src = nd[wv[i]].src;
+        g.st[0] = n.leaf ? nullptr : nd[n.child[0]].St;
+        g.st[1] = n.leaf ? nullptr : nd[n.child[1]].St;
+        g.nbc[0] = n.leaf ? 0 : (int)P.nodes[n.child[0]].bdof.size();
+        g.nbc[1] = n.leaf ? 0 : (int)P.nodes[n.child[1]].bdof.size();
+        g.el_off = pr.el_off;
+        g.dof_off = pr.dof_off;
+        maxe = std::max<int64_t>(maxe, (int64_t)(g.ni + g.nb) * (g.ni + g.nb));
+      }
+      auto* dgd = up(gd, tmp);
+      auto* dM = up(Mp, tmp);
+      auto* dA = up(Ap, tmp);
+      auto* dS = up(Sx, tmp);
+      OpDev op{d_row_ptr, d_col_idx, d_vals, q};
+      double gby = 0;
+      for (auto& g : gd) {
+        const double e = (double)g.ni * (g.ni + g.nb) + (double)g.nb * g.ni + (double)g.nb * g.nb;
+        gby += e * (sizeof(X) + (g.st[0] ? sizeof(T) : sizeof(W)));
+      }
+      int id = prof.start(C_GATHER, 0, gby);
+      fl();
+      gather_kernel<X, W, T><<<dim3(grid1(maxe, 512), (unsigned)nw), 256, 0, st>>>(op, dgd, dM, dA, dS);
+      prof.stop(id);
+      check_launch("gather");
+    }
+    // 2. Gauss-Jordan on [A_ii | A_ib]
+    {
+      std::vector<GjDesc<X>> gj;
+      for (size_t i = 0; i < nw; ++i) {
+        const PNode& n = P.nodes[wv[i]];
+        if (n.idof.empty()) continue;
+        GjDesc<X> g{};
+        g.M = Mp[i];
+        g.n = (int)n.idof.size();
+        g.W = (int)(n.idof.size() + n.bdof.size());
+        g.rowperm = nd[wv[i]].rowperm;
+        g.flag = d_sing_ + wv[i];
+        gj.push_back(g);
+      }
+      lap(2);
+      gauss_jordan<X>(gj, tmp);
+      lap(3);
+    }
+    // 3. Schur update S = A_bb - A_bi X
+    {
+      std::vector<GemmDesc> gd;
+      for (size_t i = 0; i < nw; ++i) {
+        const PNode& n = P.nodes[wv[i]];
+        const int ni = (int)n.idof.size(), nbd = (int)n.bdof.size();
+        if (ni == 0 || nbd == 0) continue;
+        gd.push_back({Ap[i], Mp[i] + (size_t)ni * ni, Sx[i], nbd, nbd, ni, nbd, ni, nbd});
+      }
+      if constexpr (std::is_same<X, float>::value) {
+        if (o.prec == HSS_PREC_BF16) {
+          run_gemm_bf16(prep_gemm<X>(gd, tmp), -1.f, 1.f, C_SCHUR);
+        } else {
+          gemm<X>(gd, traits<X>::mk(-1.0, 0.0), traits<X>::one(), C_SCHUR, tmp);
+        }
+      } else {
+        gemm<X>(gd, traits<X>::mk(-1.0, 0.0), traits<X>::one(), C_SCHUR, tmp);
+      }
+    }
+    lap(4);
+  }
+
   // ---------------------------------------------------------------- factor
   void factor(const hss_block_op_t* A, double tol_) override {
     auto t0 = std::chrono::high_resolution_clock::now();
@@ -803,6 +897,7 @@ template <class T> struct Engine : EngineBase {
     flops_factor = 0;
     host_wait_ms = 0;
     int* d_sing = persist.get<int>(nn + nprob + 1);
+    d_sing_ = d_sing;
     HIP_CHECK(hipMemsetAsync(d_sing, 0, sizeof(int) * (nn + nprob + 1), st));
     lap(0);
     // features need the diagonal-block norms: computed on the host copy if available
@@ -818,7 +913,7 @@ template <class T> struct Engine : EngineBase {
       tmp.st = st;
       // S and S~ buffers
       // S lives for the wave; S~ until the parents are assembled (with tol = 0, S~ = S)
-      std::vector<T*> Sp(wv.size()), Mp(wv.size()), Ap(wv.size());
+      std::vector<T*> Sp(wv.size());
       for (size_t i = 0; i < wv.size(); ++i) {
         const PNode& n = P.nodes[wv[i]];
         const size_t nbd = std::max<size_t>(n.bdof.size() * n.bdof.size(), 1);
@@ -829,83 +924,8 @@ template <class T> struct Engine : EngineBase {
           Sp[i] = stA.get<T>(nbd);
           nd[wv[i]].St = Sp[i];
         }
-        Mp[i] = nd[wv[i]].G;
-        Ap[i] = nd[wv[i]].Abi;
       }
-      // 1. gather
-      {
-        std::vector<GatherDesc<T>> gd(wv.size());
-        int64_t maxe = 0;
-        for (size_t i = 0; i < wv.size(); ++i) {
-          const PNode& n = P.nodes[wv[i]];
-          const PProblem& pr = P.probs[n.prob];
-          GatherDesc<T>& g = gd[i];
-          g.ni = (int)n.idof.size();
-          g.nb = (int)n.bdof.size();
-          g.gidx = nd[wv[i]].gidx;
-          g.src = nd[wv[i]].src;
-          g.st[0] = n.leaf ? nullptr : nd[n.child[0]].St;
-          g.st[1] = n.leaf ? nullptr : nd[n.child[1]].St;
-          g.nbc[0] = n.leaf ? 0 : (int)P.nodes[n.child[0]].bdof.size();
-          g.nbc[1] = n.leaf ? 0 : (int)P.nodes[n.child[1]].bdof.size();
-          g.el_off = pr.el_off;
-          g.dof_off = pr.dof_off;
-          maxe = std::max<int64_t>(maxe, (int64_t)(g.ni + g.nb) * (g.ni + g.nb));
-        }
-        auto* dgd = up(gd, tmp);
-        auto* dM = up(Mp, tmp);
-        auto* dA = up(Ap, tmp);
-        auto* dS = up(Sp, tmp);
-        OpDev op{d_row_ptr, d_col_idx, d_vals, q};
-        double gby = 0;
-        for (auto& g : gd) {
-          const double e = (double)g.ni * (g.ni + g.nb) + (double)g.nb * g.ni + (double)g.nb * g.nb;
-          gby += e * (sizeof(T) + (g.st[0] ? sizeof(T) : sizeof(W)));
-        }
-        int id = prof.start(C_GATHER, 0, gby);
-        fl();
-        gather_kernel<T, W, T><<<dim3(grid1(maxe, 512), (unsigned)wv.size()), 256, 0, st>>>(op, dgd, dM, dA, dS);
-        prof.stop(id);
-        check_launch("gather");
-      }
-      // 2. Gauss-Jordan on [A_ii | A_ib]
-      {
-        std::vector<GjDesc<T>> gj;
-        for (size_t i = 0; i < wv.size(); ++i) {
-          const PNode& n = P.nodes[wv[i]];
-          if (n.idof.empty()) continue;
-          GjDesc<T> g{};
-          g.M = nd[wv[i]].G;
-          g.n = (int)n.idof.size();
-          g.W = (int)(n.idof.size() + n.bdof.size());
-          g.rowperm = nd[wv[i]].rowperm;
-          g.flag = d_sing + wv[i];
-          gj.push_back(g);
-        }
-        lap(2);
-        gauss_jordan<T>(gj, tmp);
-        lap(3);
-      }
-      // 3. Schur update S = A_bb - A_bi X
-      {
-        std::vector<GemmDesc> gd;
-        for (size_t i = 0; i < wv.size(); ++i) {
-          const PNode& n = P.nodes[wv[i]];
-          const int ni = (int)n.idof.size(), nbd = (int)n.bdof.size();
-          if (ni == 0 || nbd == 0) continue;
-          gd.push_back({nd[wv[i]].Abi, nd[wv[i]].G + (size_t)ni * ni, Sp[i], nbd, nbd, ni, nbd, ni, nbd});
-        }
-        if constexpr (std::is_same<T, float>::value) {
-          if (o.prec == HSS_PREC_BF16) {
-            run_gemm_bf16(prep_gemm<T>(gd, tmp), -1.f, 1.f, C_SCHUR);
-          } else {
-            gemm<T>(gd, traits<T>::mk(-1.0, 0.0), traits<T>::one(), C_SCHUR, tmp);
-          }
-        } else {
-          gemm<T>(gd, traits<T>::mk(-1.0, 0.0), traits<T>::one(), C_SCHUR, tmp);
-        }
-      }
-      lap(4);
+      eliminate_wave<T>(wv, Sp, tmp, lap);
       // 4. compression
       compress_wave(wv, Sp, tmp);
       drop(tmp);
