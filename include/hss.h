@@ -103,6 +103,10 @@ typedef struct {
                               order of the hss_query "prof." classes            */
   int32_t apply_graph;     /* 1 (default): the apply sweeps run as a captured HIP
                               graph, one per right-hand-side count; 0: eager      */
+  int32_t hss_leaf_elems;  /* leaves of the HSS tree over a box's boundary: at most
+                              this many elements (0: the default, 4)               */
+  const char* rank_model_path; /* weights file written by hss_rank_model_train, read
+                              when rank_model is NULL (NULL: no file)            */
 } hss_opts_t;
 
 typedef struct {
@@ -112,7 +116,8 @@ typedef struct {
   int32_t status;      /* HSS_OK or HSS_ENOCONV                  */
 } hss_gmres_info_t;
 
-/* Fill *o with the defaults (FP32, p_os 10, l0 32, 8 attempts, seed 1508). */
+/* Fill *o with the defaults (FP32, p_os 10, l0 32, 8 attempts, seed 1508, HSS
+ * leaves of 4 elements). */
 void hss_default_opts(hss_opts_t* o);
 
 /* hss_factor -- build the preconditioner of one operator (Algorithm 2 plus
@@ -136,27 +141,37 @@ hss_status_t hss_factor_batched(int32_t nprob, const hss_block_op_t* A, const hs
                                 double tol, const hss_opts_t* o, hss_handle_t* out);
 
 /* hss_apply -- y = M^{-t} D^{-1} L^{-1} x (end of Section 3.2) for nrhs
- * columns. x, y: device arrays of FP64 (complex128 for complex operators),
- * leading dimensions ldx, ldy >= total dofs. x and y may not overlap. */
+ * columns. x, y: arrays of FP64 (complex128 for complex operators), leading
+ * dimensions ldx, ldy >= total dofs, in the caller's dof order; x and y may not
+ * overlap. on_device = 1: device arrays (work queued on the handle's stream,
+ * returns after it); 0: host arrays (copied to the device and back). */
 hss_status_t hss_apply(hss_handle_t h, int32_t nrhs, const void* x, int64_t ldx, void* y,
-                       int64_t ldy);
+                       int64_t ldy, int32_t on_device);
 
 /* gmres_solve -- right-preconditioned restarted GMRES(restart) in FP64 on the
- * device for every (problem, column) system. b, x: device arrays [ld x nrhs];
- * x holds the initial guess on entry and the solution on exit. info: host
- * array [nprob * nrhs] (problem-major). Stops a system when its rotated
+ * device for every (problem, column) system. b, x: arrays [ld x nrhs], device
+ * arrays if on_device = 1, host arrays (copied both ways) if 0; x holds the
+ * initial guess on entry and the solution on exit (x = 0 for a zero b). info:
+ * host array [nprob * nrhs] (problem-major). Stops a system when its rotated
  * residual and then its true residual are <= tol. Returns HSS_ENOCONV if any
  * system missed tol within maxit Arnoldi steps (x holds the last iterate). */
 hss_status_t gmres_solve(hss_handle_t h, int32_t nrhs, const void* b, void* x, int64_t ld,
-                         double tol, int32_t restart, int32_t maxit, hss_gmres_info_t* info);
+                         double tol, int32_t restart, int32_t maxit, int32_t on_device,
+                         hss_gmres_info_t* info);
 
 /* hss_query -- read a diagnostic of the handle into out[0..cap).
  * *len receives the number of values the key has (also when cap is smaller).
  * Keys: "n" (total dofs), "nprob", "nnodes", "nwaves", "max_err", "ranks"
  * (largest ID rank per box), "attempts" (per box), "l" (final sample count per
- * box), "err" (per box judge error), "node_heap" / "node_prob" / "node_ni" /
- * "node_nb" (per box), "features" (8 per box), "fallbacks", "retries",
- * "flops_factor", "bytes_apply", "bytes_spmv", "time_factor_ms", "host_wait_ms"
+ * box), "l_init" (first sample count per box: l0, or the rank model's size), "err" (per box judge error), "node_heap" / "node_prob" / "node_ni" /
+ * "node_nb" (per box), "features" (8 per box), "tmax" (per box, largest
+ * |interpolation coefficient|), "fallbacks", "retries",
+ * "flops_factor" (the method's work by formula, real flops, complex x4: LU
+ * (2/3) n_i^3 + triangular solves 2 n_i^2 n_b + Schur product 2 n_b^2 n_i per box,
+ * the root's LU, and the sampling and truncated QR of every compression attempt
+ * from the ranks chosen), "flops_factor_parts" (those six terms), "flops_gj" (the
+ * work of the explicit Gauss-Jordan form the library executes),
+ * "bytes_apply", "bytes_spmv", "time_factor_ms", "host_wait_ms"
  * (time the factorization spent waiting for the device at its sync points),
  * "phase_ms" (8 values: host wall time of operator upload, features, gather,
  * Gauss-Jordan, Schur GEMM, compression, root, apply set-up),
@@ -173,14 +188,16 @@ const char* hss_last_error(void);
 
 /* ---- host-only planning (no GPU needed) --------------------------------
  * hss_plan_create runs the planner of hss_factor (boundary / interior sets,
- * orderings, height waves, HSS trees) on the host and keeps the result for
+ * orderings, height waves, HSS trees with leaves of at most hss_leaf_elems
+ * elements, 0 for the default 4) on the host and keeps the result for
  * inspection. hss_plan_query keys, per box `node` (heap id):
  *   "idof" / "bdof"  I^ (interior) and B (boundary) dofs in factor order,
  *   "hss"            HSS tree as (lo, hi, left, right) quadruples, post-order,
  *                    left/right = -1 for leaves,
  *   "height"         wave index;
  * and with node = 1: "root" (the dofs of the root block). Values are int64. */
-hss_status_t hss_plan_create(const hss_block_op_t* A, const hss_tree_t* T, hss_plan_t* out);
+hss_status_t hss_plan_create(const hss_block_op_t* A, const hss_tree_t* T, int32_t hss_leaf_elems,
+                             hss_plan_t* out);
 hss_status_t hss_plan_query(hss_plan_t p, const char* key, int32_t node, int64_t* out,
                             int64_t cap, int64_t* len);
 void hss_plan_destroy(hss_plan_t p);
@@ -199,6 +216,16 @@ hss_status_t hss_mlp_grad(const float* weights, const float* x, const float* tar
                           float* grad, double* loss, void* hip_stream);
 hss_status_t hss_mlp_train(float* weights, const float* x, const float* target, int32_t n,
                            int32_t steps, float lr, float* loss_hist, void* hip_stream);
+
+/* hss_rank_model_train -- train the rank predictor on (features, rank) samples
+ * and write its weights to out_path, a file that hss_opts_t.rank_model_path can
+ * name. feat: host [n x 8] row-major (the "features" of hss_query), rank: host
+ * [n] (the "ranks" of the same boxes). Weights start N(0, 1/fan_in) from a
+ * stream keyed by seed; 1500 full-batch Adam steps on the device (learning rate
+ * 3e-3) fit log2(1 + rank). HSS_EINVAL for non-finite inputs or an unwritable
+ * path. File layout: "HSSMLP01", int32 count, count float32 (little-endian). */
+hss_status_t hss_rank_model_train(const float* feat, const float* rank, int32_t n, const char* out_path,
+                                  uint64_t seed);
 
 /* hss_mlp_grad_noalloc -- hss_mlp_grad without any device allocation, for
  * callers that cannot allocate (code under HIP graph capture, tight serving or

@@ -60,11 +60,11 @@ class NodeFactor:
 
 class OracleFactor:
     def __init__(self, op, tree, tol: float, seed: int = 1508, l0: int = 32,
-                 l_init: dict | None = None, symmetrize: bool = True):
+                 l_init: dict | None = None, symmetrize: bool = True, hss_leaf_elems: int = 4):
         self.op = op
         self.tol = tol
         self.seed = seed
-        self.sets = TreeSets(op.row_ptr, op.col_idx, op.q, tree)
+        self.sets = TreeSets(op.row_ptr, op.col_idx, op.q, tree, hss_leaf_elems)
         self.A = csr_of(op)
         self.cplx = op.is_complex
         self.nodes: dict[int, NodeFactor] = {}

@@ -83,24 +83,25 @@ def perimeter_key(ix, iy, x0, x1, y0, y1):
     raise ValueError("boundary element not on the box perimeter")
 
 
-def _bisect(lo_e: int, hi_e: int, q: int) -> HssNode:
+def _bisect(lo_e: int, hi_e: int, q: int, leaf: int = HSS_LEAF_ELEMS) -> HssNode:
     node = HssNode(lo_e * q, hi_e * q)
-    if hi_e - lo_e > HSS_LEAF_ELEMS:
+    if hi_e - lo_e > leaf:
         mid = lo_e + (hi_e - lo_e) // 2
-        node.left = _bisect(lo_e, mid, q)
-        node.right = _bisect(mid, hi_e, q)
+        node.left = _bisect(lo_e, mid, q, leaf)
+        node.right = _bisect(mid, hi_e, q, leaf)
     return node
 
 
-def hss_tree(m_elems: int, m_top: int, q: int) -> HssNode:
+def hss_tree(m_elems: int, m_top: int, q: int, leaf: int = HSS_LEAF_ELEMS) -> HssNode:
     """HSS tree over m_elems boundary elements whose first m_top form the run
-    that joins the parent's interior (m_top in {0, m_elems} means no top split)."""
+    that joins the parent's interior (m_top in {0, m_elems} means no top split);
+    leaves of at most ``leaf`` elements."""
     if 0 < m_top < m_elems:
         root = HssNode(0, m_elems * q)
-        root.left = _bisect(0, m_top, q)
-        root.right = _bisect(m_top, m_elems, q)
+        root.left = _bisect(0, m_top, q, leaf)
+        root.right = _bisect(m_top, m_elems, q, leaf)
         return root
-    return _bisect(0, m_elems, q)
+    return _bisect(0, m_elems, q, leaf)
 
 
 def hss_postorder(t: HssNode) -> list:
@@ -118,8 +119,9 @@ def hss_postorder(t: HssNode) -> list:
 class TreeSets:
     """All sets of the box tree for one operator (structure only)."""
 
-    def __init__(self, row_ptr, col_idx, q, tree):
+    def __init__(self, row_ptr, col_idx, q, tree, hss_leaf_elems: int = HSS_LEAF_ELEMS):
         self.q = int(q)
+        self.hss_leaf = int(hss_leaf_elems)
         n_el = len(row_ptr) - 1
         self.n_el = n_el
         self.nbrs = [[int(c) for c in col_idx[row_ptr[e]:row_ptr[e + 1]] if c != e]
@@ -202,7 +204,7 @@ class TreeSets:
                       n_parent_interior=m_top if parent != 1 else len(b),
                       idof=np.zeros(0, dtype=np.int64), bdof=self._dofs(b),
                       height=self.height[s])
-        ns.hss = hss_tree(len(b), m_top if parent != 1 else 0, self.q)
+        ns.hss = hss_tree(len(b), m_top if parent != 1 else 0, self.q, self.hss_leaf)
         if ns.is_leaf:
             ns.idof = self._dofs([e for e in es if e not in self.bset[s]])
         return ns

@@ -21,10 +21,13 @@ void mlp_train(float* w, const float* x, const float* t, int n, int steps, float
                hipStream_t st);
 void mlp_grad_noalloc(const float* w, const float* x, const float* t, int n, float* grad, double* loss,
                       hipStream_t st);
+std::vector<float> mlp_read(const char* path);
+void rank_model_train(const float* feat, const float* rank, int n, const char* path, uint64_t seed);
 int mlp_noalloc_max_n();
 }  // namespace hss
 
 struct hss_ctx {
+  std::vector<float> model;  // rank-model weights read from opts.rank_model_path
   std::unique_ptr<hss::EngineBase> eng;
 };
 struct hss_plan_ctx {
@@ -89,9 +92,9 @@ PlanCache& plan_cache() {
   return c;
 }
 // Visit the structure arrays in a fixed order (the caller has checked the pointers).
-template <class F> void visit_structure(int nprob, const hss_block_op_t* A, const hss_tree_t* T, F&& f) {
-  const int32_t head[1] = {nprob};
-  f(head, 1);
+template <class F> void visit_structure(int nprob, const hss_block_op_t* A, const hss_tree_t* T, int leaf, F&& f) {
+  const int32_t head[2] = {nprob, leaf};
+  f(head, 2);
   for (int p = 0; p < nprob; ++p) {
     const hss_block_op_t& a = A[p];
     const hss_tree_t& t = T[p];
@@ -105,20 +108,20 @@ template <class F> void visit_structure(int nprob, const hss_block_op_t* A, cons
     f(t.elem_xy, 2 * (size_t)a.n_el);
   }
 }
-std::shared_ptr<const hss::Plan> plan_for(int nprob, const hss_block_op_t* A, const hss_tree_t* T) {
+std::shared_ptr<const hss::Plan> plan_for(int nprob, const hss_block_op_t* A, const hss_tree_t* T, int leaf) {
   bool ok = nprob >= 1 && A && T;
   for (int p = 0; ok && p < nprob; ++p)
     ok = A[p].n_el >= 2 && A[p].row_ptr && A[p].col_idx && A[p].vals && T[p].n_leaves >= 2 && T[p].leaf_node &&
          T[p].leaf_ptr && T[p].leaf_elems && T[p].elem_xy && A[p].row_ptr[A[p].n_el] >= 0 &&
          T[p].leaf_ptr[T[p].n_leaves] == A[p].n_el;
-  if (!ok) return std::make_shared<const hss::Plan>(hss::make_plan(nprob, A, T));  // reports the error
+  if (!ok) return std::make_shared<const hss::Plan>(hss::make_plan(nprob, A, T, leaf));  // reports the error
   PlanCache& c = plan_cache();
   {
     std::lock_guard<std::mutex> lk(c.mu);
     if (c.plan) {
       size_t off = 0;
       bool same = true;
-      visit_structure(nprob, A, T, [&](const int32_t* v, size_t n) {
+      visit_structure(nprob, A, T, leaf, [&](const int32_t* v, size_t n) {
         if (!same) return;
         same = off + n <= c.key.size() && std::memcmp(c.key.data() + off, v, n * sizeof(int32_t)) == 0;
         off += n;
@@ -126,9 +129,9 @@ std::shared_ptr<const hss::Plan> plan_for(int nprob, const hss_block_op_t* A, co
       if (same && off == c.key.size()) return c.plan;
     }
   }
-  auto plan = std::make_shared<const hss::Plan>(hss::make_plan(nprob, A, T));
+  auto plan = std::make_shared<const hss::Plan>(hss::make_plan(nprob, A, T, leaf));
   std::vector<int32_t> key;
-  visit_structure(nprob, A, T, [&](const int32_t* v, size_t n) { key.insert(key.end(), v, v + n); });
+  visit_structure(nprob, A, T, leaf, [&](const int32_t* v, size_t n) { key.insert(key.end(), v, v + n); });
   std::lock_guard<std::mutex> lk(c.mu);
   c.key = std::move(key);
   c.plan = plan;
@@ -151,6 +154,8 @@ void hss_default_opts(hss_opts_t* o) {
   o->hip_stream = nullptr;
   o->profile = 0;
   o->apply_graph = 1;
+  o->hss_leaf_elems = 4;
+  o->rank_model_path = nullptr;
 }
 
 const char* hss_last_error(void) { return g_err.c_str(); }
@@ -164,13 +169,19 @@ hss_status_t hss_factor_batched(int32_t nprob, const hss_block_op_t* A, const hs
     hss_opts_t opts;
     hss_default_opts(&opts);
     if (o) opts = *o;
-    if (opts.p_os < 1 || opts.l0 < 1 || opts.max_attempts < 1) return fail(HSS_EINVAL, "bad options");
+    if (opts.p_os < 1 || opts.l0 < 1 || opts.max_attempts < 1 || opts.hss_leaf_elems < 0)
+      return fail(HSS_EINVAL, "bad options");
+    const int leaf = opts.hss_leaf_elems > 0 ? opts.hss_leaf_elems : 4;
     if (opts.prec != HSS_PREC_FP64 && opts.prec != HSS_PREC_FP32 && opts.prec != HSS_PREC_BF16)
       return fail(HSS_EINVAL, "unknown precision");
-    std::shared_ptr<const hss::Plan> plan = plan_for(nprob, A, T);
+    std::shared_ptr<const hss::Plan> plan = plan_for(nprob, A, T, leaf);
     for (int p = 0; p < nprob; ++p) check_finite_host(A[p]);
     ensure_device();
     std::unique_ptr<hss_ctx> h(new hss_ctx);
+    if (!opts.rank_model && opts.rank_model_path) {
+      h->model = hss::mlp_read(opts.rank_model_path);
+      opts.rank_model = h->model.data();
+    }
     h->eng = hss::make_engine(std::move(plan), opts, A[0].dtype == HSS_C128);
     h->eng->factor(A, tol);
     *out = h.release();
@@ -183,21 +194,22 @@ hss_status_t hss_factor(const hss_block_op_t* A, const hss_tree_t* T, double tol
   return hss_factor_batched(1, A, T, tol, o, out);
 }
 
-hss_status_t hss_apply(hss_handle_t h, int32_t nrhs, const void* x, int64_t ldx, void* y, int64_t ldy) {
+hss_status_t hss_apply(hss_handle_t h, int32_t nrhs, const void* x, int64_t ldx, void* y, int64_t ldy,
+                       int32_t on_device) {
   return guarded([&]() -> hss_status_t {
     if (!h || !h->eng) return fail(HSS_EINVAL, "null handle");
-    h->eng->apply(nrhs, x, ldx, y, ldy);
+    h->eng->apply(nrhs, x, ldx, y, ldy, on_device != 0);
     return HSS_OK;
   });
 }
 
 hss_status_t gmres_solve(hss_handle_t h, int32_t nrhs, const void* b, void* x, int64_t ld, double tol,
-                         int32_t restart, int32_t maxit, hss_gmres_info_t* info) {
+                         int32_t restart, int32_t maxit, int32_t on_device, hss_gmres_info_t* info) {
   return guarded([&]() -> hss_status_t {
     if (!h || !h->eng) return fail(HSS_EINVAL, "null handle");
     if (!info) return fail(HSS_EINVAL, "info is null");
     if (!(tol > 0)) return fail(HSS_EINVAL, "tol must be > 0");
-    int s = h->eng->gmres(nrhs, b, x, ld, tol, restart, maxit, info);
+    int s = h->eng->gmres(nrhs, b, x, ld, tol, restart, maxit, on_device != 0, info);
     if (s != HSS_OK) return fail(s, "GMRES did not reach the tolerance within maxit");
     return HSS_OK;
   });
@@ -221,12 +233,14 @@ void hss_destroy(hss_handle_t h) {
   }
 }
 
-hss_status_t hss_plan_create(const hss_block_op_t* A, const hss_tree_t* T, hss_plan_t* out) {
+hss_status_t hss_plan_create(const hss_block_op_t* A, const hss_tree_t* T, int32_t hss_leaf_elems,
+                             hss_plan_t* out) {
   if (out) *out = nullptr;
   return guarded([&]() -> hss_status_t {
     if (!out) return fail(HSS_EINVAL, "out is null");
+    if (hss_leaf_elems < 0) return fail(HSS_EINVAL, "HSS leaf size must be >= 0");
     std::unique_ptr<hss_plan_ctx> p(new hss_plan_ctx);
-    p->plan = hss::make_plan(1, A, T);
+    p->plan = hss::make_plan(1, A, T, hss_leaf_elems > 0 ? hss_leaf_elems : 4);
     *out = p.release();
     return HSS_OK;
   });
@@ -360,6 +374,16 @@ hss_status_t hss_debug_row_id(int32_t scalar, const void* Zt, int32_t m, int32_t
       return fail(HSS_EINVAL, "row id sizes out of range");
     ensure_device();
     hss::debug_row_id(scalar, Zt, m, l, thresh, p_os, k, skel, U, tmax, (hipStream_t)hip_stream);
+    return HSS_OK;
+  });
+}
+
+hss_status_t hss_rank_model_train(const float* feat, const float* rank, int32_t n, const char* out_path,
+                                  uint64_t seed) {
+  return guarded([&]() -> hss_status_t {
+    if (!feat || !rank || !out_path || n < 1) return fail(HSS_EINVAL, "bad rank model arguments");
+    ensure_device();
+    hss::rank_model_train(feat, rank, n, out_path, seed);
     return HSS_OK;
   });
 }

@@ -254,6 +254,12 @@ struct Prof {
     if (id < 0) return;
     HIP_CHECK(hipEventRecord(recs[id].b, st));
   }
+  // algorithmic work of a timed launch that is only known after it ran
+  void set_work(int id, double fl, double by) {
+    if (id < 0) return;
+    recs[id].flops = fl;
+    recs[id].bytes = by;
+  }
   void collect() {
     if (!on || recs.empty()) return;
     HIP_CHECK(hipStreamSynchronize(st));
@@ -343,11 +349,13 @@ template <class T> struct Engine : EngineBase {
   std::vector<RootDev> rt;
 
   // diagnostics
-  std::vector<int> rank_v, attempts_v, l_v;
+  std::vector<int> rank_v, attempts_v, l_v, l_init_v;
   std::vector<double> err_v;
   std::vector<float> tmax_v;
   int fallbacks = 0, retries = 0;
   double flops_factor = 0, time_factor_ms = 0, host_wait_ms = 0;
+  // algorithmic work of the compression (all attempts), real flops
+  double alg_sample = 0, alg_cpqr = 0;
   double phase_ms[8] = {};
   std::vector<float> feat_v;
 
@@ -582,10 +590,10 @@ template <class T> struct Engine : EngineBase {
       c.nb = c.ps.nb;
       return c;
     }
-    // Complex panels taller than the compact kernel holds are not run (the panel
-    // paths for them are switched off): such boxes are refused.
-    if (traits<X>::cplx)
-      throw Error(HSS_EUNSUPPORTED, "complex Gauss-Jordan panels of " + std::to_string(rmax) +
+    // Single-precision complex panels taller than the compact kernel holds are not
+    // run (that path is switched off): such boxes are refused.
+    if (std::is_same<X, cf>::value)
+      throw Error(HSS_EUNSUPPORTED, "complex64 Gauss-Jordan panels of " + std::to_string(rmax) +
                                         " rows are not supported (at most 2048)");
     // register-resident panel when the tallest panel fits: rows per thread (rpt) and
     // panel width (nb) from a budget of 192 registers for the panel values
@@ -748,6 +756,35 @@ template <class T> struct Engine : EngineBase {
     }
   }
 
+  // ---------------------------------------------------------------- input check
+  // Every value finite, and A(e, f) = A(f, e)^T to 1e-12 of the largest entry: the
+  // compression takes the column bases equal to the row bases (V = U), which needs
+  // symmetric (or complex-symmetric) complements. Checked on the device, so that
+  // device-resident values are covered as well as host ones.
+  void validate_values(const PlanFlat& F) {
+    Arena t;
+    t.st = st;
+    int32_t* dt = up(F.tblk, t);
+    unsigned long long* dout = t.get<unsigned long long>(3);
+    HIP_CHECK(hipMemsetAsync(dout, 0, 3 * sizeof(unsigned long long), st));
+    fl();
+    const int64_t tot = nnzb * (int64_t)q * q;
+    validate_kernel<W><<<grid1(tot, 1024), 256, 0, st>>>(d_vals, dt, nnzb, q, dout);
+    check_launch("validate");
+    const unsigned long long* h = d2h_pinned(dout, 3);
+    sync();
+    unsigned long long hv[3];
+    std::memcpy(hv, h, sizeof(hv));
+    drop(t);
+    double amax, dmax;
+    std::memcpy(&amax, &hv[0], sizeof(double));
+    std::memcpy(&dmax, &hv[1], sizeof(double));
+    if (hv[2]) throw Error(HSS_EINVAL, "operator holds " + std::to_string(hv[2]) + " non-finite value(s)");
+    if (dmax > 1e-12 * amax)
+      throw Error(HSS_EUNSUPPORTED, "operator values are not symmetric: max |A(e,f) - A(f,e)^T| = " +
+                                        std::to_string(dmax) + " against max |A| = " + std::to_string(amax));
+  }
+
   // ---------------------------------------------------------------- one wave
   // Gather, Gauss-Jordan elimination of the interiors and Schur update of the
   // boxes of one wave (arithmetic X = T).
@@ -869,6 +906,7 @@ template <class T> struct Engine : EngineBase {
         HIP_CHECK(hipMemcpyAsync(d_vals + (size_t)pr.blk_off * blk, A[p].vals, nb_p * blk * sizeof(W), kind, st));
       }
       d_perm = up(F.perm, persist);
+      validate_values(F);
     }
     // per box index data and factor storage
     const int nn = (int)P.nodes.size();
@@ -891,10 +929,12 @@ template <class T> struct Engine : EngineBase {
     rank_v.assign(nn, 0);
     attempts_v.assign(nn, 0);
     l_v.assign(nn, 0);
+    l_init_v.assign(nn, 0);
     err_v.assign(nn, 0.0);
     tmax_v.assign(nn, 0.f);
     fallbacks = retries = 0;
     flops_factor = 0;
+    alg_sample = alg_cpqr = 0;
     host_wait_ms = 0;
     int* d_sing = persist.get<int>(nn + nprob + 1);
     d_sing_ = d_sing;
@@ -981,7 +1021,9 @@ template <class T> struct Engine : EngineBase {
       auto* dgd = up(gd, tmp);
       auto* dR = up(Rp, tmp);
       OpDev op{d_row_ptr, d_col_idx, d_vals, q};
-      int id = prof.start(C_ROOT, 0, 0);
+      double rby = 0;
+      for (int p = 0; p < nprob; ++p) rby += (double)rt[p].n * rt[p].n * (sizeof(W) + sizeof(T));
+      int id = prof.start(C_ROOT, 0, rby);
       fl();
       gather_kernel<W, W, T><<<dim3(grid1(maxe, 512), (unsigned)nprob), 256, 0, st>>>(op, dgd, dR, nullptr, nullptr);
       prof.stop(id);
@@ -1180,6 +1222,7 @@ template <class T> struct Engine : EngineBase {
       todo.push_back(i);
       int lcap = std::min(all[i].n + o.p_os, kLcapMax);
       lcur[i] = std::min(std::max(predicted_l(wv[i]), 4), lcap);
+      l_init_v[wv[i]] = lcur[i];
     }
     // the norms are read at the first judge sync (no wait here)
     std::vector<double> nrm(nb_boxes, 0.0);
@@ -1192,6 +1235,7 @@ template <class T> struct Engine : EngineBase {
       const int na = (int)todo.size();
       std::vector<CompBox<T>> bx(na);
       std::vector<HssDesc<T>> hs;
+      std::vector<int> hs_height;
       std::vector<std::vector<int>> byh;
       std::vector<int> leaves;
       std::vector<HTile> tiles;
@@ -1204,6 +1248,9 @@ template <class T> struct Engine : EngineBase {
       int64_t maxe = 0, maxol = 0;
       int lmax = 0;
       std::vector<GemmDesc> yg;
+      size_t nhs_all = 0;
+      for (int a = 0; a < na; ++a) nhs_all += P.nodes[wv[todo[a]]].hss.size();
+      int* d_kall = at.get<int>(std::max<size_t>(nhs_all, 1));  // rank of every HSS node
       for (int a = 0; a < na; ++a) {
         const int i = todo[a];
         const PNode& n = P.nodes[wv[i]];
@@ -1243,7 +1290,7 @@ template <class T> struct Engine : EngineBase {
             const int kc = std::min(l, d.zcap);
             d.cand = at.get<int>(d.zcap);
             d.skel = at.get<int>(d.zcap);
-            d.k = at.get<int>(1);
+            d.k = d_kall + base + (int)t;
             d.Zt = at.get<T>((size_t)l * d.zcap);
             d.U = at.get<T>((size_t)d.zcap * kc);
             d.Ut = at.get<T>((size_t)width * kc);
@@ -1252,6 +1299,7 @@ template <class T> struct Engine : EngineBase {
           }
           if (hn.left < 0) leaves.push_back(base + (int)t);
           hs.push_back(d);
+          hs_height.push_back(hn.height);
         }
       }
       // expand tiles (need the right child's width)
@@ -1283,6 +1331,8 @@ template <class T> struct Engine : EngineBase {
       std::vector<HTile*> d_stl(nh, nullptr), d_utl(nh, nullptr);
       std::vector<unsigned> n_stl(nh, 0), n_utl(nh, 0);
       std::vector<double> sfl(nh, 0.0);
+      std::vector<int> rec_sample(nh, -1), rec_id(nh, -1), rec_utall(nh, -1);
+      int rec_expand = -1;
       for (int hh = 0; hh < nh; ++hh) {
         if (byh[hh].empty()) continue;
         d_lvl[hh] = up(byh[hh], at);
@@ -1317,24 +1367,28 @@ template <class T> struct Engine : EngineBase {
       for (int hh = 0; hh < nh; ++hh) {
         if (byh[hh].empty()) continue;
         int id = prof.start(C_SAMPLE, sfl[hh], 0);
+        rec_sample[hh] = id;
         fl();
         if (zmax[hh] <= 512) sample_kernel<T, 512><<<n_stl[hh], 256, 0, st>>>(dbx, dhs, d_stl[hh]);
         else sample_kernel<T, 1024><<<n_stl[hh], 256, 0, st>>>(dbx, dhs, d_stl[hh]);
         prof.stop(id);
         check_launch("sample");
         id = prof.start(C_ID, 0, 0);
+        rec_id[hh] = id;
         cpqr_launch(dbx, dhs, d_lvl[hh], (unsigned)byh[hh].size(), lmax, zmax[hh], in_lds[hh], o.p_os);
         prof.stop(id);
       }
       for (int hh = 0; hh < nh; ++hh) {
         if (byh[hh].empty()) continue;
         int id = prof.start(C_UTALL, 0, 0);
+        rec_utall[hh] = id;
         utall_kernel<T><<<n_utl[hh], 256, 0, st>>>(dbx, dhs, d_utl[hh]);
         prof.stop(id);
         check_launch("utall");
       }
       {
         int id = prof.start(C_EXPAND, 0, 0);
+        rec_expand = id;
         diag_copy_kernel<T><<<(unsigned)leaves.size(), 256, 0, st>>>(dbx, dhs, d_leaves);
         check_launch("diag_copy");
         if (!tiles.empty()) {
@@ -1349,7 +1403,45 @@ template <class T> struct Engine : EngineBase {
       }
       const double* h_err = d2h_pinned(d_err, na);
       const int* h_flh = d2h_pinned(d_flags, 3 * na);
+      const int* h_k = d2h_pinned(d_kall, nhs_all);
       sync();
+      // algorithmic work of this attempt from the ranks the IDs chose (real flops;
+      // a complex multiply-add counts 8): samples Z of every HSS node, the truncated
+      // Householder QR and T = R11^-1 R12, the tall bases, and the expansion
+      {
+        const double mac = Flop<T>::mac, qrf = CX ? 4.0 : 1.0;
+        std::vector<double> wz(nh, 0.0), wq(nh, 0.0), wu(nh, 0.0);
+        double we = 0;
+        for (size_t t = 0; t < hs.size(); ++t) {
+          const HssDesc<T>& d = hs[t];
+          if (!d.k) continue;  // the HSS root carries no ID
+          const int hh = hs_height[t];
+          const double l = bx[d.box].l, width = d.hi - d.lo, k = h_k[t];
+          const double m = d.left < 0 ? width : (double)h_k[d.left] + h_k[d.right];
+          wz[hh] += mac * m * width * l;
+          wq[hh] += qrf * (4.0 * l * m * k - 2.0 * (l + m) * k * k + (4.0 / 3.0) * k * k * k + 2.0 * k * k * (m - k));
+          if (d.left >= 0) {
+            const double na_ = hs[d.left].hi - hs[d.left].lo, nb_ = hs[d.right].hi - hs[d.right].lo;
+            wu[hh] += mac * (na_ * h_k[d.left] + nb_ * h_k[d.right]) * k;
+          }
+        }
+        for (size_t t = 0; t < hs.size(); ++t) {
+          const HssDesc<T>& d = hs[t];
+          if (d.left < 0) continue;
+          const double ka = h_k[d.left], kc = h_k[d.right];
+          const double na_ = hs[d.left].hi - hs[d.left].lo, nc = hs[d.right].hi - hs[d.right].lo;
+          we += mac * (ka * kc * nc + na_ * ka * nc);
+        }
+        for (int hh = 0; hh < nh; ++hh) {
+          prof.set_work(rec_sample[hh], wz[hh], 0);
+          prof.set_work(rec_id[hh], wq[hh], 0);
+          prof.set_work(rec_utall[hh], wu[hh], 0);
+          alg_sample += wz[hh];
+          alg_cpqr += wq[hh];
+        }
+        prof.set_work(rec_expand, we, 0);
+        for (auto& b : bx) alg_sample += mac * (double)b.n * b.n * b.l;  // Y = S Omega
+      }
       // pinned results stay valid until the next staging request
       std::vector<double> err(h_err, h_err + na);
       std::vector<int> flh(h_flh, h_flh + 3 * na);
@@ -1528,9 +1620,24 @@ template <class T> struct Engine : EngineBase {
     return b;
   }
 
-  void apply(int nrhs, const void* x, int64_t ldx, void* y, int64_t ldy) override {
+  void apply(int nrhs, const void* x, int64_t ldx, void* y, int64_t ldy, bool on_device) override {
     if (nrhs < 1 || ldx < ntot || ldy < ntot || !x || !y) throw Error(HSS_EINVAL, "bad apply arguments");
-    apply_dev(nrhs, (const W*)x, ldx, (W*)y, ldy);
+    if (on_device) {
+      apply_dev(nrhs, (const W*)x, ldx, (W*)y, ldy);
+    } else {
+      // host vectors: staged through device buffers (the copies cross PCIe)
+      Arena hv;
+      hv.st = st;
+      W* dx = hv.get<W>((size_t)ntot * nrhs);
+      W* dy = hv.get<W>((size_t)ntot * nrhs);
+      HIP_CHECK(hipMemcpy2DAsync(dx, ntot * sizeof(W), x, ldx * sizeof(W), ntot * sizeof(W), nrhs,
+                                 hipMemcpyHostToDevice, st));
+      apply_dev(nrhs, dx, ntot, dy, ntot);
+      HIP_CHECK(hipMemcpy2DAsync(y, ldy * sizeof(W), dy, ntot * sizeof(W), ntot * sizeof(W), nrhs,
+                                 hipMemcpyDeviceToHost, st));
+      sync();
+      drop(hv);
+    }
     sync();
     prof.collect();
   }
@@ -1544,10 +1651,27 @@ template <class T> struct Engine : EngineBase {
     check_launch("spmv");
   }
 
-  int gmres(int nrhs, const void* bv, void* xv, int64_t ld, double gtol, int m, int maxit,
+  int gmres(int nrhs, const void* bv, void* xv, int64_t ld, double gtol, int m, int maxit, bool on_device,
             hss_gmres_info_t* info) override {
     if (nrhs < 1 || ld < ntot || !bv || !xv || m < 1 || maxit < 1)
       throw Error(HSS_EINVAL, "bad gmres arguments");
+    if (!on_device) {
+      // host vectors: b and the initial guess go to device buffers, x comes back
+      Arena hv;
+      hv.st = st;
+      W* db = hv.get<W>((size_t)ntot * nrhs);
+      W* dx = hv.get<W>((size_t)ntot * nrhs);
+      HIP_CHECK(hipMemcpy2DAsync(db, ntot * sizeof(W), bv, ld * sizeof(W), ntot * sizeof(W), nrhs,
+                                 hipMemcpyHostToDevice, st));
+      HIP_CHECK(hipMemcpy2DAsync(dx, ntot * sizeof(W), xv, ld * sizeof(W), ntot * sizeof(W), nrhs,
+                                 hipMemcpyHostToDevice, st));
+      const int status = gmres(nrhs, db, dx, ntot, gtol, m, maxit, true, info);
+      HIP_CHECK(hipMemcpy2DAsync(xv, ld * sizeof(W), dx, ntot * sizeof(W), ntot * sizeof(W), nrhs,
+                                 hipMemcpyDeviceToHost, st));
+      sync();
+      drop(hv);
+      return status;
+    }
     const int nprob = (int)P.probs.size();
     const int ns = nprob * nrhs;
     Arena ga;
@@ -1775,6 +1899,7 @@ template <class T> struct Engine : EngineBase {
     else if (key == "ranks") per_node([&](int g) { return rank_v[g]; });
     else if (key == "attempts") per_node([&](int g) { return attempts_v[g]; });
     else if (key == "l") per_node([&](int g) { return l_v[g]; });
+    else if (key == "l_init") per_node([&](int g) { return l_init_v[g]; });
     else if (key == "err") per_node([&](int g) { return err_v[g]; });
     else if (key == "tmax") per_node([&](int g) { return tmax_v[g]; });
     else if (key == "node_heap") per_node([&](int g) { return P.nodes[g].heap; });
@@ -1785,7 +1910,24 @@ template <class T> struct Engine : EngineBase {
       for (float f : feat_v) out.push_back(f);
     } else if (key == "fallbacks") out = {(double)fallbacks};
     else if (key == "retries") out = {(double)retries};
-    else if (key == "flops_factor") {
+    else if (key == "flops_factor" || key == "flops_factor_parts") {
+      // the method's work by formula (real flops, x4 for complex): LU (2/3) n_i^3,
+      // triangular solves 2 n_i^2 n_b and the Schur product 2 n_b^2 n_i per box, the
+      // root's LU, the sampling and the truncated QR of every attempt
+      const double cx = CX ? 4.0 : 1.0;
+      double lu = 0, trsm = 0, gemm_ = 0, root = 0;
+      for (auto& n : P.nodes) {
+        const double ni = (double)n.idof.size(), nbd = (double)n.bdof.size();
+        lu += cx * (2.0 / 3.0) * ni * ni * ni;
+        trsm += cx * 2.0 * ni * ni * nbd;
+        gemm_ += cx * 2.0 * nbd * nbd * ni;
+      }
+      for (auto& r : rt) root += cx * (2.0 / 3.0) * (double)r.n * r.n * r.n;
+      if (key == "flops_factor") out = {lu + trsm + gemm_ + root + alg_sample + alg_cpqr};
+      else out = {lu, trsm, gemm_, root, alg_sample, alg_cpqr};
+    } else if (key == "flops_gj") {
+      // the work the explicit Gauss-Jordan form executes: n_i^2 (n_i + n_b) for the
+      // interior inverse and X, n_b^2 n_i for the Schur product, n^3 for the root
       double f = 0;
       for (auto& n : P.nodes) {
         double ni = (double)n.idof.size(), nbd = (double)n.bdof.size();

@@ -14,9 +14,9 @@ namespace hss {
 struct EngineBase {
   virtual ~EngineBase() {}
   virtual void factor(const hss_block_op_t* A, double tol) = 0;
-  virtual void apply(int nrhs, const void* x, int64_t ldx, void* y, int64_t ldy) = 0;
+  virtual void apply(int nrhs, const void* x, int64_t ldx, void* y, int64_t ldy, bool on_device) = 0;
   virtual int gmres(int nrhs, const void* b, void* x, int64_t ld, double tol, int restart, int maxit,
-                    hss_gmres_info_t* info) = 0;
+                    bool on_device, hss_gmres_info_t* info) = 0;
   virtual bool query(const std::string& key, std::vector<double>& out) = 0;
 };
 

@@ -84,4 +84,49 @@ __global__ __launch_bounds__(256) void gather_kernel(OpDev A, const GatherDesc<T
   }
 }
 
+// Check of the operator's values: out[0] = bits of max |a| over the finite
+// entries, out[1] = bits of max |A(e, f) - A(f, e)^T| (the symmetry the method
+// assumes: V = U in the compression), out[2] = number of non-finite entries.
+// Non-negative doubles order like their bit patterns. grid: chunks over all entries.
+template <class W>
+__global__ __launch_bounds__(256) void validate_kernel(const W* __restrict__ vals, const int32_t* __restrict__ tblk,
+                                                       int64_t nnzb, int q, unsigned long long* out) {
+  const int64_t qq = (int64_t)q * q, tot = nnzb * qq;
+  double amax = 0, dmax = 0;
+  unsigned bad = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int64_t b = e / qq, rc = e % qq;
+    const int c = (int)(rc / q), r = (int)(rc % q);
+    const W v = vals[e];
+    const W t = vals[(int64_t)tblk[b] * qq + (int64_t)r * q + c];  // entry (c, r) of block (f, e)
+    const double a = sqrt((double)traits<W>::abs2(v));
+    const double d = sqrt((double)traits<W>::abs2(v - t));
+    if (!(a <= 1.7976931348623157e308) || !(d <= 1.7976931348623157e308)) {
+      ++bad;
+    } else {
+      amax = fmax(amax, a);
+      dmax = fmax(dmax, d);
+    }
+  }
+  __shared__ double ra[256], rd[256];
+  __shared__ unsigned rb[256];
+  ra[threadIdx.x] = amax;
+  rd[threadIdx.x] = dmax;
+  rb[threadIdx.x] = bad;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      ra[threadIdx.x] = fmax(ra[threadIdx.x], ra[threadIdx.x + s]);
+      rd[threadIdx.x] = fmax(rd[threadIdx.x], rd[threadIdx.x + s]);
+      rb[threadIdx.x] += rb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(ra[0]));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(rd[0]));
+    if (rb[0]) atomicAdd(&out[2], (unsigned long long)rb[0]);
+  }
+}
+
 }  // namespace hss

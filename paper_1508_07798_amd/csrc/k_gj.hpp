@@ -190,7 +190,7 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc
   if (j0 >= g.n) return;
   const int w = min(nb, g.n - j0);
   const int base = g.poff + j0;  // first candidate row
-  const int Rr = g.rows - base;
+  const int Rr = g.rows - base;  // candidate rows
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* P = LDS ? (T*)smem_raw : g.gpanel;
   __shared__ R red_v[2][NW];
@@ -198,13 +198,15 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_kernel(const GjDesc
   __shared__ int s_pphys[64];     // physical pivot row of each panel column
   __shared__ T s_lu[NB][NB + 1];  // packed L\U row of the pivot of column c
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // panel load, four independent loads in flight per thread
+  // panel load, four independent loads in flight per thread; the index of a load
+  // past the panel is clamped to its first element (sel evaluates both operands)
   for (int idx0 = tid; idx0 < Rr * w; idx0 += 4 * NT) {
     T v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int idx = idx0 + u * NT;
-      v[u] = sel(idx < Rr * w, g.M[(base + idx % Rr) + (size_t)(j0 + idx / Rr) * g.rows], traits<T>::zero());
+      const int ic = idx < Rr * w ? idx : 0;
+      v[u] = sel(idx < Rr * w, g.M[(base + ic % Rr) + (size_t)(j0 + ic / Rr) * g.rows], traits<T>::zero());
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -324,7 +326,7 @@ __global__ __launch_bounds__(GJ_PANEL_THREADS) void gj_panel_reg_kernel(const Gj
   if (j0 >= g.n) return;
   const int w = min(nb, g.n - j0);
   const int base = g.poff + j0;  // first candidate row
-  const int Rr = g.rows - base;
+  const int Rr = g.rows - base;  // candidate rows
   __shared__ RedPair<R> s_red[2][NW];
   __shared__ int s_pphys[NB];
   __shared__ T s_lu[NB][NB + 1];  // packed L\U row of the pivot of column c, in order
@@ -628,7 +630,7 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
   if (j0 >= g.n) return;
   const int w = min(nb, g.n - j0);
   const int base = g.poff + j0;  // first candidate row
-  const int Rr = g.rows - base;  // >= w
+  const int Rr = g.rows - base;  // candidate rows, >= w
   __shared__ RedPair<R> s_red[2][NW];
   __shared__ uint64_t s_key[2][NW];
   constexpr bool KEYS = std::is_same<R, float>::value;  // one 64-bit reduction

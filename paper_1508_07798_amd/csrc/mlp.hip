@@ -2,6 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -147,6 +150,87 @@ void mlp_train(float* w, const float* x, const float* t, int n, int steps, float
     check("mlp_adam");
   }
   HIP_CHECK(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------- weights files
+// Binary layout: the 8 bytes "HSSMLP01", an int32 parameter count (HSS_MLP_NPARAMS),
+// then the parameters as float32 (W1, b1, W2, b2, W3, b3, row-major [out][in]),
+// all little-endian.
+namespace {
+const char kMagic[8] = {'H', 'S', 'S', 'M', 'L', 'P', '0', '1'};
+}
+
+void mlp_write(const char* path, const std::vector<float>& w) {
+  FILE* f = std::fopen(path, "wb");
+  if (!f) throw Error(HSS_EINVAL, std::string("cannot write ") + path);
+  const int32_t cnt = (int32_t)w.size();
+  const bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(&cnt, 4, 1, f) == 1 &&
+                  std::fwrite(w.data(), 4, w.size(), f) == w.size();
+  if (std::fclose(f) != 0 || !ok) throw Error(HSS_EINVAL, std::string("write failed: ") + path);
+}
+
+std::vector<float> mlp_read(const char* path) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) throw Error(HSS_EINVAL, std::string("cannot read ") + path);
+  char mg[8];
+  int32_t cnt = 0;
+  std::vector<float> w(MLP_NP);
+  bool ok = std::fread(mg, 1, 8, f) == 8 && std::memcmp(mg, kMagic, 8) == 0 && std::fread(&cnt, 4, 1, f) == 1 &&
+            cnt == MLP_NP && std::fread(w.data(), 4, MLP_NP, f) == (size_t)MLP_NP;
+  std::fclose(f);
+  if (!ok) throw Error(HSS_EINVAL, std::string("not a rank-model weights file: ") + path);
+  for (float v : w)
+    if (!std::isfinite(v)) throw Error(HSS_EINVAL, std::string("non-finite weight in ") + path);
+  return w;
+}
+
+// Train the rank predictor from host samples (features n x 8, ranks n) on the
+// device and write its weights: weights drawn N(0, 1/fan_in) (biases 0) from a
+// splitmix64 stream keyed by seed, targets log2(1 + rank), 1500 full-batch Adam
+// steps at learning rate 3e-3 (the library's training kernels).
+void rank_model_train(const float* feat, const float* rank, int n, const char* path, uint64_t seed) {
+  std::vector<float> w(MLP_NP, 0.f), t(n);
+  uint64_t st = seed;
+  auto next = [&]() {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto normal = [&]() {
+    const double u1 = ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+  };
+  for (int i = 0; i < OFF_B1; ++i) w[i] = (float)(normal() / std::sqrt((double)MLP_IN));
+  for (int i = OFF_W2; i < OFF_B2; ++i) w[i] = (float)(normal() / std::sqrt((double)MLP_H));
+  for (int i = OFF_W3; i < OFF_B3; ++i) w[i] = (float)(normal() / std::sqrt((double)MLP_H));
+  for (int i = 0; i < n; ++i) {
+    if (!(rank[i] >= 0) || !std::isfinite(rank[i])) throw Error(HSS_EINVAL, "ranks must be finite and >= 0");
+    t[i] = (float)std::log2(1.0 + (double)rank[i]);
+  }
+  for (int64_t i = 0; i < (int64_t)n * MLP_IN; ++i)
+    if (!std::isfinite(feat[i])) throw Error(HSS_EINVAL, "features must be finite");
+  float *dw = nullptr, *dx = nullptr, *dt = nullptr;
+  HIP_CHECK(hipMalloc(&dw, sizeof(float) * MLP_NP));
+  try {
+    HIP_CHECK(hipMalloc(&dx, sizeof(float) * (size_t)n * MLP_IN));
+    HIP_CHECK(hipMalloc(&dt, sizeof(float) * (size_t)n));
+    HIP_CHECK(hipMemcpy(dw, w.data(), sizeof(float) * MLP_NP, hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(dx, feat, sizeof(float) * (size_t)n * MLP_IN, hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(dt, t.data(), sizeof(float) * (size_t)n, hipMemcpyHostToDevice));
+    mlp_train(dw, dx, dt, n, 1500, 3e-3f, nullptr, nullptr);
+    HIP_CHECK(hipMemcpy(w.data(), dw, sizeof(float) * MLP_NP, hipMemcpyDeviceToHost));
+  } catch (...) {
+    (void)hipFree(dw);
+    if (dx) (void)hipFree(dx);
+    if (dt) (void)hipFree(dt);
+    throw;
+  }
+  (void)hipFree(dw);
+  (void)hipFree(dx);
+  (void)hipFree(dt);
+  mlp_write(path, w);
 }
 
 }  // namespace hss

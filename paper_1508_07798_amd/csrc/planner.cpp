@@ -37,28 +37,28 @@ int64_t perimeter_key(int ix, int iy, int x0, int x1, int y0, int y1) {
   bad("a boundary element of a box is not on the box perimeter");
 }
 
-int bisect(std::vector<HssNode>& out, int lo_e, int hi_e, int q) {
-  if (hi_e - lo_e <= kHssLeafElems) {
+int bisect(std::vector<HssNode>& out, int lo_e, int hi_e, int q, int leaf) {
+  if (hi_e - lo_e <= leaf) {
     out.push_back({lo_e * q, hi_e * q, -1, -1, 0});
     return (int)out.size() - 1;
   }
   int mid = lo_e + (hi_e - lo_e) / 2;
-  int l = bisect(out, lo_e, mid, q);
-  int r = bisect(out, mid, hi_e, q);
+  int l = bisect(out, lo_e, mid, q, leaf);
+  int r = bisect(out, mid, hi_e, q, leaf);
   out.push_back({lo_e * q, hi_e * q, l, r, 1 + std::max(out[l].height, out[r].height)});
   return (int)out.size() - 1;
 }
 
-void build_hss(PNode& nd, int q, bool split_top) {
+void build_hss(PNode& nd, int q, bool split_top, int leaf) {
   int m = (int)nd.bnd_elems.size();
   nd.hss.clear();
   if (m == 0) return;
   if (split_top && nd.n_top > 0 && nd.n_top < m) {
-    int l = bisect(nd.hss, 0, nd.n_top, q);
-    int r = bisect(nd.hss, nd.n_top, m, q);
+    int l = bisect(nd.hss, 0, nd.n_top, q, leaf);
+    int r = bisect(nd.hss, nd.n_top, m, q, leaf);
     nd.hss.push_back({0, m * q, l, r, 1 + std::max(nd.hss[l].height, nd.hss[r].height)});
   } else {
-    bisect(nd.hss, 0, m, q);
+    bisect(nd.hss, 0, m, q, leaf);
   }
 }
 
@@ -77,7 +77,8 @@ int Plan::find(int prob, int heap) const {
   return -1;
 }
 
-Plan make_plan(int nprob, const hss_block_op_t* A, const hss_tree_t* T) {
+Plan make_plan(int nprob, const hss_block_op_t* A, const hss_tree_t* T, int hss_leaf_elems) {
+  if (hss_leaf_elems < 1) bad("HSS leaf size must be at least one element");
   if (nprob < 1 || !A || !T) bad("null operator / tree or nprob < 1");
   Plan P;
   P.probs.resize(nprob);
@@ -112,14 +113,17 @@ Plan make_plan(int nprob, const hss_block_op_t* A, const hss_tree_t* T) {
         if (b > pr.row_ptr[e] && pr.col_idx[b - 1] >= c) bad("col_idx not ascending in a row");
         if (c == e) pr.diag_blk[e] = b;
       }
-    // the sets need a structurally symmetric operator
+    // the sets need a structurally symmetric operator; the block (c, e) of every
+    // block (e, c) is recorded for the value-symmetry check
+    pr.tblk.assign(nnzb, -1);
     for (int e = 0; e < a.n_el; ++e)
       for (int b = pr.row_ptr[e]; b < pr.row_ptr[e + 1]; ++b) {
         int c = pr.col_idx[b];
         const int32_t* beg = pr.col_idx.data() + pr.row_ptr[c];
         const int32_t* end = pr.col_idx.data() + pr.row_ptr[c + 1];
-        if (!std::binary_search(beg, end, e))
-          throw Error(HSS_EUNSUPPORTED, "structurally nonsymmetric operator");
+        const int32_t* it = std::lower_bound(beg, end, e);
+        if (it == end || *it != e) throw Error(HSS_EUNSUPPORTED, "structurally nonsymmetric operator");
+        pr.tblk[b] = (int32_t)(it - pr.col_idx.data());
       }
     // leaves
     pr.elem_leaf.assign(a.n_el, -1);
@@ -232,7 +236,7 @@ Plan make_plan(int nprob, const hss_block_op_t* A, const hss_tree_t* T) {
             if (!fl[i]) bad("parent-interior run of a box is not contiguous");
         }
       }
-      build_hss(nd, pr.q, !top);
+      build_hss(nd, pr.q, !top, hss_leaf_elems);
       dofs_of(nd.bnd_elems, pr.q, nd.bdof);
       if (nd.leaf) {
         std::vector<char> isb(0);
@@ -343,8 +347,10 @@ void flatten(Plan& P) {
   for (int p = 0; p < nprob; ++p) {
     const PProblem& pr = P.probs[p];
     for (int e = 0; e < pr.n_el; ++e) {
-      for (int b = pr.row_ptr[e]; b < pr.row_ptr[e + 1]; ++b)
+      for (int b = pr.row_ptr[e]; b < pr.row_ptr[e + 1]; ++b) {
         F.col_idx.push_back((int32_t)(pr.el_off + pr.col_idx[b]));
+        F.tblk.push_back((int32_t)(pr.blk_off + pr.tblk[b]));
+      }
       F.row_ptr.push_back((int32_t)F.col_idx.size());
       F.elem_dof.push_back(pr.dof_off + (int64_t)e * pr.q);
       for (int k = 0; k < pr.q; ++k) {

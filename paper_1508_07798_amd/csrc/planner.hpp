@@ -29,7 +29,7 @@
 
 namespace hss {
 
-constexpr int kHssLeafElems = 4;
+constexpr int kHssLeafElems = 4;  // default HSS leaf size over a box's boundary, in elements
 
 struct HssNode {
   int lo, hi;        // dof range in the box's B order
@@ -69,6 +69,7 @@ struct PProblem {
   int64_t el_off = 0, blk_off = 0;
   std::vector<int32_t> row_ptr, col_idx;
   std::vector<int32_t> diag_blk;     // block index of (e, e) per element
+  std::vector<int32_t> tblk;         // per block (e, f): index of the block (f, e)
   std::vector<int32_t> elem_leaf;    // heap id of the leaf holding each element
   std::vector<int64_t> perm;         // perm[tree position] = local dof
   int max_height = 0;
@@ -82,6 +83,7 @@ struct PlanFlat {
   // and tree position -> global dof
   std::vector<int32_t> row_ptr, col_idx, dof_elem, dof_prob;
   std::vector<int64_t> elem_dof, seg, perm;
+  std::vector<int32_t> tblk;  // per block (global index): the transposed block
   // per box: interior + boundary dofs (global), merge sources, parent positions,
   // each with its offset into the concatenation
   std::vector<int64_t> gidx, bpos;
@@ -108,6 +110,6 @@ struct Plan {
 void flatten(Plan& plan);
 
 // Builds the plan; throws hss::Error(HSS_EINVAL / HSS_EUNSUPPORTED, msg) on bad input.
-Plan make_plan(int nprob, const hss_block_op_t* A, const hss_tree_t* T);
+Plan make_plan(int nprob, const hss_block_op_t* A, const hss_tree_t* T, int hss_leaf_elems = kHssLeafElems);
 
 }  // namespace hss

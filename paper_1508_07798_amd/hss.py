@@ -23,7 +23,7 @@ MLP_NPARAMS = 4801
 
 EXPORTS = ["hss_default_opts", "hss_factor", "hss_factor_batched", "hss_apply", "gmres_solve", "hss_query",
            "hss_destroy", "hss_last_error", "hss_plan_create", "hss_plan_query", "hss_plan_destroy",
-           "hss_mlp_forward", "hss_mlp_grad", "hss_mlp_train", "hss_mlp_grad_noalloc"]
+           "hss_mlp_forward", "hss_mlp_grad", "hss_mlp_train", "hss_mlp_grad_noalloc", "hss_rank_model_train"]
 
 
 class BlockOp(C.Structure):
@@ -39,7 +39,8 @@ class TreeC(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("p_os", C.c_int32), ("l0", C.c_int32), ("max_attempts", C.c_int32),
                 ("seed", C.c_uint64), ("rank_model", C.c_void_p), ("kappa_h", C.c_double),
-                ("hip_stream", C.c_void_p), ("profile", C.c_int32), ("apply_graph", C.c_int32)]
+                ("hip_stream", C.c_void_p), ("profile", C.c_int32), ("apply_graph", C.c_int32),
+                ("hss_leaf_elems", C.c_int32), ("rank_model_path", C.c_char_p)]
 
 
 class GmresInfo(C.Structure):
@@ -70,16 +71,17 @@ def lib():
                                  C.POINTER(C.c_void_p)]
         L.hss_factor_batched.argtypes = [C.c_int32, C.POINTER(BlockOp), C.POINTER(TreeC), C.c_double,
                                          C.POINTER(Opts), C.POINTER(C.c_void_p)]
-        L.hss_apply.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]
+        L.hss_apply.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32]
         L.gmres_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
-                                  C.c_int32, C.c_int32, C.POINTER(GmresInfo)]
+                                  C.c_int32, C.c_int32, C.c_int32, C.POINTER(GmresInfo)]
         L.hss_query.argtypes = [C.c_void_p, C.c_char_p, C.POINTER(C.c_double), C.c_int64,
                                 C.POINTER(C.c_int64)]
         L.hss_destroy.argtypes = [C.c_void_p]
         L.hss_destroy.restype = None
         L.hss_default_opts.argtypes = [C.POINTER(Opts)]
         L.hss_default_opts.restype = None
-        L.hss_plan_create.argtypes = [C.POINTER(BlockOp), C.POINTER(TreeC), C.POINTER(C.c_void_p)]
+        L.hss_plan_create.argtypes = [C.POINTER(BlockOp), C.POINTER(TreeC), C.c_int32, C.POINTER(C.c_void_p)]
+        L.hss_rank_model_train.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_char_p, C.c_uint64]
         L.hss_plan_query.argtypes = [C.c_void_p, C.c_char_p, C.c_int32, C.POINTER(C.c_int64), C.c_int64,
                                      C.POINTER(C.c_int64)]
         L.hss_plan_destroy.argtypes = [C.c_void_p]
@@ -182,25 +184,58 @@ class Handle:
             raise ValueError(f"vector length {x.shape[0]} != {self.ndof}")
         return x.t().contiguous().t() if x.stride(0) != 1 else x
 
+    def _host(self, x):
+        want = np.complex128 if self.cplx else np.float64
+        x = np.asarray(x)
+        if x.dtype != want:
+            raise TypeError(f"expected a host array of {want}")
+        if x.ndim == 1:
+            x = x[:, None]
+        if x.shape[0] != self.ndof:
+            raise ValueError(f"vector length {x.shape[0]} != {self.ndof}")
+        return np.asfortranarray(x)
+
     def apply(self, x):
-        """y = M^{-t} D^{-1} L^{-1} x for a [n] or [n, k] CUDA tensor."""
+        """y = M^{-t} D^{-1} L^{-1} x for a [n] or [n, k] CUDA tensor, or a host
+        numpy array (on_device = 0: the library copies it to the device and back)."""
+        if isinstance(x, np.ndarray):
+            squeeze = x.ndim == 1
+            xx = self._host(x)
+            y = np.empty_like(xx, order="F")
+            _check(lib().hss_apply(self.ptr, xx.shape[1], xx.ctypes.data, self.ndof, y.ctypes.data, self.ndof, 0))
+            return y[:, 0] if squeeze else y
         import torch
         squeeze = x.dim() == 1
         xx = self._vec(x)
         y = torch.empty_like(xx).t().contiguous().t()
         ld_x = xx.stride(1) if xx.shape[1] > 1 else self.ndof
         ld_y = y.stride(1) if y.shape[1] > 1 else self.ndof
-        _check(lib().hss_apply(self.ptr, xx.shape[1], xx.data_ptr(), ld_x, y.data_ptr(), ld_y))
+        _check(lib().hss_apply(self.ptr, xx.shape[1], xx.data_ptr(), ld_x, y.data_ptr(), ld_y, 1))
         return y[:, 0] if squeeze else y
 
     def gmres(self, b, x0=None, tol=1e-8, restart=30, maxit=1000, nprob=1, raise_on_noconv=True):
+        """gmres_solve for a CUDA tensor b (device vectors) or a host numpy array
+        (on_device = 0)."""
+        if isinstance(b, np.ndarray):
+            squeeze = b.ndim == 1
+            bb = self._host(b)
+            x = np.zeros_like(bb, order="F") if x0 is None else np.array(self._host(x0), order="F")
+            k = bb.shape[1]
+            info = (GmresInfo * (nprob * k))()
+            st = lib().gmres_solve(self.ptr, k, bb.ctypes.data, x.ctypes.data, self.ndof, tol, restart, maxit, 0,
+                                   info)
+            if st != HSS_OK and not (st == HSS_ENOCONV and not raise_on_noconv):
+                _check(st)
+            out = [dict(iters=i.iters, restarts=i.restarts, true_relres=i.true_relres, status=i.status)
+                   for i in info]
+            return (x[:, 0] if squeeze else x), out
         import torch
         squeeze = b.dim() == 1
         bb = self._vec(b).t().contiguous().t()
         x = torch.zeros_like(bb) if x0 is None else self._vec(x0).t().contiguous().t().clone()
         k = bb.shape[1]
         info = (GmresInfo * (nprob * k))()
-        st = lib().gmres_solve(self.ptr, k, bb.data_ptr(), x.data_ptr(), self.ndof, tol, restart, maxit, info)
+        st = lib().gmres_solve(self.ptr, k, bb.data_ptr(), x.data_ptr(), self.ndof, tol, restart, maxit, 1, info)
         if st != HSS_OK and not (st == HSS_ENOCONV and not raise_on_noconv):
             _check(st)
         out = [dict(iters=i.iters, restarts=i.restarts, true_relres=i.true_relres, status=i.status) for i in info]
@@ -216,16 +251,19 @@ class Handle:
 
 
 def factor(op, tree, tol, prec="fp32", seed=1508, stream=None, l0=32, p_os=10, max_attempts=8,
-           rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True):
+           rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True, hss_leaf_elems=4,
+           rank_model_path=None):
     """hss_factor: build the preconditioner of one operator (see include/hss.h)."""
     return factor_batched([op], [tree], tol, prec=prec, seed=seed, stream=stream, l0=l0, p_os=p_os,
                           max_attempts=max_attempts, rank_model=rank_model, kappa_h=kappa_h,
                           profile=profile, vals_dev=None if vals_dev is None else [vals_dev],
-                          apply_graph=apply_graph)
+                          apply_graph=apply_graph, hss_leaf_elems=hss_leaf_elems,
+                          rank_model_path=rank_model_path)
 
 
 def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, p_os=10, max_attempts=8,
-                   rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True):
+                   rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True, hss_leaf_elems=4,
+                   rank_model_path=None):
     keep = _Keep()
     n = len(ops)
     A = (BlockOp * n)(*[_op_struct(op, keep, None if vals_dev is None else vals_dev[i])
@@ -241,6 +279,10 @@ def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, 
     # True: every kernel class; an int: the class bit mask (bit c + 1 for class c)
     o.profile = (1 if profile else 0) if isinstance(profile, bool) else int(profile)
     o.apply_graph = 1 if apply_graph else 0
+    o.hss_leaf_elems = int(hss_leaf_elems)
+    if rank_model_path is not None:
+        o.rank_model_path = os.fsencode(rank_model_path)
+        keep.items.append(o.rank_model_path)
     o.hip_stream = _stream_ptr(stream)
     if rank_model is not None:
         o.rank_model = keep.arr(rank_model, np.float32)
@@ -253,12 +295,12 @@ def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, 
 class Plan:
     """Host-only planner output (hss_plan_create)."""
 
-    def __init__(self, op, tree):
+    def __init__(self, op, tree, hss_leaf_elems=0):
         keep = _Keep()
         A = _op_struct(op, keep)
         T = _tree_struct(tree, keep)
         p = C.c_void_p()
-        _check(lib().hss_plan_create(C.byref(A), C.byref(T), C.byref(p)))
+        _check(lib().hss_plan_create(C.byref(A), C.byref(T), int(hss_leaf_elems), C.byref(p)))
         self.ptr = p.value
 
     def query(self, key, node=1):
@@ -295,6 +337,17 @@ def mlp_grad(w, x, t, stream=None):
     _check(lib().hss_mlp_grad(w.data_ptr(), x.contiguous().data_ptr(), t.contiguous().data_ptr(), x.shape[0],
                               g.data_ptr(), C.byref(loss), _stream_ptr(stream)))
     return g, loss.value
+
+
+def rank_model_train(features, ranks, out_path, seed=0):
+    """hss_rank_model_train: train on host (features [n, 8], ranks [n]) and write the
+    weights file that factor(..., rank_model_path=...) reads."""
+    f = np.ascontiguousarray(features, dtype=np.float32)
+    r = np.ascontiguousarray(ranks, dtype=np.float32)
+    if f.ndim != 2 or f.shape[1] != 8 or r.shape != (f.shape[0],):
+        raise ValueError("features must be [n, 8] and ranks [n]")
+    _check(lib().hss_rank_model_train(f.ctypes.data, r.ctypes.data, f.shape[0], os.fsencode(out_path),
+                                      C.c_uint64(seed)))
 
 
 MLP_NOALLOC_MAX_N = 8192

@@ -91,10 +91,39 @@ def training_problems(family="helmholtz_p2_64", seed_offsets=(1, 2), grids=(16, 
     return out
 
 
+def configs123_problems():
+    """The Poisson (16 x 16, p = 1), Helmholtz (p = 2) and variable-coefficient Poisson
+    (p = 3) workloads at their full sizes and on smaller grids of the same families,
+    each factorized in its own precision: the runs the p = 4 Helmholtz configuration's
+    rank model learns from."""
+    from workloads import configs
+    out = [(configs.make("poisson_p1_16"), "fp64")]
+    for n in (16, 24, 32, 48, 64):
+        out.append((configs.make("helmholtz_p2_64", n=n), "fp32"))
+    for n in (16, 32, 64, 128):
+        out.append((configs.make("varpoisson_p3_128", n=n), "bf16"))
+    return out
+
+
+def collect_mixed(problems, device="cuda:0"):
+    """collect() over (problem, precision) pairs."""
+    X, K = [], []
+    for P, prec in problems:
+        x, k = collect([P], prec=prec, device=device)
+        X.append(x)
+        K.append(k)
+    return np.concatenate(X), np.concatenate(K)
+
+
 def fit_default(device="cuda:0", steps=1500, family="helmholtz_p2_64", prec="fp32"):
-    """Collect ranks on the training problems and train; returns (weights, info)."""
+    """Collect ranks on the training problems and train; returns (weights, info).
+    family "configs123" trains on the Poisson, Helmholtz p = 2 and variable-coefficient
+    Poisson runs (configs123_problems)."""
     t0 = time.perf_counter()
-    X, K = collect(training_problems(family), prec=prec, device=device)
+    if family == "configs123":
+        X, K = collect_mixed(configs123_problems(), device=device)
+    else:
+        X, K = collect(training_problems(family), prec=prec, device=device)
     t1 = time.perf_counter()
     w, hist = train(X, K, steps=steps, device=device)
     t2 = time.perf_counter()

@@ -34,9 +34,9 @@ def test_exports_every_declared_symbol():
         assert hasattr(L, n), n
 
 
-def _check_plan(op, tree):
-    pl = hss.Plan(op, tree)
-    T = TreeSets(op.row_ptr, op.col_idx, op.q, tree)
+def _check_plan(op, tree, leaf=4):
+    pl = hss.Plan(op, tree, hss_leaf_elems=leaf)
+    T = TreeSets(op.row_ptr, op.col_idx, op.q, tree, hss_leaf_elems=leaf)
     for s in T.nodes:
         ns = T.sets[s]
         assert np.array_equal(pl.query("idof", s), ns.idof), s
@@ -59,6 +59,13 @@ def test_planner_matches_oracle(n, p, pde, scheme):
     op = sipg.assemble(n, p, pde, kappa=10.0)
     tree = partition.build_tree(n, n, 16, scheme=scheme)
     _check_plan(op, tree)
+
+
+@pytest.mark.parametrize("leaf", [1, 2, 7])
+def test_planner_hss_leaf_size_matches_oracle(leaf):
+    op = sipg.assemble(24, 2, "helmholtz", kappa=10.0)
+    tree = partition.build_tree(24, 24, 16)
+    _check_plan(op, tree, leaf)
 
 
 def test_planner_full_helmholtz_workload():
