@@ -323,10 +323,13 @@ def test_singular_block_is_reported():
     op = sipg.assemble(8, 1)
     op.vals = op.vals.copy()
     tree = partition.build_tree(8, 8, 16)
-    # zero an element's rows inside a leaf interior: A_ii becomes singular
+    # zero an element's rows and columns inside a leaf interior (the operator stays
+    # symmetric): A_ii becomes singular
     e = 9  # interior element of the first leaf (1, 1)
-    for b in range(op.row_ptr[e], op.row_ptr[e + 1]):
-        op.vals[b] = 0.0
+    for f in range(op.n_el):
+        for b in range(op.row_ptr[f], op.row_ptr[f + 1]):
+            if f == e or op.col_idx[b] == e:
+                op.vals[b] = 0.0
     with pytest.raises(hss.HssError) as ex:
         hss.factor(op, tree, 1e-6, prec="fp64")
     assert ex.value.status == hss.HSS_ESINGULAR
