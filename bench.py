@@ -185,7 +185,7 @@ def main():
                     help="spin kernels around the timed steps, to cut a kernel trace to them")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS),
                     help="measured workload (default: the largest configuration, p=4 Helmholtz on 256x256)")
-    ap.add_argument("--oracle-sample-n", type=int, default=32,
+    ap.add_argument("--oracle-sample-n", type=int, default=16,
                     help="grid of the smaller same-family problem the oracle is timed on when the "
                          "workload itself is too large for the host")
     args = ap.parse_args()

@@ -313,6 +313,8 @@ template <class T> struct Engine : EngineBase {
   // above which it is used
   static constexpr int kGjBlock = 128;
   static constexpr int kGjBlockMin = 128;
+  // complex64 boxes above this many interior rows are eliminated in complex128
+  static constexpr int kGjWidenAbove = 2048;
   // largest sample count of the randomized ID (a box whose ID needs more rows keeps
   // its dense complement once its attempts are spent)
   static constexpr int kLcapMax = 512;
@@ -833,9 +835,13 @@ template <class T> struct Engine : EngineBase {
       prof.stop(id);
       check_launch("gather");
     }
-    // 2. Gauss-Jordan on [A_ii | A_ib]
+    // 2. Gauss-Jordan on [A_ii | A_ib]. Complex64 boxes with more than
+    //    kGjWidenAbove interior rows are eliminated in complex128: the block is
+    //    widened, eliminated and narrowed back into the factor storage.
     {
       std::vector<GjDesc<X>> gj;
+      std::vector<GjDesc<W>> wide;
+      std::vector<std::pair<X*, int64_t>> narrow;  // factor block, element count
       for (size_t i = 0; i < nw; ++i) {
         const PNode& n = P.nodes[wv[i]];
         if (n.idof.empty()) continue;
@@ -845,10 +851,46 @@ template <class T> struct Engine : EngineBase {
         g.W = (int)(n.idof.size() + n.bdof.size());
         g.rowperm = nd[wv[i]].rowperm;
         g.flag = d_sing_ + wv[i];
+        if constexpr (std::is_same<X, cf>::value) {
+          if (g.n > kGjWidenAbove) {
+            const int64_t ne = (int64_t)g.n * g.W;
+            GjDesc<W> gw{};
+            gw.M = tmp.get<W>((size_t)ne);
+            gw.n = g.n;
+            gw.W = g.W;
+            gw.rowperm = g.rowperm;
+            gw.flag = g.flag;
+            wide.push_back(gw);
+            narrow.push_back({g.M, ne});
+            continue;
+          }
+        }
         gj.push_back(g);
       }
       lap(2);
       gauss_jordan<X>(gj, tmp);
+      if constexpr (std::is_same<X, cf>::value) {
+        if (!wide.empty()) {
+          const double cby = [&] {
+            double b = 0;
+            for (auto& nr : narrow) b += 2.0 * nr.second * (sizeof(X) + sizeof(W));
+            return b;
+          }();
+          int id = prof.start(C_GJ_ROWS, 0, cby / 2);
+          for (size_t k = 0; k < wide.size(); ++k)
+            convert_kernel<W, X><<<grid1(narrow[k].second, 4096), 256, 0, st>>>(narrow[k].first, wide[k].M,
+                                                                                narrow[k].second);
+          prof.stop(id);
+          check_launch("widen");
+          gauss_jordan<W>(wide, tmp);
+          id = prof.start(C_GJ_ROWS, 0, cby / 2);
+          for (size_t k = 0; k < wide.size(); ++k)
+            convert_kernel<X, W><<<grid1(narrow[k].second, 4096), 256, 0, st>>>(wide[k].M, narrow[k].first,
+                                                                                narrow[k].second);
+          prof.stop(id);
+          check_launch("narrow");
+        }
+      }
       lap(3);
     }
     // 3. Schur update S = A_bb - A_bi X
@@ -1238,7 +1280,6 @@ template <class T> struct Engine : EngineBase {
       std::vector<int> hs_height;
       std::vector<std::vector<int>> byh;
       std::vector<int> leaves;
-      std::vector<HTile> tiles;
       double* d_err = at.get<double>(na);
       int* d_flags = at.get<int>(3 * na);
       int* d_kmax = d_flags + na;
@@ -1302,14 +1343,28 @@ template <class T> struct Engine : EngineBase {
           hs_height.push_back(hn.height);
         }
       }
-      // expand tiles (need the right child's width)
-      const int tw = std::max(1, std::min(32, (int)(49152 / ((size_t)lmax * sizeof(T)))));
+      // expansion of every internal node (children a, c): Et = S(J_a, J_c) Ut_c^T in
+      // 64 x 64 tiles, the product Ut_a Et into S~ (depth k_a set on the device), and
+      // the mirror in MT x MT tiles
+      constexpr int MT = sizeof(T) >= 16 ? 32 : 64;
+      std::vector<HTile> etl, mtl;
+      std::vector<GemmDesc> eg;
+      std::vector<const int*> ek;
       for (size_t t = 0; t < hs.size(); ++t)
         if (hs[t].left >= 0) {
-          const int nc = hs[hs[t].right].hi - hs[hs[t].right].lo;
-          const int na_ = hs[hs[t].left].hi - hs[hs[t].left].lo;
-          for (int c0 = 0; c0 < nc; c0 += tw)
-            for (int r0 = 0; r0 < na_; r0 += 64) tiles.push_back({(int)t, r0, c0});
+          const HssDesc<T>& a = hs[hs[t].left];
+          const HssDesc<T>& c = hs[hs[t].right];
+          const int nc = c.hi - c.lo, na_ = a.hi - a.lo, n = bx[hs[t].box].n;
+          const int kam = std::min(bx[hs[t].box].l, a.zcap);  // columns of Ut_a
+          hs[t].Et = at.get<T>((size_t)kam * nc);
+          hs[t].ldet = kam;
+          for (int r0 = 0; r0 < kam; r0 += 64)
+            for (int c0 = 0; c0 < nc; c0 += 64) etl.push_back({(int)t, r0, c0});
+          for (int c0 = 0; c0 < nc; c0 += MT)
+            for (int r0 = 0; r0 < na_; r0 += MT) mtl.push_back({(int)t, r0, c0});
+          eg.push_back({a.Ut, hs[t].Et, bx[hs[t].box].St + a.lo + (size_t)c.lo * n, na_, nc, kam, na_, kam, n, 0,
+                        nc});
+          ek.push_back(a.k);
         }
       // per HSS height: the largest candidate count, and where the CPQR keeps its
       // working copy (LDS when the largest l x zcap of the height fits, else a
@@ -1350,7 +1405,11 @@ template <class T> struct Engine : EngineBase {
         n_utl[hh] = (unsigned)utl.size();
       }
       int* d_leaves = up(leaves, at);
-      HTile* d_tiles = tiles.empty() ? nullptr : up(tiles, at);
+      HTile* d_etl = etl.empty() ? nullptr : up(etl, at);
+      HTile* d_mtl = mtl.empty() ? nullptr : up(mtl, at);
+      const int** d_ek = ek.empty() ? nullptr : up(ek, at);
+      const GemmLaunch eL = prep_gemm<T>(eg, at);
+      if (eL.n != (int)ek.size()) throw Error(HSS_EDEVICE, "expand: an HSS child of zero width");
       double oby = 0, jby = 0;
       for (auto& b : bx) {
         oby += (double)b.n * b.l * sizeof(T);
@@ -1391,9 +1450,16 @@ template <class T> struct Engine : EngineBase {
         rec_expand = id;
         diag_copy_kernel<T><<<(unsigned)leaves.size(), 256, 0, st>>>(dbx, dhs, d_leaves);
         check_launch("diag_copy");
-        if (!tiles.empty()) {
-          expand_kernel<T><<<(unsigned)tiles.size(), 256, (size_t)lmax * tw * sizeof(T), st>>>(dbx, dhs, d_tiles, tw);
-          check_launch("expand");
+        if (!etl.empty()) {
+          expand_tmp_kernel<T><<<(unsigned)etl.size(), 256, 0, st>>>(dbx, dhs, d_etl);
+          check_launch("expand_tmp");
+          set_depth_kernel<GemmDesc><<<cdiv((int)ek.size(), 256), 256, 0, st>>>(eL.d, d_ek, (int)ek.size());
+          check_launch("set_depth");
+          gemm_nn_kernel<T, GEMM_GENERIC><<<eL.tiles, 256, 0, st>>>(eL.d, eL.pre, eL.n, traits<T>::one(),
+                                                                     traits<T>::zero());
+          check_launch("expand_gemm");
+          mirror_kernel<T, MT><<<(unsigned)mtl.size(), 256, 0, st>>>(dbx, dhs, d_mtl);
+          check_launch("mirror");
         }
         prof.stop(id);
         id = prof.start(C_JUDGE, 0, jby);

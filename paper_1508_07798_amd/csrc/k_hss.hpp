@@ -81,6 +81,8 @@ template <class T> struct HssDesc {
   T* Zw;              // l x zcap working copy for the CPQR when it does not fit in LDS
   T* U;               // zcap x l interpolation matrix (ld = zcap)
   T* Ut;              // (hi - lo) x l tall basis (ld = hi - lo)
+  T* Et;              // internal nodes: S(J_a, J_c) Ut_c^T of the children a, c (ld = ldet)
+  int ldet;
 };
 
 // ------------------------------------------------------------- kernels
@@ -514,41 +516,97 @@ __global__ __launch_bounds__(256) void utall_kernel(const CompBox<T>* __restrict
   }
 }
 
-// S~ off-diagonal blocks, one workgroup per (internal HSS node, tw-column tile of
-// its right child, 64-row tile of its left child):
-// out = Ut_a(rows, :) * (S(J_a, J_b) * Ut_b(cols, :)^T), written with its mirror.
+// S~ off-diagonal blocks of an internal HSS node with children a, c: the block
+// Ut_a (S(J_a, J_c) Ut_c^T) and its mirror. Three launches over all internal nodes:
+// expand_tmp_kernel forms Et = S(J_a, J_c) Ut_c^T (k_a x n_c), the batched MFMA
+// GEMM forms Ut_a Et in place in S~ (its depth k_a is set on the device by
+// set_depth_kernel, since the ranks are known there only), and mirror_kernel
+// writes the transposed block.
+
+// Et, one workgroup per (internal node, 64 x 64 tile of Et); each thread 4 x 4 values
 template <class T>
-__global__ __launch_bounds__(256) void expand_kernel(const CompBox<T>* __restrict__ bx,
+__global__ __launch_bounds__(256) void expand_tmp_kernel(const CompBox<T>* __restrict__ bx,
+                                                         const HssDesc<T>* __restrict__ hs,
+                                                         const HTile* __restrict__ tiles) {
+  const HTile tl = tiles[blockIdx.x];
+  const HssDesc<T> h = hs[tl.hnode];
+  const HssDesc<T> a = hs[h.left], c = hs[h.right];
+  const int ka = *a.k, kc = *c.k;
+  if (tl.r0 >= ka) return;
+  const CompBox<T> b = bx[h.box];
+  const int nc = c.hi - c.lo, n = b.n;
+  __shared__ T Gs[16][65];  // S(J_a, J_c) slab: 16 skeleton columns of c x 64 rows
+  __shared__ T Us[16][65];  // Ut_c^T slab: 16 ranks x 64 columns
+  __shared__ int s_ra[64];
+  const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
+  if (tid < 64) s_ra[tid] = tl.r0 + tid < ka ? a.skel[tl.r0 + tid] : 0;
+  T acc[4][4];
+  static_for<0, 4>([&](auto uu) {
+    static_for<0, 4>([&](auto vv) { acc[decltype(uu)::value][decltype(vv)::value] = traits<T>::zero(); });
+  });
+  __syncthreads();
+  for (int q0 = 0; q0 < kc; q0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int qq = e >> 6, i = e & 63, q = q0 + qq;
+      const bool in = q < kc && tl.r0 + i < ka;
+      Gs[qq][i] = in ? b.S[s_ra[i] + (size_t)c.skel[in ? q : 0] * n] : traits<T>::zero();
+      const bool inu = q < kc && tl.c0 + i < nc;
+      Us[qq][i] = inu ? c.Ut[(tl.c0 + i) + (size_t)(inu ? q : 0) * nc] : traits<T>::zero();
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int qq = 0; qq < 16; ++qq) {
+      T g[4], u[4];
+      static_for<0, 4>([&](auto xx) {
+        constexpr int x = decltype(xx)::value;
+        g[x] = Gs[qq][ti + 16 * x];
+        u[x] = Us[qq][tj + 16 * x];
+      });
+      static_for<0, 4>([&](auto uu) {
+        static_for<0, 4>([&](auto vv) {
+          constexpr int x = decltype(uu)::value, y = decltype(vv)::value;
+          acc[x][y] = acc[x][y] + sc_mul(g[x], u[y]);
+        });
+      });
+    }
+    __syncthreads();
+  }
+  static_for<0, 4>([&](auto uu) {
+    static_for<0, 4>([&](auto vv) {
+      constexpr int x = decltype(uu)::value, y = decltype(vv)::value;
+      const int r = tl.r0 + ti + 16 * x, col = tl.c0 + tj + 16 * y;
+      if (r < ka && col < nc) h.Et[r + (size_t)col * h.ldet] = acc[x][y];
+    });
+  });
+}
+
+// the depth of every expand GEMM: D[i].K = *kp[i]
+template <class D>
+__global__ void set_depth_kernel(D* __restrict__ d, const int* const* __restrict__ kp, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i].K = *kp[i];
+}
+
+// S~(J_c-range, J_a-range) = S~(J_a-range, J_c-range)^T through an LDS tile; one
+// workgroup per (internal node, MT x MT tile of the a x c block)
+template <class T, int MT>
+__global__ __launch_bounds__(256) void mirror_kernel(const CompBox<T>* __restrict__ bx,
                                                      const HssDesc<T>* __restrict__ hs,
-                                                     const HTile* __restrict__ tiles, int tw) {
+                                                     const HTile* __restrict__ tiles) {
   const HTile tl = tiles[blockIdx.x];
   const HssDesc<T> h = hs[tl.hnode];
   const CompBox<T> b = bx[h.box];
   const HssDesc<T> a = hs[h.left], c = hs[h.right];
-  const int ka = *a.k, kc = *c.k;
-  const int na = a.hi - a.lo, nc = c.hi - c.lo;
-  const int cw = min(tw, nc - tl.c0);
-  const int rw = min(64, na - tl.r0);
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* tmp = (T*)smem_raw;  // ka x tw
-  const int n = b.n;
-  for (int e = threadIdx.x; e < ka * cw; e += 256) {
-    const int i = e % ka, j = e / ka;
-    const int si = a.skel[i];
-    T acc = traits<T>::zero();
-    for (int q = 0; q < kc; ++q)
-      acc = acc + sc_mul(b.S[si + (size_t)c.skel[q] * n], c.Ut[(tl.c0 + j) + (size_t)q * nc]);
-    tmp[i + j * ka] = acc;
+  const int na = a.hi - a.lo, nc = c.hi - c.lo, n = b.n;
+  __shared__ T t[MT][MT + 1];
+  for (int e = threadIdx.x; e < MT * MT; e += 256) {
+    const int i = e % MT, j = e / MT;
+    if (tl.r0 + i < na && tl.c0 + j < nc) t[j][i] = b.St[(a.lo + tl.r0 + i) + (size_t)(c.lo + tl.c0 + j) * n];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < rw * cw; e += 256) {
-    const int rr = e % rw, j = e / rw;
-    const int r = tl.r0 + rr;
-    T acc = traits<T>::zero();
-    for (int q = 0; q < ka; ++q) acc = acc + sc_mul(a.Ut[r + (size_t)q * na], tmp[q + j * ka]);
-    const int gr = a.lo + r, gc = c.lo + tl.c0 + j;
-    b.St[gr + (size_t)gc * n] = acc;
-    b.St[gc + (size_t)gr * n] = acc;
+  for (int e = threadIdx.x; e < MT * MT; e += 256) {
+    const int j = e % MT, i = e / MT;
+    if (tl.r0 + i < na && tl.c0 + j < nc) b.St[(c.lo + tl.c0 + j) + (size_t)(a.lo + tl.r0 + i) * n] = t[j][i];
   }
 }
 

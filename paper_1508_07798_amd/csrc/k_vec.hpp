@@ -146,6 +146,14 @@ __global__ void permute_kernel(const V* __restrict__ x, int64_t ldx, V* __restri
   }
 }
 
+// dst = src converted elementwise between scalar types (a complex64 block widened
+// to complex128 and back)
+template <class D, class S>
+__global__ __launch_bounds__(256) void convert_kernel(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    dst[e] = traits<D>::mk(traits<S>::re(src[e]), traits<S>::im(src[e]));
+}
+
 // y = A x (mode 0) or y = b - A x (mode 1) for the element-block operator.
 // dof_elem[d]: global element of global dof d; elem_dof[e]: first global dof of e.
 template <class V>

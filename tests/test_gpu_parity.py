@@ -179,14 +179,8 @@ def test_multiple_rhs_and_batched_problems():
     hb.close()
 
 
-P4_64_SKIP = ("its 3,200-row complex root needs a complex64 Gauss-Jordan panel above 2048 rows, a path "
-              "switched off after a GPU fault at 3,150 rows whose cause is not found")
-
-
 @pytest.mark.parametrize("name,n,prec", [("varpoisson_p3_128", None, "bf16"), ("helmholtz_p4_256", 32, "fp32"),
-                                         pytest.param("helmholtz_p4_256", 64, "fp32",
-                                                      marks=pytest.mark.skip(reason=P4_64_SKIP)),
-                                         ("helmholtz_p4_256", 64, "fp64")])
+                                         ("helmholtz_p4_256", 64, "fp32"), ("helmholtz_p4_256", 64, "fp64")])
 def test_full_and_degree4_configurations(name, n, prec):
     """The variable-coefficient Poisson workload at its full size (128 x 128, p = 3,
     BF16 Schur products) and the p = 4 Helmholtz family on reduced grids: every box
