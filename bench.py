@@ -20,14 +20,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 CLASSES = ["gather", "gj_panel", "gj_rows", "gj_update", "gj_perm", "schur_gemm", "symm", "omega",
-           "sample_gemm", "sample", "id", "utall", "expand", "judge", "root", "apply", "spmv", "gmres"]
+           "sample_gemm", "sample", "id", "utall", "expand", "judge", "root", "apply", "spmv", "gmres",
+           "gj_panel_wide", "gj_rows_wide", "gj_update_wide"]
 # MI355X peaks: dense MFMA FP32 / FP64, vector FP32 / FP64, HBM3E
 PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "mfma_bf16": 2500.0, "alu_fp32": 157.3, "alu_fp64": 78.6,
         "hbm": 8000.0}
 # bound of each kernel class and whether its algorithmic work is counted in flops or bytes
 BOUND = {"gather": "hbm", "gj_panel": "alu", "gj_rows": "hbm", "gj_update": "mfma", "schur_gemm": "mfma",
          "symm": "hbm", "omega": "hbm", "sample_gemm": "mfma", "sample": "alu", "id": "alu", "utall": "alu",
-         "expand": "alu", "judge": "hbm", "apply": "hbm", "spmv": "hbm", "root": "hbm", "gj_perm": "hbm"}
+         "expand": "mfma", "judge": "hbm", "apply": "hbm", "spmv": "hbm", "root": "hbm", "gj_perm": "hbm",
+         "gj_panel_wide": "alu", "gj_rows_wide": "hbm", "gj_update_wide": "mfma"}
+# the *_wide classes: Gauss-Jordan work that a single-precision factorization does in
+# double precision (complex64 boxes above 2048 interior rows, and the root)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "roofline_traffic.json")
 # measured workloads: the mixed form's precision and the arithmetic type it computes in
 WORKLOADS = {
@@ -64,6 +68,7 @@ def class_table(h, steps=1):
 
 def roofline_entry(cls, rec, fp64, bf16_schur=False):
     bound = BOUND.get(cls, "alu")
+    fp64 = fp64 or cls.endswith("_wide")
     if bf16_schur and cls == "schur_gemm":  # BF16 matrix cores (algorithmic flops, dense BF16 peak)
         achieved = rec["flops"] / (rec["ms"] * 1e-3) / 1e12 if rec["flops"] > 0 else None
         return {"bound": "mfma", "achieved": None if achieved is None else round(achieved, 4),

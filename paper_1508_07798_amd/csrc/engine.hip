@@ -201,11 +201,15 @@ struct Arena {
 // ------------------------------------------------------------------ profiling
 enum Cls {
   C_GATHER, C_GJ_PANEL, C_GJ_ROWS, C_GJ_UPDATE, C_GJ_PERM, C_SCHUR, C_SYMM, C_OMEGA, C_SAMPLE_GEMM,
-  C_SAMPLE, C_ID, C_UTALL, C_EXPAND, C_JUDGE, C_ROOT, C_APPLY, C_SPMV, C_GMRES, C_NCLS
+  C_SAMPLE, C_ID, C_UTALL, C_EXPAND, C_JUDGE, C_ROOT, C_APPLY, C_SPMV, C_GMRES,
+  // Gauss-Jordan work done in the vector type by a factorization of a narrower type
+  // (complex64 boxes widened to complex128, and the root)
+  C_GJ_PANEL_W, C_GJ_ROWS_W, C_GJ_UPDATE_W, C_NCLS
 };
 static const char* kClsName[C_NCLS] = {"gather", "gj_panel", "gj_rows", "gj_update", "gj_perm",
                                        "schur_gemm", "symm", "omega", "sample_gemm", "sample", "id",
-                                       "utall", "expand", "judge", "root", "apply", "spmv", "gmres"};
+                                       "utall", "expand", "judge", "root", "apply", "spmv", "gmres",
+                                       "gj_panel_wide", "gj_rows_wide", "gj_update_wide"};
 
 // HIP events are created once per process and reused by every handle's profiler
 // (creating them per factorization costs more than the kernels they time).
@@ -531,12 +535,14 @@ template <class T> struct Engine : EngineBase {
     fl();
     int id = prof.start(cls, L.flops, 0);
     if (cls == C_SCHUR) gemm_nn_kernel<X, GEMM_SCHUR><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
-    else if (cls == C_GJ_UPDATE) gemm_nn_kernel<X, GEMM_GJ_UPDATE><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+    else if (cls == C_GJ_UPDATE || cls == C_GJ_UPDATE_W)
+      gemm_nn_kernel<X, GEMM_GJ_UPDATE><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
     else if (cls == C_SAMPLE_GEMM) gemm_nn_kernel<X, GEMM_SAMPLE><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
     else gemm_nn_kernel<X, GEMM_GENERIC><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
     prof.stop(id);
     check_launch("gemm");
-    if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_SAMPLE_GEMM) flops_factor += L.flops;
+    if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_GJ_UPDATE_W || cls == C_SAMPLE_GEMM)
+      flops_factor += L.flops;
   }
   // real FP32 operands on BF16 matrix cores (three products of the hi / lo split)
   void run_gemm_bf16(const GemmLaunch& L, float alpha, float beta, int cls) {
@@ -580,7 +586,9 @@ template <class T> struct Engine : EngineBase {
   // register kernel, else the LDS / global-memory panel kernel.
   struct GjCfg {
     int nb, rpt;
-    bool rot, reg, lds;
+    bool rot, reg, lds, tourn;
+    int nch;  // tournament: chunks of kTournChunk candidate rows
+    int* cand;
     size_t shm;
     PanelShape ps;
   };
@@ -597,6 +605,16 @@ template <class T> struct Engine : EngineBase {
     if (std::is_same<X, cf>::value)
       throw Error(HSS_EUNSUPPORTED, "complex64 Gauss-Jordan panels of " + std::to_string(rmax) +
                                         " rows are not supported (at most 2048)");
+    // taller panels: tournament pivoting over chunks held by the compact kernel
+    if constexpr (!std::is_same<X, cf>::value) {
+      const int nch = cdiv(rmax, kTournChunk);
+      if (nch * tourn_nb<X>() <= kTournCand) {
+        c.tourn = true;
+        c.nb = tourn_nb<X>();
+        c.nch = nch;
+        return c;
+      }
+    }
     // register-resident panel when the tallest panel fits: rows per thread (rpt) and
     // panel width (nb) from a budget of 192 registers for the panel values
     const int words = sX / 4;
@@ -624,6 +642,7 @@ template <class T> struct Engine : EngineBase {
   template <class X>
   void gj_sweep(const std::vector<GjDesc<X>>& ds, const GjDesc<X>* dd, const GjCfg& c, Arena& ar) {
     const int nn = (int)ds.size(), nb = c.nb, sX = (int)sizeof(X);
+    constexpr bool wide = !std::is_same<X, T>::value;
     int nmax = 0, wmax = 0, rmax = 0;
     for (auto& g : ds) nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W), rmax = std::max(rmax, g.rows);
     // every panel's trailing-update descriptors, uploaded together
@@ -650,20 +669,23 @@ template <class T> struct Engine : EngineBase {
           rby += (2.0 * g.rows * w + 3.0 * w * g.W) * sX;
         }
       }
-      int id = prof.start(C_GJ_PANEL, pfl, 0);
+      int id = prof.start(wide ? C_GJ_PANEL_W : C_GJ_PANEL, pfl, 0);
       if (c.rot) launch_panel_rot<X>(dd, nn, j0, nb, c.ps, st);
+      else if (c.tourn) {
+        if constexpr (!std::is_same<X, cf>::value) launch_panel_tourn<X>(dd, nn, j0, nb, c.nch, c.cand, st);
+      }
       else if (c.reg) launch_panel_reg<X>(dd, nn, j0, nb, c.rpt, c.shm);
       else if (c.lds && nb == 16) gj_panel_kernel<X, true, 16><<<nn, GJ_PANEL_THREADS, c.shm, st>>>(dd, j0, nb);
       else if (c.lds) gj_panel_kernel<X, true, 32><<<nn, GJ_PANEL_THREADS, c.shm, st>>>(dd, j0, nb);
       else gj_panel_kernel<X, false, 32><<<nn, GJ_PANEL_THREADS, 0, st>>>(dd, j0, nb);
       prof.stop(id);
       check_launch("gj_panel");
-      id = prof.start(C_GJ_ROWS, 0, rby);
+      id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, rby);
       gj_rows_kernel<X><<<dim3(cdiv(wmax, 64) + cdiv(rmax, 256), nn), 256, 0, st>>>(dd, j0, nb, cdiv(wmax, 64),
-                                                                                   c.rot ? 1 : 0);
+                                                                                   c.rot || c.tourn ? 1 : 0);
       prof.stop(id);
       check_launch("gj_rows");
-      run_gemm<X>(upd[pi], m1, p1, C_GJ_UPDATE);
+      run_gemm<X>(upd[pi], m1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
     }
   }
 
@@ -674,6 +696,7 @@ template <class T> struct Engine : EngineBase {
   template <class X>
   void gauss_jordan(std::vector<GjDesc<X>>& ds, Arena& ar, int block = 0) {
     if (ds.empty()) return;
+    constexpr bool wide = !std::is_same<X, T>::value;
     int nmax = 0, wmax = 0;
     for (auto& g : ds) {
       g.rows = g.n;
@@ -681,8 +704,9 @@ template <class T> struct Engine : EngineBase {
       nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W);
     }
     const int sX = (int)sizeof(X);
-    const GjCfg c = gj_config<X>(nmax);
+    GjCfg c = gj_config<X>(nmax);
     const int nb = c.nb;
+    if (c.tourn) c.cand = ar.get<int>(ds.size() * (size_t)c.nch * nb);
     int wo = block > 0 ? std::min(block, GJ_BLOCK_MAX) : (nmax > kGjBlockMin ? kGjBlock : 0);
     if (wo >= nmax) wo = 0;
     // scratch per box
@@ -742,19 +766,19 @@ template <class T> struct Engine : EngineBase {
           cby += 2.0 * g.rows * wb * sX;
           bby += 3.0 * wb * g.W * sX;
         }
-      int id = prof.start(C_GJ_ROWS, 0, cby);
+      int id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, cby);
       gj_block_copy_kernel<X><<<dim3(std::min(cdiv(nmax * wo, 256), 256), nn), 256, 0, st>>>(dd, J, wo);
       prof.stop(id);
       check_launch("gj_block_copy");
       const std::vector<GjDesc<X>> blk(inner.begin() + ioff[b], inner.begin() + ioff[b + 1]);
       gj_sweep<X>(blk, di + ioff[b], c, ar);
-      id = prof.start(C_GJ_ROWS, 0, bby);
+      id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, bby);
       gj_block_moves_kernel<X><<<nn, 256, 0, st>>>(dd, J);
       check_launch("gj_block_moves");
       gj_block_rows_kernel<X><<<dim3(cdiv(wmax, GJ_BLOCK_TILE), nn), 256, 0, st>>>(dd, J, wo);
       prof.stop(id);
       check_launch("gj_block_rows");
-      run_gemm<X>(outer[b], p1, p1, C_GJ_UPDATE);
+      run_gemm<X>(outer[b], p1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
     }
   }
 
@@ -876,14 +900,14 @@ template <class T> struct Engine : EngineBase {
             for (auto& nr : narrow) b += 2.0 * nr.second * (sizeof(X) + sizeof(W));
             return b;
           }();
-          int id = prof.start(C_GJ_ROWS, 0, cby / 2);
+          int id = prof.start(C_GJ_ROWS_W, 0, cby / 2);
           for (size_t k = 0; k < wide.size(); ++k)
             convert_kernel<W, X><<<grid1(narrow[k].second, 4096), 256, 0, st>>>(narrow[k].first, wide[k].M,
                                                                                 narrow[k].second);
           prof.stop(id);
           check_launch("widen");
           gauss_jordan<W>(wide, tmp);
-          id = prof.start(C_GJ_ROWS, 0, cby / 2);
+          id = prof.start(C_GJ_ROWS_W, 0, cby / 2);
           for (size_t k = 0; k < wide.size(); ++k)
             convert_kernel<X, W><<<grid1(narrow[k].second, 4096), 256, 0, st>>>(wide[k].M, narrow[k].first,
                                                                                 narrow[k].second);

@@ -620,33 +620,32 @@ __device__ __forceinline__ void pivot_block_gj(const GjDesc<T>& g, int j0, int b
 // partials and updates its rows with the pivot row. The search and the
 // elimination run in the matrix's own precision, so the pivots are those of
 // partial pivoting in that precision.
-template <class T, int NB, int RPT, int NT>
-__global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __restrict__ descs, int j0, int nb) {
+// The pivot search of the compact panel: the Rr candidate rows rowof(0 .. Rr - 1)
+// of M (Rr <= RPT * NT), columns j0 .. j0 + w - 1; s_pphys[c] receives the index
+// r of the pivot of column c. Every thread of the block takes part. An exactly zero
+// pivot sets *zflag (when given): the panel is singular if the search covers all
+// its candidate rows, not when it covers one chunk of them.
+template <class T, int NB, int RPT, int NT, class RowOf>
+__device__ __forceinline__ void rot_search(const GjDesc<T>& g, int j0, int w, int Rr, RowOf rowof, int* s_pphys,
+                                           int* zflag) {
   using S = T;
   using R = typename traits<S>::real;
   constexpr bool CPLX = traits<T>::cplx;
   constexpr int NW = NT / 64;
-  const GjDesc<T> g = descs[blockIdx.x];
-  if (j0 >= g.n) return;
-  const int w = min(nb, g.n - j0);
-  const int base = g.poff + j0;  // first candidate row
-  const int Rr = g.rows - base;  // candidate rows, >= w
   __shared__ RedPair<R> s_red[2][NW];
   __shared__ uint64_t s_key[2][NW];
   constexpr bool KEYS = std::is_same<R, float>::value;  // one 64-bit reduction
-  __shared__ int s_pphys[NB];
   __shared__ R s_cre[2][NW][NB];
   __shared__ R s_cim[2][NW][CPLX ? NB : 1];
-  __shared__ T s_row[2][NB], s_col[2][NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   R re[RPT][NB], im[RPT][NB];
   static_for<0, RPT>([&](auto tidx) {
     constexpr int t = decltype(tidx)::value;
     const int r = tid + t * NT;
-    const int rr = min(r, Rr - 1);
+    const int rr = rowof(min(r, Rr - 1));
     static_for<0, NB>([&](auto ci) {
       constexpr int cc = decltype(ci)::value;
-      const T v = g.M[(base + rr) + (size_t)(j0 + min(cc, w - 1)) * g.rows];
+      const T v = g.M[rr + (size_t)(j0 + min(cc, w - 1)) * g.rows];
       const bool keep = r < Rr && cc < w;
       re[t][cc] = keep ? R(traits<T>::re(v)) : R(0);
       im[t][cc] = keep ? R(traits<T>::im(v)) : R(0);
@@ -729,7 +728,7 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
     __builtin_amdgcn_sched_barrier(0);
     const S pv = traits<S>::mk(prr[0], pri[0]);
     const bool zero = traits<S>::abs2(pv) == 0;
-    if (zero && tid == 0) *g.flag = 1;
+    if (zero && tid == 0 && zflag) *zflag = 1;
     const S inv = zero ? traits<S>::zero() : pivot_inv(pv);
     S l[RPT];
     static_for<0, RPT>([&](auto tidx) {
@@ -753,13 +752,91 @@ __global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __res
       im[t][NB - 1] = R(0);
     });
   }
-  // the row permutation is updated here (gj_rows_kernel is told to leave it)
+}
+
+// the end of a panel step once its pivots (relative to base) are in s_pphys: the
+// row permutation (gj_rows_kernel is told to leave it), the net row movement and
+// Pinv from the original pivot rows
+template <class T, int NB, int NT>
+__device__ __forceinline__ void panel_finish(const GjDesc<T>& g, int j0, int base, int w, int* s_pphys) {
+  __shared__ T s_row[2][NB], s_col[2][NB];
+  const int tid = threadIdx.x;
   if (g.rowperm && j0 == 0)
     for (int i = tid; i < g.rows; i += NT) g.rowperm[i] = i;
   __syncthreads();
-  if (wave == 0) panel_moves(g.mv, s_pphys, w, g.rowperm, base);
+  if ((tid >> 6) == 0) panel_moves(g.mv, s_pphys, w, g.rowperm, base);
   pivot_block_gj<T, NB, NT>(g, j0, base, w, s_pphys, s_row, s_col);
 }
+
+template <class T, int NB, int RPT, int NT>
+__global__ __launch_bounds__(NT) void gj_panel_rot_kernel(const GjDesc<T>* __restrict__ descs, int j0, int nb) {
+  const GjDesc<T> g = descs[blockIdx.x];
+  if (j0 >= g.n) return;
+  const int w = min(nb, g.n - j0);
+  const int base = g.poff + j0;  // first candidate row
+  const int Rr = g.rows - base;  // candidate rows, >= w
+  __shared__ int s_pphys[NB];
+  rot_search<T, NB, RPT, NT>(g, j0, w, Rr, [&](int r) { return base + r; }, s_pphys, g.flag);
+  panel_finish<T, NB, NT>(g, j0, base, w, s_pphys);
+}
+
+// Tournament pivoting for panels taller than one compact kernel holds (the
+// communication-avoiding LU of Grigori, Demmel and Xiang): the candidate rows are
+// cut into chunks of RPT * NT rows, each chunk picks w local pivots by partial
+// pivoting on its own rows (gj_tourn_local_kernel, one workgroup per chunk and
+// box), and partial pivoting on the original values of the stacked local pivots
+// picks the panel's pivots (gj_tourn_final_kernel, one workgroup per box).
+// cand[(box * nch + chunk) * NB + c]: local pivot c of the chunk, relative to the
+// panel's first candidate row, or -1.
+template <class T, int NB, int RPT, int NT>
+__global__ __launch_bounds__(NT) void gj_tourn_local_kernel(const GjDesc<T>* __restrict__ descs, int j0, int nb,
+                                                            int nch, int* __restrict__ cand) {
+  const GjDesc<T> g = descs[blockIdx.y];
+  int* out = cand + ((size_t)blockIdx.y * nch + blockIdx.x) * NB;
+  const int w = j0 < g.n ? min(nb, g.n - j0) : 0;
+  const int base = g.poff + j0;
+  const int r0 = (int)blockIdx.x * RPT * NT;
+  const int cnt = w > 0 ? min(RPT * NT, g.rows - base - r0) : 0;
+  if (cnt <= 0) {
+    if (threadIdx.x < NB) out[threadIdx.x] = -1;
+    return;
+  }
+  __shared__ int s_pphys[NB];
+  const int wl = min(w, cnt);
+  rot_search<T, NB, RPT, NT>(g, j0, wl, cnt, [&](int r) { return base + r0 + r; }, s_pphys, nullptr);
+  __syncthreads();
+  if (threadIdx.x < NB) out[threadIdx.x] = threadIdx.x < wl ? r0 + s_pphys[threadIdx.x] : -1;
+}
+
+template <class T, int NB, int RPT, int NT>
+__global__ __launch_bounds__(NT) void gj_tourn_final_kernel(const GjDesc<T>* __restrict__ descs, int j0, int nb,
+                                                            int nch, const int* __restrict__ cand) {
+  const GjDesc<T> g = descs[blockIdx.x];
+  if (j0 >= g.n) return;
+  const int w = min(nb, g.n - j0);
+  const int base = g.poff + j0;
+  __shared__ int s_cl[RPT * NT];  // the valid candidates, relative to base
+  __shared__ int s_m;
+  __shared__ int s_pphys[NB];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    int m = 0;
+    for (int i = 0; i < nch * NB; ++i) {
+      const int v = cand[(size_t)blockIdx.x * nch * NB + i];
+      if (v >= 0 && m < RPT * NT) s_cl[m++] = v;
+    }
+    s_m = m;
+  }
+  __syncthreads();
+  const int m = s_m;
+  rot_search<T, NB, RPT, NT>(g, j0, w, m, [&](int r) { return base + s_cl[r]; }, s_pphys, g.flag);
+  __syncthreads();
+  const int p = tid < w ? s_cl[s_pphys[tid]] : 0;
+  __syncthreads();
+  if (tid < w) s_pphys[tid] = p;
+  panel_finish<T, NB, NT>(g, j0, base, w, s_pphys);
+}
+
 
 // Row interchanges, pivot-row scaling and the saved panel columns; grid
 // (ntx column tiles of 64 + row blocks of 256, box). The panel columns of M are

@@ -65,6 +65,15 @@ void launch_panel_rot(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelSh
                                ", threads " + std::to_string(s.nt));
 }
 
+template <class X>
+void launch_panel_tourn(const GjDesc<X>* dd, int nn, int j0, int nb, int nch, int* cand, hipStream_t st) {
+  constexpr int NB = tourn_nb<X>();
+  static_assert(kTournChunk == 4 * 256 && kTournCand == 256, "launch shapes below");
+  if (nb != NB || nch < 1 || nch * NB > kTournCand) throw Error(HSS_EINVAL, "tournament panel shape");
+  gj_tourn_local_kernel<X, NB, 4, 256><<<dim3(nch, nn), 256, 0, st>>>(dd, j0, nb, nch, cand);
+  gj_tourn_final_kernel<X, NB, 1, 256><<<nn, 256, 0, st>>>(dd, j0, nb, nch, cand);
+}
+
 template bool panel_rot_config<float>(int, PanelShape&);
 template bool panel_rot_config<double>(int, PanelShape&);
 template bool panel_rot_config<cf>(int, PanelShape&);
@@ -73,5 +82,8 @@ template void launch_panel_rot<float>(const GjDesc<float>*, int, int, int, const
 template void launch_panel_rot<double>(const GjDesc<double>*, int, int, int, const PanelShape&, hipStream_t);
 template void launch_panel_rot<cf>(const GjDesc<cf>*, int, int, int, const PanelShape&, hipStream_t);
 template void launch_panel_rot<cd>(const GjDesc<cd>*, int, int, int, const PanelShape&, hipStream_t);
+template void launch_panel_tourn<float>(const GjDesc<float>*, int, int, int, int, int*, hipStream_t);
+template void launch_panel_tourn<double>(const GjDesc<double>*, int, int, int, int, int*, hipStream_t);
+template void launch_panel_tourn<cd>(const GjDesc<cd>*, int, int, int, int, int*, hipStream_t);
 
 }  // namespace hss
