@@ -1269,7 +1269,13 @@ template <class T> struct Engine : EngineBase {
       for (auto& b : all) sby += 2.0 * b.n * b.n * sizeof(T);
       int id = prof.start(C_SYMM, 0, sby);
       fl();
-      symm_norm_kernel<T><<<dim3(grid1(maxe, 256), nb_boxes), 256, 0, st>>>(d);
+      constexpr int MT = sizeof(T) >= 8 ? 32 : 64;
+      int64_t npair = 0;
+      for (auto& b : all) {
+        const int64_t t = cdiv(b.n, MT);
+        npair = std::max<int64_t>(npair, t * (t + 1) / 2);
+      }
+      if (npair > 0) symm_norm_kernel<T, MT><<<dim3((unsigned)npair, nb_boxes), 256, 0, st>>>(d);
       prof.stop(id);
       check_launch("symm");
     }

@@ -97,25 +97,50 @@ __global__ void omega_kernel(const CompBox<T>* __restrict__ bx, uint64_t seed) {
   }
 }
 
-// grid (chunks, boxes): S <- (S + S^T)/2 and ||S||_F^2 (atomic partial sums)
-template <class T>
+// S <- (S + S^T)/2 and ||S||_F^2 (atomic partial sums). Grid (tile pairs, boxes):
+// block x takes the MT x MT tiles (ti, tj) and (tj, ti), ti <= tj, of the tile
+// triangle in order tj (tj + 1) / 2 + ti; both tiles pass through LDS, so every
+// global read and write is along columns.
+template <class T, int MT>
 __global__ __launch_bounds__(256) void symm_norm_kernel(const CompBox<T>* __restrict__ bx) {
   const CompBox<T> b = bx[blockIdx.y];
-  const int64_t tot = (int64_t)b.n * b.n;
+  const int nt = (b.n + MT - 1) / MT;
+  const int64_t k = blockIdx.x;
+  if (k >= (int64_t)nt * (nt + 1) / 2) return;
+  int tj = (int)((sqrt(8.0 * (double)k + 1.0) - 1.0) / 2.0);
+  while ((int64_t)tj * (tj + 1) / 2 > k) --tj;
+  while ((int64_t)(tj + 1) * (tj + 2) / 2 <= k) ++tj;
+  const int ti = (int)(k - (int64_t)tj * (tj + 1) / 2);
+  const int r0 = ti * MT, c0 = tj * MT, n = b.n;
+  __shared__ T up[MT][MT + 1];  // up[c][r] = S(r0 + r, c0 + c)
+  __shared__ T lo[MT][MT + 1];  // lo[c][r] = S(c0 + r, r0 + c)
+  for (int e = threadIdx.x; e < MT * MT; e += 256) {
+    const int r = e % MT, c = e / MT;
+    if (r0 + r < n && c0 + c < n) up[c][r] = b.S[(r0 + r) + (size_t)(c0 + c) * n];
+    if (c0 + r < n && r0 + c < n) lo[c][r] = b.S[(c0 + r) + (size_t)(r0 + c) * n];
+  }
+  __syncthreads();
   double acc = 0;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
-    const int r = (int)(e % b.n), c = (int)(e / b.n);
-    if (r < c) {
-      T* a = b.S + r + (size_t)c * b.n;
-      T* t = b.S + c + (size_t)r * b.n;
-      T m = traits<T>::mk(0.5 * (traits<T>::re(*a) + traits<T>::re(*t)),
-                          0.5 * (traits<T>::im(*a) + traits<T>::im(*t)));
-      *a = m;
-      *t = m;
-      acc += 2.0 * (double)traits<T>::abs2(m);
-    } else if (r == c) {
-      acc += (double)traits<T>::abs2(b.S[e]);
+  // entry (r0 + r, c0 + c) pairs with (c0 + c, r0 + r) = lo[r][c]
+  for (int e = threadIdx.x; e < MT * MT; e += 256) {
+    const int r = e % MT, c = e / MT;
+    if (r0 + r < n && c0 + c < n && (ti < tj || r <= c)) {
+      const T a = up[c][r], t = lo[r][c];
+      const T m = traits<T>::mk(0.5 * (traits<T>::re(a) + traits<T>::re(t)),
+                                0.5 * (traits<T>::im(a) + traits<T>::im(t)));
+      acc += (ti < tj || r < c ? 2.0 : 1.0) * (double)traits<T>::abs2(m);
+      up[c][r] = m;
     }
+  }
+  __syncthreads();
+  // diagonal tiles: the lower half takes the mirror of the upper half
+  for (int e = threadIdx.x; e < MT * MT; e += 256) {
+    const int r = e % MT, c = e / MT;
+    if (r0 + r < n && c0 + c < n) {
+      const T v = (ti < tj || r <= c) ? up[c][r] : up[r][c];
+      b.S[(r0 + r) + (size_t)(c0 + c) * n] = v;
+    }
+    if (ti < tj && c0 + r < n && r0 + c < n) b.S[(c0 + r) + (size_t)(r0 + c) * n] = up[r][c];
   }
   __shared__ double red[256];
   red[threadIdx.x] = acc;
