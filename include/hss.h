@@ -52,7 +52,8 @@ typedef enum {
   HSS_PREC_FP64 = 0, /* everything in FP64 (complex128)                              */
   HSS_PREC_FP32 = 1, /* FP32 (complex64) factor, FP32 MFMA Schur products            */
   HSS_PREC_BF16 = 2  /* as FP32, but Schur products on BF16 MFMA with FP32 accumulate,
-                        operands split in three BF16 terms (hi*hi + hi*lo + lo*hi)    */
+                        operands split in three BF16 terms (hi*hi + hi*lo + lo*hi);
+                        real and complex operators                                     */
 } hss_prec_t;
 
 /* Element-block operator (Section 3.0: A is never assembled).

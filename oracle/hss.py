@@ -31,11 +31,15 @@ tall bases Ut (leaf: U; parent: diag(Ut_a, Ut_b) U).
 
 Tolerance reading (the paper asks for ||A - A_HSS|| <= eps without naming
 the norm): relative Frobenius error per node, ||S - S~||_F <= tol ||S||_F.
-Per-ID threshold on the true block error: delta = tol ||S||_F / sqrt(2 n_id);
-on the samples it is delta * sqrt(l) (E||E Omega||_F^2 = l ||E||_F^2). A
-node whose measured error misses tol is redone with delta / 4; an ID that
-needs more than l - p_os rows is redone with l doubled. A node whose measured
-error meets tol is accepted as it is.
+Per-ID threshold on the true block error: delta = tol ||S||_F / (4 sqrt(2 n_id));
+on the samples it is delta * sqrt(l) (E||E Omega||_F^2 = l ||E||_F^2). The
+sqrt(2 n_id) splits the budget between the IDs as if their errors added in
+quadrature; the factor 1/4 allows for the nested bases, through which a
+child's truncation error reaches the parent's block multiplied by the
+parent's interpolation matrix (entries up to 2 in modulus). A node whose
+measured error misses tol is redone with delta / 4; an ID that needs more
+than l - p_os rows is redone with l doubled. A node whose measured error
+meets tol is accepted as it is.
 
 Test infrastructure only.
 """
@@ -49,6 +53,7 @@ import scipy.linalg as sla
 from .sets import HssNode, hss_postorder
 
 P_OS = 10
+INITIAL_DELTA_SCALE = 0.25  # delta's first value relative to tol ||S||_F / sqrt(2 n_id)
 
 
 @dataclasses.dataclass
@@ -202,7 +207,7 @@ def compress_adaptive(S: np.ndarray, tree: HssNode, tol: float, omega_fn, l0: in
         return CompressLog(0, 0, 1.0, HssResult(S.copy(), 0.0, [], 0, False, 0.0, n_id), False)
     l_cap = n + P_OS
     l = min(l0, l_cap)
-    scale = 1.0
+    scale = INITIAL_DELTA_SCALE
     res = None
     for att in range(1, max_attempts + 1):
         delta = scale * tol * nrm / np.sqrt(2.0 * n_id)

@@ -544,6 +544,17 @@ template <class T> struct Engine : EngineBase {
     if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_GJ_UPDATE_W || cls == C_SAMPLE_GEMM)
       flops_factor += L.flops;
   }
+  // complex64 operands on BF16 matrix cores (three products per real product)
+  void run_gemm_cbf16(const GemmLaunch& L, cf alpha, cf beta, int cls) {
+    if (L.n == 0) return;
+    fl();
+    int id = prof.start(cls, L.flops, 0);
+    if (cls == C_SCHUR) gemm_cbf16x3_kernel<GEMM_SCHUR><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+    else gemm_cbf16x3_kernel<GEMM_GENERIC><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+    prof.stop(id);
+    check_launch("gemm_cbf16x3");
+    if (cls == C_SCHUR || cls == C_GJ_UPDATE || cls == C_SAMPLE_GEMM) flops_factor += L.flops;
+  }
   // real FP32 operands on BF16 matrix cores (three products of the hi / lo split)
   void run_gemm_bf16(const GemmLaunch& L, float alpha, float beta, int cls) {
     if (L.n == 0) return;
@@ -932,6 +943,12 @@ template <class T> struct Engine : EngineBase {
         } else {
           gemm<X>(gd, traits<X>::mk(-1.0, 0.0), traits<X>::one(), C_SCHUR, tmp);
         }
+      } else if constexpr (std::is_same<X, cf>::value) {
+        if (o.prec == HSS_PREC_BF16) {
+          run_gemm_cbf16(prep_gemm<X>(gd, tmp), traits<cf>::mk(-1.0, 0.0), traits<cf>::one(), C_SCHUR);
+        } else {
+          gemm<X>(gd, traits<X>::mk(-1.0, 0.0), traits<X>::one(), C_SCHUR, tmp);
+        }
       } else {
         gemm<X>(gd, traits<X>::mk(-1.0, 0.0), traits<X>::one(), C_SCHUR, tmp);
       }
@@ -1282,7 +1299,10 @@ template <class T> struct Engine : EngineBase {
     if (tol <= 0) return;  // S~ = S (same buffer)
     std::vector<int> todo;
     std::vector<int> lcur(nb_boxes), att(nb_boxes, 0);
-    std::vector<double> scale(nb_boxes, 1.0);
+    // the per-ID threshold starts at tol ||S||_F / (4 sqrt(2 n_id)): the 1/4 allows for
+    // the nested bases, through which a child's truncation error reaches the parent's
+    // block multiplied by the parent's interpolation matrix (entries up to 2)
+    std::vector<double> scale(nb_boxes, 0.25);
     std::vector<int> copy_boxes;
     for (int i = 0; i < nb_boxes; ++i) {
       const PNode& n = P.nodes[wv[i]];
@@ -2065,8 +2085,6 @@ template <class T> struct Engine : EngineBase {
 
 std::unique_ptr<EngineBase> make_engine(std::shared_ptr<const Plan> plan, const hss_opts_t& opts, bool cplx) {
   const bool fp64 = opts.prec == HSS_PREC_FP64;
-  if (opts.prec == HSS_PREC_BF16 && cplx)
-    throw Error(HSS_EUNSUPPORTED, "BF16 Schur products are built for real operators only");
   if (cplx) {
     if (fp64) return std::unique_ptr<EngineBase>(new Engine<cd>(std::move(plan), opts));
     return std::unique_ptr<EngineBase>(new Engine<cf>(std::move(plan), opts));
@@ -2106,6 +2124,13 @@ void debug_gemm_t(int nb, const void* const* A, const void* const* B, void* cons
       gemm_bf16x3_kernel<GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), (float)al[0], (float)be[0]);
     else
       gemm_nn_kernel<X, GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), (float)al[0], (float)be[0]);
+  } else if constexpr (std::is_same<X, cf>::value) {
+    if (bf16x3)
+      gemm_cbf16x3_kernel<GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), traits<cf>::mk(al[0], al[1]),
+                                                                   traits<cf>::mk(be[0], be[1]));
+    else
+      gemm_nn_kernel<X, GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), traits<cf>::mk(al[0], al[1]),
+                                                                  traits<cf>::mk(be[0], be[1]));
   } else {
     gemm_nn_kernel<X, GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), traits<X>::mk(al[0], al[1]),
                                                                 traits<X>::mk(be[0], be[1]));
@@ -2127,6 +2152,7 @@ void debug_gemm(int scalar, int nb, const void* const* A, const void* const* B, 
     case 2: debug_gemm_t<cf>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
     case 3: debug_gemm_t<cd>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
     case 4: debug_gemm_t<float>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st, true); break;
+    case 5: debug_gemm_t<cf>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st, true); break;
     default: throw Error(HSS_EINVAL, "unknown scalar code");
   }
 }

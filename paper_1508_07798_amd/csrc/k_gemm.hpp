@@ -332,4 +332,139 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmDesc* __rest
   });
 }
 
+// Complex64 operands on BF16 matrix cores, the same three-term split per real
+// product: Re C += Ar Br + (-Ai) Bi, Im C += Ar Bi + Ai Br, each real product as
+// hi*hi + hi*lo + lo*hi, i.e. 12 bf16 MFMAs per 16 x 16 x 32 block. A keeps six
+// bf16 planes in LDS (re, im and -im, each hi and lo; the negation is exact), B
+// four. Tiles, slabs and the prologue as gemm_bf16x3_kernel.
+template <int ROLE>
+__global__ __launch_bounds__(256) void gemm_cbf16x3_kernel(const GemmDesc* __restrict__ descs,
+                                                           const int* __restrict__ tprefix, int nent, cf alpha,
+                                                           cf beta) {
+  constexpr int BK = 32, LDK = BK + 8;
+  __shared__ __attribute__((aligned(16))) __bf16 As[6][GBM][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[4][GBN][LDK];
+  const int bid = blockIdx.x;
+  int lo = 0, hi = nent;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (tprefix[mid] <= bid) lo = mid; else hi = mid;
+  }
+  const GemmDesc g = descs[lo];
+  const int t = bid - tprefix[lo];
+  const int tmc = (g.M + GBM - 1) / GBM;
+  const int m0 = (t % tmc) * GBM, n0 = (t / tmc) * GBN;
+  const cf* __restrict__ Ag = (const cf*)g.A;
+  const cf* __restrict__ Bg = (const cf*)g.B;
+  cf* __restrict__ Cg = (cf*)g.C;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  v4f accr[2][2], acci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) accr[i][j] = acci[i][j] = v4f{0, 0, 0, 0};
+  constexpr int E = GBM * BK / 256;  // 8 values of A and of B per thread and slab
+  cf ra[E], rb[E];
+  const cf z = traits<cf>::zero();
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = tid + e * 256;
+      const int i = idx % GBM, k = idx / GBM;  // A: m fastest (coalesced)
+      const int gi = m0 + i, gk = k0 + k;
+      ra[e] = (gi < g.M && gk < g.K) ? Ag[gi + (size_t)gk * g.lda] : z;
+      const int kb = idx % BK, j = idx / BK;    // B: k fastest (coalesced)
+      const int gkb = k0 + kb, gj = n0 + j;
+      rb[e] = (gkb < g.K && gj < g.N) ? Bg[gkb + (size_t)gj * g.ldb] : z;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = tid + e * 256;
+      const int i = idx % GBM, k = idx / GBM;
+      const __bf16 rh = (__bf16)ra[e].x, ih = (__bf16)ra[e].y;
+      const __bf16 rl = (__bf16)(ra[e].x - (float)rh), il = (__bf16)(ra[e].y - (float)ih);
+      As[0][i][k] = rh;
+      As[1][i][k] = rl;
+      As[2][i][k] = ih;
+      As[3][i][k] = il;
+      As[4][i][k] = -ih;
+      As[5][i][k] = -il;
+      const int kb = idx % BK, j = idx / BK;
+      const __bf16 brh = (__bf16)rb[e].x, bih = (__bf16)rb[e].y;
+      Bs[0][j][kb] = brh;
+      Bs[1][j][kb] = (__bf16)(rb[e].x - (float)brh);
+      Bs[2][j][kb] = bih;
+      Bs[3][j][kb] = (__bf16)(rb[e].y - (float)bih);
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    store();
+    __syncthreads();
+    if (k0 + BK < g.K) load(k0 + BK);
+    bf16x8 a[6][2], b[4][2];  // [plane][block]
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int p = 0; p < 6; ++p) a[p][i] = *(const bf16x8*)&As[p][wm + i * 16 + li][lk * 8];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) b[p][i] = *(const bf16x8*)&Bs[p][wn + i * 16 + li][lk * 8];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        v4f r = accr[i][j], m = acci[i][j];
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[5][i], b[2][j], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[4][i], b[3][j], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[4][i], b[2][j], r, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[2][j], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[3][j], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[3][i], b[0][j], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[1][j], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], m, 0, 0, 0);
+        accr[i][j] = r;
+        acci[i][j] = m;
+      }
+    __syncthreads();
+  }
+  // all reads of C before the first store (see gemm_nn_kernel)
+  const bool rdc = !(beta.x == 0.f && beta.y == 0.f);
+  cf cv[2][2][4];
+  static_for<0, 2>([&](auto ii) {
+    static_for<0, 2>([&](auto jj) {
+      constexpr int i = decltype(ii)::value, j = decltype(jj)::value;
+      const int col = n0 + wn + j * 16 + li;
+      const bool keep = col < g.N && (col < g.z0 || col >= g.z1) && rdc;
+      static_for<0, 4>([&](auto vv) {
+        constexpr int v = decltype(vv)::value;
+        const int row = m0 + wm + i * 16 + mfma_acc<float>::row(lk, v);
+        cv[i][j][v] = (keep && row < g.M) ? Cg[row + (size_t)col * g.ldc] : z;
+      });
+    });
+  });
+  static_for<0, 2>([&](auto ii) {
+    static_for<0, 2>([&](auto jj) {
+      constexpr int i = decltype(ii)::value, j = decltype(jj)::value;
+      const int col = n0 + wn + j * 16 + li;
+      static_for<0, 4>([&](auto vv) {
+        constexpr int v = decltype(vv)::value;
+        const int row = m0 + wm + i * 16 + mfma_acc<float>::row(lk, v);
+        if (col < g.N && row < g.M)
+          Cg[row + (size_t)col * g.ldc] =
+              sc_mul(alpha, traits<cf>::mk(accr[i][j][v], acci[i][j][v])) + sc_mul(beta, cv[i][j][v]);
+      });
+    });
+  });
+}
+
 }  // namespace hss

@@ -61,7 +61,7 @@ template <class T> struct CompBox {
   T* Y;          // n x l = S Om
   int n, l, n_id;
   uint32_t node;     // heap id (Philox counter word)
-  double tol_scale;  // tol * 2^-(2 * retries)
+  double tol_scale;  // tol * 2^-(2 * (retries + 1))
   double* nrm2;      // ||S||_F^2
   double* err2;      // ||S - S~||_F^2
   int* flags;        // bit 0: an ID ran out of samples

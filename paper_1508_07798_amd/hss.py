@@ -381,7 +381,8 @@ def _scalar_code(t):
 def debug_gemm(As, Bs, Cs, alpha=1.0, beta=0.0, stream=None, bf16x3=False):
     """C_b = alpha A_b B_b + beta C_b in place (column-major views of CUDA tensors:
     pass tensors shaped [cols, rows] in row-major storage, i.e. X.T of the matrix).
-    bf16x3: float32 operands on the BF16 matrix cores (hi / lo split, three products)."""
+    bf16x3: float32 or complex64 operands on the BF16 matrix cores (hi / lo split, three
+    products per real product)."""
     L = lib()
     L.hss_debug_gemm.restype = C.c_int
     n = len(As)
@@ -389,9 +390,9 @@ def debug_gemm(As, Bs, Cs, alpha=1.0, beta=0.0, stream=None, bf16x3=False):
     I = C.c_int32 * n
     code = _scalar_code(As[0])
     if bf16x3:
-        if code != 0:
-            raise ValueError("bf16x3 takes float32 operands")
-        code = 4
+        if code not in (0, 2):
+            raise ValueError("bf16x3 takes float32 or complex64 operands")
+        code = 4 if code == 0 else 5
     M = I(*[c.shape[1] for c in Cs])
     N = I(*[c.shape[0] for c in Cs])
     K = I(*[a.shape[0] for a in As])

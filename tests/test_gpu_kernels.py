@@ -71,6 +71,31 @@ def test_batched_gemm_bf16x3():
         assert np.all(np.abs(got - R) <= 4e-5 * Mg + 1e-6), (m, n, k)
 
 
+def test_batched_gemm_complex_bf16x3():
+    """Complex64 operands on BF16 matrix cores: each of the four real products split
+    in three bf16 terms, so each real part carries the real kernel's error bound."""
+    print("complex bf16x3 gemm", flush=True)
+    rng = np.random.default_rng(19)
+    shapes = [(70, 45, 33), (1, 130, 7), (64, 64, 64), (129, 3, 200), (200, 150, 1), (300, 257, 513)]
+    cx = lambda *sh: (rng.standard_normal(sh) + 1j * rng.standard_normal(sh)).astype(np.complex64)
+    As, Bs, Cs, ref, mag = [], [], [], [], []
+    alpha, beta = -1.0 + 0.5j, 1.0 - 0.25j
+    for (m, n, k) in shapes:
+        A, B, Cm = cx(m, k), cx(k, n), cx(m, n)
+        A2, B2, C2 = A.astype(np.complex128), B.astype(np.complex128), Cm.astype(np.complex128)
+        ref.append(alpha * (A2 @ B2) + beta * C2)
+        mag.append(abs(alpha) * (np.abs(A2.real) + np.abs(A2.imag)) @ (np.abs(B2.real) + np.abs(B2.imag))
+                   + abs(beta) * np.abs(C2))
+        As.append(_dev(A, torch.complex64))
+        Bs.append(_dev(B, torch.complex64))
+        Cs.append(_dev(Cm, torch.complex64))
+    hss.debug_gemm(As, Bs, Cs, alpha=alpha, beta=beta, bf16x3=True)
+    for (m, n, k), Cd, R, Mg in zip(shapes, Cs, ref, mag):
+        got = Cd.cpu().numpy().T.astype(np.complex128)
+        assert np.all(np.abs(got.real - R.real) <= 4e-5 * Mg + 1e-6), (m, n, k)
+        assert np.all(np.abs(got.imag - R.imag) <= 4e-5 * Mg + 1e-6), (m, n, k)
+
+
 GJ_CASES = [(name, 0, ((1, 3), (7, 0), (33, 20), (100, 45), (200, 230))) for name in DT]
 # second-level blocks: forced narrow blocks over ragged sizes, and the automatic
 # choice for blocks above 512 rows (128-column blocks, ragged last block)

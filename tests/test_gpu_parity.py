@@ -127,11 +127,23 @@ def test_variable_coefficient_poisson(n, prec):
     h.close()
 
 
-def test_bf16_is_rejected_for_complex_operators():
-    P = configs.make("helmholtz_p2_64", n=8)
-    with pytest.raises(hss.HssError) as e:
-        hss.factor(P.op, P.tree, P.tol, prec="bf16")
-    assert e.value.status == -6
+@pytest.mark.parametrize("name,n", [("helmholtz_p2_64", 32), ("helmholtz_p2_64", None), ("helmholtz_p4_256", 32),
+                                    ("helmholtz_p4_256", 64)])
+def test_complex_bf16_schur_products(name, n):
+    """Complex operators with the Schur products on BF16 matrix cores (three-term
+    split): every box meets tol and GMRES reaches 1e-8 in the oracle's count +-1."""
+    P = configs.make(name, n=n)
+    print(f"{name} n={P.op.n} bf16", flush=True)
+    kh = P.kappa / P.op.n
+    h = hss.factor(P.op, P.tree, P.tol, prec="bf16", seed=P.seed, vals_dev=_t(P.op.vals), kappa_h=kh)
+    assert h.query("max_err")[0] <= P.tol
+    _check_p_bound(h)
+    b = P.rhs[:, 0]
+    x, info = h.gmres(_t(b), tol=P.gmres_tol)
+    g = GOLD[f"{name}@{P.op.n}"]
+    assert abs(info[0]["iters"] - g["iters"]) <= 1, (info, g["iters"])
+    assert _relres(P.op, b, x.cpu().numpy()) <= P.gmres_tol * 1.01
+    h.close()
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -234,7 +246,7 @@ def test_batched_workload_subset_matches_oracle():
 
 
 @pytest.mark.parametrize("name,n,restart", [("poisson_p1_16", None, 1), ("poisson_p1_16", None, 2),
-                                            ("helmholtz_p2_64", 16, 3)])
+                                            ("helmholtz_p2_64", 16, 2)])
 def test_restarted_gmres_matches_oracle(name, n, restart):
     """A cycle shorter than the iterations needed exercises the restart (the update
     of x and the recomputed residual): with the FP64 factor the preconditioner is
