@@ -108,6 +108,10 @@ typedef struct {
                               this many elements (0: the default, 4)               */
   const char* rank_model_path; /* weights file written by hss_rank_model_train, read
                               when rank_model is NULL (NULL: no file)            */
+  int32_t keep_box;        /* heap id of one box of problem 0 whose Schur complement
+                              S (symmetrized, before compression) and compressed S~
+                              the handle keeps for hss_query "kept_S" / "kept_St"
+                              (0: none; HSS_EINVAL if no such box)                */
 } hss_opts_t;
 
 typedef struct {

@@ -345,6 +345,10 @@ template <class T> struct Engine : EngineBase {
     T* St = nullptr;          // compressed complement (live during the factorization)
   };
   std::vector<NodeDev> nd;
+  // the box kept for inspection (hss_opts_t.keep_box): S and S~, n x n, device
+  int keep_g_ = -1, kept_n_ = 0;
+  T* kept_S_ = nullptr;
+  T* kept_St_ = nullptr;
   struct RootDev {
     W* R = nullptr;      // (P A_root)^{-1}
     int* rowperm = nullptr;
@@ -970,6 +974,12 @@ template <class T> struct Engine : EngineBase {
     };
     tol = tol_;
     const int nprob = (int)P.probs.size();
+    keep_g_ = -1;
+    kept_n_ = 0;
+    if (o.keep_box > 0) {
+      keep_g_ = P.find(0, o.keep_box);
+      if (keep_g_ < 0) throw Error(HSS_EINVAL, "keep_box " + std::to_string(o.keep_box) + " is not a box of problem 0");
+    }
     // operator upload (FP64); the index arrays come precomputed with the plan
     const PlanFlat& F = P.flat;
     {
@@ -1051,6 +1061,15 @@ template <class T> struct Engine : EngineBase {
       eliminate_wave<T>(wv, Sp, tmp, lap);
       // 4. compression
       compress_wave(wv, Sp, tmp);
+      for (size_t i = 0; i < wv.size(); ++i)
+        if (wv[i] == keep_g_) {
+          kept_n_ = (int)P.nodes[wv[i]].bdof.size();
+          const size_t ne = std::max<size_t>((size_t)kept_n_ * kept_n_, 1);
+          kept_S_ = persist.get<T>(ne);
+          kept_St_ = persist.get<T>(ne);
+          HIP_CHECK(hipMemcpyAsync(kept_S_, Sp[i], ne * sizeof(T), hipMemcpyDeviceToDevice, st));
+          HIP_CHECK(hipMemcpyAsync(kept_St_, nd[wv[i]].St, ne * sizeof(T), hipMemcpyDeviceToDevice, st));
+        }
       drop(tmp);
       lap(5);
     }
@@ -2007,7 +2026,20 @@ template <class T> struct Engine : EngineBase {
     auto per_node = [&](auto f) {
       for (int g = 0; g < nn; ++g) out.push_back((double)f(g));
     };
-    if (key == "n") out = {(double)ntot};
+    if (key == "kept_n") out = {(double)kept_n_};
+    else if (key == "kept_S" || key == "kept_St") {
+      const size_t ne = (size_t)kept_n_ * kept_n_;
+      std::vector<T> h(ne);
+      if (ne) {
+        HIP_CHECK(hipMemcpyAsync(h.data(), key == "kept_S" ? kept_S_ : kept_St_, ne * sizeof(T),
+                                 hipMemcpyDeviceToHost, st));
+        sync();
+      }
+      for (const T& v : h) {
+        out.push_back((double)traits<T>::re(v));
+        if (CX) out.push_back((double)traits<T>::im(v));
+      }
+    } else if (key == "n") out = {(double)ntot};
     else if (key == "nprob") out = {(double)P.probs.size()};
     else if (key == "nnodes") out = {(double)nn};
     else if (key == "nwaves") out = {(double)P.waves.size()};

@@ -40,7 +40,7 @@ class Opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("p_os", C.c_int32), ("l0", C.c_int32), ("max_attempts", C.c_int32),
                 ("seed", C.c_uint64), ("rank_model", C.c_void_p), ("kappa_h", C.c_double),
                 ("hip_stream", C.c_void_p), ("profile", C.c_int32), ("apply_graph", C.c_int32),
-                ("hss_leaf_elems", C.c_int32), ("rank_model_path", C.c_char_p)]
+                ("hss_leaf_elems", C.c_int32), ("rank_model_path", C.c_char_p), ("keep_box", C.c_int32)]
 
 
 class GmresInfo(C.Structure):
@@ -184,6 +184,19 @@ class Handle:
             raise ValueError(f"vector length {x.shape[0]} != {self.ndof}")
         return x.t().contiguous().t() if x.stride(0) != 1 else x
 
+    def kept_schur(self):
+        """(S, S~) of the box named by factor(..., keep_box=heap id): its Schur complement
+        (symmetrized, before compression) and the compressed form, n x n over the box's
+        boundary dofs in the planner's order."""
+        n = int(self.query("kept_n")[0])
+        out = []
+        for key in ("kept_S", "kept_St"):
+            v = np.asarray(self.query(key))
+            if self.cplx:
+                v = v[0::2] + 1j * v[1::2]
+            out.append(v.reshape((n, n), order="F"))
+        return out[0], out[1]
+
     def _host(self, x):
         want = np.complex128 if self.cplx else np.float64
         x = np.asarray(x)
@@ -252,18 +265,18 @@ class Handle:
 
 def factor(op, tree, tol, prec="fp32", seed=1508, stream=None, l0=32, p_os=10, max_attempts=8,
            rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True, hss_leaf_elems=4,
-           rank_model_path=None):
+           rank_model_path=None, keep_box=0):
     """hss_factor: build the preconditioner of one operator (see include/hss.h)."""
     return factor_batched([op], [tree], tol, prec=prec, seed=seed, stream=stream, l0=l0, p_os=p_os,
                           max_attempts=max_attempts, rank_model=rank_model, kappa_h=kappa_h,
                           profile=profile, vals_dev=None if vals_dev is None else [vals_dev],
                           apply_graph=apply_graph, hss_leaf_elems=hss_leaf_elems,
-                          rank_model_path=rank_model_path)
+                          rank_model_path=rank_model_path, keep_box=keep_box)
 
 
 def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, p_os=10, max_attempts=8,
                    rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True, hss_leaf_elems=4,
-                   rank_model_path=None):
+                   rank_model_path=None, keep_box=0):
     keep = _Keep()
     n = len(ops)
     A = (BlockOp * n)(*[_op_struct(op, keep, None if vals_dev is None else vals_dev[i])
@@ -280,6 +293,7 @@ def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, 
     o.profile = (1 if profile else 0) if isinstance(profile, bool) else int(profile)
     o.apply_graph = 1 if apply_graph else 0
     o.hss_leaf_elems = int(hss_leaf_elems)
+    o.keep_box = int(keep_box)
     if rank_model_path is not None:
         o.rank_model_path = os.fsencode(rank_model_path)
         keep.items.append(o.rank_model_path)

@@ -121,3 +121,35 @@ def test_rank_model_file_round_trip(tmp_path):
     with pytest.raises(hss.HssError) as e:
         hss.factor(Q.op, Q.tree, Q.tol, prec="fp32", seed=Q.seed, rank_model_path=str(tmp_path / "missing"))
     assert e.value.status == hss.HSS_EINVAL
+
+
+@pytest.mark.parametrize("name,prec,box,tol_s", [("poisson_p1_16", "fp64", "leaf", 1e-12),
+                                                 ("poisson_p1_16", "fp64", 2, 1e-10),
+                                                 ("helmholtz_p2_64", "fp32", "leaf", 2e-5)])
+def test_kept_schur_complement_matches_oracle(name, prec, box, tol_s):
+    """One box's Schur complement S (symmetrized, before compression) and its
+    compressed S~, kept by the handle (keep_box): S equals the oracle's S of the same
+    box element by element (a leaf takes identical inputs; in FP64 a merge box too,
+    since its children's S~ then agree), and ||S - S~||_F / ||S||_F recomputed on the
+    host meets tol and equals the judge's figure for the box."""
+    P = configs.make(name, n=16)
+    heap = int(P.tree.leaf_node[0]) if box == "leaf" else box
+    print(f"kept S {name} {prec} box {heap}", flush=True)
+    kh = P.kappa / P.op.n if P.kappa else 0.0
+    h = hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, kappa_h=kh, keep_box=heap)
+    S, St = h.kept_schur()
+    F = OracleFactor(P.op, P.tree, P.tol, seed=P.seed)
+    nf = F.nodes[heap]
+    assert S.shape == nf.S.shape and S.shape[0] > 0
+    assert np.linalg.norm(S - nf.S) <= tol_s * np.linalg.norm(nf.S)
+    e = np.linalg.norm(S - St) / np.linalg.norm(S)
+    assert e <= P.tol
+    heaps = h.query("node_heap").astype(int)
+    e_dev = float(h.query("err")[heaps == heap][0])
+    assert abs(e - e_dev) <= 1e-3 * e_dev + 1e-12
+    if prec == "fp64":
+        assert np.linalg.norm(St - nf.S_tilde) <= 1e-8 * np.linalg.norm(nf.S_tilde)
+    h.close()
+    with pytest.raises(hss.HssError) as ex:
+        hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, keep_box=1 << 20)
+    assert ex.value.status == hss.HSS_EINVAL
