@@ -32,8 +32,8 @@ hss_status_t hss_debug_gemm(int32_t scalar, int32_t nbatch, const void* const* A
 /* In-place [A_b | B_b] -> [A_b^{-1} | A_b^{-1} B_b] (n_b x (n_b + m_b), ld n_b) by
  * the blocked Gauss-Jordan elimination with partial pivoting that the
  * factorization uses for every A^_ii. block = 0 keeps the factorization's own
- * choice of second-level blocking; block in [1, 128] forces blocks of that many
- * pivot columns (HSS_EINVAL outside [0, 128]). *singular receives 1 if a pivot
+ * choice of second-level blocking; block in [1, 256] forces blocks of that many
+ * pivot columns (HSS_EINVAL outside [0, 256]). *singular receives 1 if a pivot
  * was 0. */
 hss_status_t hss_debug_gj(int32_t scalar, int32_t nbatch, void* const* Mat, const int32_t* n,
                           const int32_t* m, int32_t block, int32_t* singular, void* hip_stream);

@@ -358,7 +358,7 @@ hss_status_t hss_debug_gj(int32_t scalar, int32_t nbatch, void* const* Mat, cons
                           int32_t block, int32_t* singular, void* hip_stream) {
   return guarded([&]() -> hss_status_t {
     if (nbatch < 0 || !Mat || !n || !m || !singular) return fail(HSS_EINVAL, "bad gj arguments");
-    if (block < 0 || block > 128) return fail(HSS_EINVAL, "gj block width must be in [0, 128]");
+    if (block < 0 || block > 256) return fail(HSS_EINVAL, "gj block width must be in [0, 256]");
     for (int b = 0; b < nbatch; ++b)
       if (n[b] < 0 || m[b] < 0) return fail(HSS_EINVAL, "bad gj sizes");
     ensure_device();

@@ -975,7 +975,7 @@ __global__ __launch_bounds__(256) void gj_rows_kernel(const GjDesc<T>* __restric
 // M) the product is exactly the block's Gauss-Jordan update; the identity in
 // rbuf's block columns (beta = 0 there) writes pb back into M.
 
-constexpr int GJ_BLOCK_MAX = 128;  // widest block (2 GJ_BLOCK_MAX <= 256 moved rows)
+constexpr int GJ_BLOCK_MAX = 256;  // widest block (at most 2 GJ_BLOCK_MAX moved rows)
 constexpr int GJ_BLOCK_TILE = 16;  // columns per workgroup of gj_block_rows
 
 // pb = M(:, J : J + wb); grid (chunks, box)
@@ -1016,13 +1016,23 @@ __global__ __launch_bounds__(256) void gj_block_moves_kernel(const GjDesc<T>* __
   }
   __syncthreads();
   const int nm = min(s_cnt, 2 * GJ_BLOCK_MAX);
-  const int v = tid < nm ? g.rowperm[s_src[tid]] : 0;
+  constexpr int MPT = 2 * GJ_BLOCK_MAX / 256;  // moves per thread
+  int v[MPT];
+  static_for<0, MPT>([&](auto uu) {
+    constexpr int u = decltype(uu)::value;
+    const int i = tid + u * 256;
+    v[u] = i < nm ? g.rowperm[s_src[i]] : 0;
+  });
   __syncthreads();
-  if (tid < nm) {
-    g.rowperm[s_dst[tid]] = v;
-    g.mv[1 + 2 * tid] = s_dst[tid] - J;
-    g.mv[2 + 2 * tid] = s_src[tid] - J;
-  }
+  static_for<0, MPT>([&](auto uu) {
+    constexpr int u = decltype(uu)::value;
+    const int i = tid + u * 256;
+    if (i < nm) {
+      g.rowperm[s_dst[i]] = v[u];
+      g.mv[1 + 2 * i] = s_dst[i] - J;
+      g.mv[2 + 2 * i] = s_src[i] - J;
+    }
+  });
   if (tid == 0) g.mv[0] = nm;
 }
 

@@ -100,6 +100,7 @@ GJ_CASES = [(name, 0, ((1, 3), (7, 0), (33, 20), (100, 45), (200, 230))) for nam
 # second-level blocks: forced narrow blocks over ragged sizes, and the automatic
 # choice for blocks above 512 rows (128-column blocks, ragged last block)
 GJ_CASES += [(name, 32, ((1, 3), (7, 0), (33, 20), (100, 45), (200, 230))) for name in DT]
+GJ_CASES += [("complex128", 256, ((600, 70), (530, 0), (40, 9))), ("float32", 256, ((700, 30), (257, 3)))]
 GJ_CASES += [("float64", 0, ((600, 70), (530, 0), (40, 9))), ("complex64", 0, ((600, 70), (530, 0), (40, 9))),
              ("float32", 100, ((450, 30), (129, 1))),
              # tall double panels (beyond the register-resident kernel)
