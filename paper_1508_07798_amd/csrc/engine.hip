@@ -607,7 +607,7 @@ template <class T> struct Engine : EngineBase {
   struct GjCfg {
     int nb, rpt;
     bool rot, reg, lds, tourn;
-    int nch;  // tournament: chunks of kTournChunk candidate rows
+    int nch;  // tournament: chunks of tourn_chunk<X>() candidate rows
     int* cand;
     size_t shm;
     PanelShape ps;
@@ -627,8 +627,8 @@ template <class T> struct Engine : EngineBase {
                                         " rows are not supported (at most 2048)");
     // taller panels: tournament pivoting over chunks held by the compact kernel
     if constexpr (!std::is_same<X, cf>::value) {
-      const int nch = cdiv(rmax, kTournChunk);
-      if (nch * tourn_nb<X>() <= kTournCand) {
+      const int nch = cdiv(rmax, tourn_chunk<X>());
+      if (nch * tourn_nb<X>() <= tourn_cand<X>()) {
         c.tourn = true;
         c.nb = tourn_nb<X>();
         c.nch = nch;

@@ -67,11 +67,10 @@ void launch_panel_rot(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelSh
 
 template <class X>
 void launch_panel_tourn(const GjDesc<X>* dd, int nn, int j0, int nb, int nch, int* cand, hipStream_t st) {
-  constexpr int NB = tourn_nb<X>();
-  static_assert(kTournChunk == 4 * 256 && kTournCand == 256, "launch shapes below");
-  if (nb != NB || nch < 1 || nch * NB > kTournCand) throw Error(HSS_EINVAL, "tournament panel shape");
-  gj_tourn_local_kernel<X, NB, 4, 256><<<dim3(nch, nn), 256, 0, st>>>(dd, j0, nb, nch, cand);
-  gj_tourn_final_kernel<X, NB, 1, 256><<<nn, 256, 0, st>>>(dd, j0, nb, nch, cand);
+  constexpr int NB = tourn_nb<X>(), RPT = tourn_rpt<X>(), RPTF = tourn_cand<X>() / 256;
+  if (nb != NB || nch < 1 || nch * NB > tourn_cand<X>()) throw Error(HSS_EINVAL, "tournament panel shape");
+  gj_tourn_local_kernel<X, NB, RPT, 256><<<dim3(nch, nn), 256, 0, st>>>(dd, j0, nb, nch, cand);
+  gj_tourn_final_kernel<X, NB, RPTF, 256><<<nn, 256, 0, st>>>(dd, j0, nb, nch, cand);
 }
 
 template bool panel_rot_config<float>(int, PanelShape&);

@@ -21,12 +21,14 @@ template <class X> bool panel_rot_config(int rows, PanelShape& s);
 template <class X>
 void launch_panel_rot(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelShape& s, hipStream_t st);
 
-// Tournament pivoting for panels above the compact kernels' capacity: the width,
-// the chunk of rows each local search holds (kTournChunk) and the largest number of
-// candidate rows of the final search (kTournCand).
-constexpr int kTournChunk = 1024;
-constexpr int kTournCand = 256;
-template <class X> constexpr int tourn_nb() { return std::is_same<X, cd>::value ? 8 : 16; }
+// Tournament pivoting for panels above the compact kernels' capacity: the width
+// (16), the chunk of rows each local search holds in registers (tourn_chunk: four
+// rows per thread, two for complex128, whose values take four registers each) and
+// the largest number of candidate rows of the final search (tourn_cand).
+template <class X> constexpr int tourn_nb() { return 16; }
+template <class X> constexpr int tourn_rpt() { return std::is_same<X, cd>::value ? 2 : 4; }
+template <class X> constexpr int tourn_chunk() { return 256 * tourn_rpt<X>(); }
+template <class X> constexpr int tourn_cand() { return std::is_same<X, cd>::value ? 512 : 256; }
 
 // Launch the local searches (grid nch x nn) and the final search (grid nn) of one
 // panel step; cand holds nn * nch * tourn_nb<X>() ints.
