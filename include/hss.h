@@ -207,6 +207,30 @@ hss_status_t hss_plan_query(hss_plan_t p, const char* key, int32_t node, int64_t
                             int64_t cap, int64_t* len);
 void hss_plan_destroy(hss_plan_t p);
 
+/* Tuning table of the Gauss-Jordan kernels that eliminate the box interiors, as
+ * written by the project's autotuner (paper_1508_07798_amd/autotune.py): per
+ * scalar type (0 float, 1 double, 2 complex float, 3 complex double) and size
+ * class (boxes of at most 128, 256, 512, 1024, 2048 or 4096 interior rows) a
+ * compact panel shape (width nb, rows per thread rpt, threads nt; nt = 0 keeps
+ * the built-in choice) and a second-level block width (-1: built-in, 0: none,
+ * else at most 256 columns). The library reads tuning_gfx950.json beside
+ * libhss.so at the first factorization ($HSS_TUNING names another file; an empty
+ * value: none) unless a call below has set the table first. An entry whose shape is not compiled or holds fewer rows than a
+ * box is ignored for that box. The table is process-wide; changing it while
+ * another thread factorizes is a race.
+ *   hss_tuning_load        reads a JSON file {"entries": [{"scalar": "complex64",
+ *                          "rows": 1024, "nb": 16, "rpt": 4, "nt": 256,
+ *                          "block": 128}, ...]}; HSS_EINVAL if malformed
+ *   hss_tuning_set         one entry (rows_class one of the class sizes)
+ *   hss_tuning_clear       back to the built-in rules
+ *   hss_tuning_candidates  the compiled shapes that hold `rows` rows: (nb, rpt, nt)
+ *                          triples into out (host, at most cap), *count all of them */
+hss_status_t hss_tuning_load(const char* path);
+hss_status_t hss_tuning_set(int32_t scalar, int32_t rows_class, int32_t nb, int32_t rpt, int32_t nt,
+                            int32_t block);
+void hss_tuning_clear(void);
+hss_status_t hss_tuning_candidates(int32_t scalar, int32_t rows, int32_t* out, int32_t cap, int32_t* count);
+
 /* ---- rank-predictor MLP (8 -> 64 -> 64 -> 1, tanh) ---------------------
  * Not in the paper: it replaces the anticipated rank of Section 4 by a
  * learned prediction. Device pointers; weights as in hss_opts_t.rank_model.

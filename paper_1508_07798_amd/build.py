@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhss.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["planner.cpp", "capi.cpp", "engine.hip", "mlp.hip", "panel.hip"]
+SOURCES = ["planner.cpp", "tuning.cpp", "capi.cpp", "engine.hip", "mlp.hip", "panel.hip"]
 ARCH = os.environ.get("HSS_OFFLOAD_ARCH", "gfx950")
 
 
@@ -52,7 +52,7 @@ def build(verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs]
+    cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs, "-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -13,6 +13,7 @@
 #include "common.hpp"
 #include "engine.hpp"
 #include "planner.hpp"
+#include "tuning.hpp"
 
 namespace hss {
 void mlp_forward(const float* w, const float* x, int n, float* y, hipStream_t st);
@@ -24,6 +25,7 @@ void mlp_grad_noalloc(const float* w, const float* x, const float* t, int n, flo
 std::vector<float> mlp_read(const char* path);
 void rank_model_train(const float* feat, const float* rank, int n, const char* path, uint64_t seed);
 int mlp_noalloc_max_n();
+int panel_candidates(int scalar, int rows, int32_t* out, int cap);
 }  // namespace hss
 
 struct hss_ctx {
@@ -175,6 +177,7 @@ hss_status_t hss_factor_batched(int32_t nprob, const hss_block_op_t* A, const hs
     const int leaf = opts.hss_leaf_elems > 0 ? opts.hss_leaf_elems : 4;
     if (opts.prec != HSS_PREC_FP64 && opts.prec != HSS_PREC_FP32 && opts.prec != HSS_PREC_BF16)
       return fail(HSS_EINVAL, "unknown precision");
+    hss::tuning_load_default();
     std::shared_ptr<const hss::Plan> plan = plan_for(nprob, A, T, leaf);
     for (int p = 0; p < nprob; ++p) check_finite_host(A[p]);
     ensure_device();
@@ -280,6 +283,37 @@ hss_status_t hss_plan_query(hss_plan_t p, const char* key, int32_t node, int64_t
 
 void hss_plan_destroy(hss_plan_t p) { delete p; }
 
+hss_status_t hss_tuning_load(const char* path) {
+  return guarded([&]() -> hss_status_t {
+    if (!path) return fail(HSS_EINVAL, "null path");
+    hss::tuning_load(path);
+    return HSS_OK;
+  });
+}
+
+hss_status_t hss_tuning_set(int32_t scalar, int32_t rows_class, int32_t nb, int32_t rpt, int32_t nt, int32_t block) {
+  return guarded([&]() -> hss_status_t {
+    if (nb < 0 || rpt < 0 || nt < 0 || block < -1) return fail(HSS_EINVAL, "bad tuning entry");
+    hss::TuneEntry e;
+    e.nb = nb;
+    e.rpt = rpt;
+    e.nt = nt;
+    e.block = block;
+    hss::tuning_set(scalar, rows_class, e);
+    return HSS_OK;
+  });
+}
+
+void hss_tuning_clear(void) { hss::tuning_clear(); }
+
+hss_status_t hss_tuning_candidates(int32_t scalar, int32_t rows, int32_t* out, int32_t cap, int32_t* count) {
+  return guarded([&]() -> hss_status_t {
+    if (scalar < 0 || scalar > 3 || rows < 1 || !count || cap < 0) return fail(HSS_EINVAL, "bad arguments");
+    *count = hss::panel_candidates(scalar, rows, out, cap);
+    return HSS_OK;
+  });
+}
+
 hss_status_t hss_mlp_forward(const float* w, const float* x, int32_t n, float* y, void* stream) {
   return guarded([&]() -> hss_status_t {
     if (!w || !x || !y || n < 1) return fail(HSS_EINVAL, "bad mlp arguments");
@@ -362,6 +396,7 @@ hss_status_t hss_debug_gj(int32_t scalar, int32_t nbatch, void* const* Mat, cons
     for (int b = 0; b < nbatch; ++b)
       if (n[b] < 0 || m[b] < 0) return fail(HSS_EINVAL, "bad gj sizes");
     ensure_device();
+    hss::tuning_load_default();
     hss::debug_gj(scalar, nbatch, Mat, n, m, block, singular, (hipStream_t)hip_stream);
     return HSS_OK;
   });

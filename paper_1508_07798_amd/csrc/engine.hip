@@ -18,6 +18,7 @@
 #include "k_hss.hpp"
 #include "k_vec.hpp"
 #include "panel.hpp"
+#include "tuning.hpp"
 
 namespace hss {
 
@@ -607,14 +608,31 @@ template <class T> struct Engine : EngineBase {
   struct GjCfg {
     int nb, rpt;
     bool rot, reg, lds, tourn;
-    int nch;  // tournament: chunks of tourn_chunk<X>() candidate rows
+    int nch;    // tournament: chunks of tourn_chunk<X>() candidate rows
+    int block;  // second-level block width from the tuning table (-1: the built-in rule)
     int* cand;
     size_t shm;
     PanelShape ps;
   };
+  template <class X> static constexpr int scalar_code() {
+    return std::is_same<X, float>::value ? 0 : std::is_same<X, double>::value ? 1 : std::is_same<X, cf>::value ? 2 : 3;
+  }
   template <class X> GjCfg gj_config(int rmax) const {
     const int sX = (int)sizeof(X);
     GjCfg c{};
+    c.block = -1;
+    // the tuning table (autotuner), where it names a compiled shape that holds rmax rows
+    TuneEntry te;
+    if (tuning_lookup(scalar_code<X>(), rmax, te)) {
+      c.block = te.block;
+      const PanelShape s{te.nb, te.rpt, te.nt};
+      if (te.nt > 0 && te.rpt * te.nt >= rmax && panel_rot_compiled<X>(s)) {
+        c.rot = true;
+        c.ps = s;
+        c.nb = s.nb;
+        return c;
+      }
+    }
     if (panel_rot_config<X>(rmax, c.ps)) {
       c.rot = true;
       c.nb = c.ps.nb;
@@ -728,6 +746,7 @@ template <class T> struct Engine : EngineBase {
     const int nb = c.nb;
     if (c.tourn) c.cand = ar.get<int>(ds.size() * (size_t)c.nch * nb);
     int wo = block > 0 ? std::min(block, GJ_BLOCK_MAX)
+                       : c.block >= 0 ? std::min(c.block, GJ_BLOCK_MAX)
                        : (nmax > kGjBlockWideAbove ? kGjBlockWide : nmax > kGjBlockMin ? kGjBlock : 0);
     if (wo >= nmax) wo = 0;
     // scratch per box

@@ -41,12 +41,14 @@ bool panel_rot_config(int rows, PanelShape& s) {
   return false;
 }
 
+// Launches the compact panel of shape s (dd == nullptr: only reports whether that
+// shape is compiled); false when it is not.
 template <class X>
-void launch_panel_rot(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelShape& s, hipStream_t st) {
+bool panel_rot_variant(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelShape& s, hipStream_t st) {
 #define HSS_ROT(NB_, RPT_, NT_)                                                      \
   if (s.nb == NB_ && s.rpt == RPT_ && s.nt == NT_) {                                 \
-    gj_panel_rot_kernel<X, NB_, RPT_, NT_><<<nn, NT_, 0, st>>>(dd, j0, nb);          \
-    return;                                                                          \
+    if (dd) gj_panel_rot_kernel<X, NB_, RPT_, NT_><<<nn, NT_, 0, st>>>(dd, j0, nb);  \
+    return true;                                                                     \
   }
   if constexpr (std::is_same<X, cd>::value) {
     HSS_ROT(8, 1, 128)
@@ -61,8 +63,18 @@ void launch_panel_rot(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelSh
     HSS_ROT(16, 6, 512) HSS_ROT(16, 8, 512)
   }
 #undef HSS_ROT
-  throw Error(HSS_EDEVICE, "no panel variant for nb " + std::to_string(s.nb) + ", rpt " + std::to_string(s.rpt) +
-                               ", threads " + std::to_string(s.nt));
+  return false;
+}
+
+template <class X>
+void launch_panel_rot(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelShape& s, hipStream_t st) {
+  if (!panel_rot_variant<X>(dd, nn, j0, nb, s, st))
+    throw Error(HSS_EDEVICE, "no panel variant for nb " + std::to_string(s.nb) + ", rpt " + std::to_string(s.rpt) +
+                                 ", threads " + std::to_string(s.nt));
+}
+
+template <class X> bool panel_rot_compiled(const PanelShape& s) {
+  return panel_rot_variant<X>(nullptr, 0, 0, 0, s, nullptr);
 }
 
 template <class X>
@@ -73,6 +85,35 @@ void launch_panel_tourn(const GjDesc<X>* dd, int nn, int j0, int nb, int nch, in
   gj_tourn_final_kernel<X, NB, RPTF, 256><<<nn, 256, 0, st>>>(dd, j0, nb, nch, cand);
 }
 
+// compiled compact panel shapes of a scalar type (0 float, 1 double, 2 complex
+// float, 3 complex double) that hold `rows` rows: (nb, rpt, nt) triples into out
+// (at most cap), their count returned
+int panel_candidates(int scalar, int rows, int32_t* out, int cap) {
+  int n = 0;
+  for (int nb : {8, 16})
+    for (int nt : {128, 256, 512})
+      for (int rpt = 1; rpt <= 8; ++rpt) {
+        const PanelShape s{nb, rpt, nt};
+        if (rpt * nt < rows) continue;
+        const bool ok = scalar == 0   ? panel_rot_compiled<float>(s)
+                        : scalar == 1 ? panel_rot_compiled<double>(s)
+                        : scalar == 2 ? panel_rot_compiled<cf>(s)
+                                      : panel_rot_compiled<cd>(s);
+        if (!ok) continue;
+        if (out && n < cap) {
+          out[3 * n] = nb;
+          out[3 * n + 1] = rpt;
+          out[3 * n + 2] = nt;
+        }
+        ++n;
+      }
+  return n;
+}
+
+template bool panel_rot_compiled<float>(const PanelShape&);
+template bool panel_rot_compiled<double>(const PanelShape&);
+template bool panel_rot_compiled<cf>(const PanelShape&);
+template bool panel_rot_compiled<cd>(const PanelShape&);
 template bool panel_rot_config<float>(int, PanelShape&);
 template bool panel_rot_config<double>(int, PanelShape&);
 template bool panel_rot_config<cf>(int, PanelShape&);

@@ -17,6 +17,9 @@ struct PanelShape {
 // no instantiation holds that many rows in registers.
 template <class X> bool panel_rot_config(int rows, PanelShape& s);
 
+// Whether a compact panel of shape s is compiled for X.
+template <class X> bool panel_rot_compiled(const PanelShape& s);
+
 // Launch gj_panel_rot_kernel for nn boxes (descriptors on the device).
 template <class X>
 void launch_panel_rot(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelShape& s, hipStream_t st);

@@ -23,7 +23,8 @@ MLP_NPARAMS = 4801
 
 EXPORTS = ["hss_default_opts", "hss_factor", "hss_factor_batched", "hss_apply", "gmres_solve", "hss_query",
            "hss_destroy", "hss_last_error", "hss_plan_create", "hss_plan_query", "hss_plan_destroy",
-           "hss_mlp_forward", "hss_mlp_grad", "hss_mlp_train", "hss_mlp_grad_noalloc", "hss_rank_model_train"]
+           "hss_mlp_forward", "hss_mlp_grad", "hss_mlp_train", "hss_mlp_grad_noalloc", "hss_rank_model_train",
+           "hss_tuning_load", "hss_tuning_set", "hss_tuning_clear", "hss_tuning_candidates"]
 
 
 class BlockOp(C.Structure):
@@ -65,7 +66,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.hss_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("hss_last_error", "hss_default_opts", "hss_destroy", "hss_plan_destroy"):
+            if name not in ("hss_last_error", "hss_default_opts", "hss_destroy", "hss_plan_destroy",
+                            "hss_tuning_clear"):
                 getattr(L, name).restype = C.c_int
         L.hss_factor.argtypes = [C.POINTER(BlockOp), C.POINTER(TreeC), C.c_double, C.POINTER(Opts),
                                  C.POINTER(C.c_void_p)]
@@ -84,6 +86,11 @@ def lib():
         L.hss_rank_model_train.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_char_p, C.c_uint64]
         L.hss_plan_query.argtypes = [C.c_void_p, C.c_char_p, C.c_int32, C.POINTER(C.c_int64), C.c_int64,
                                      C.POINTER(C.c_int64)]
+        L.hss_tuning_load.argtypes = [C.c_char_p]
+        L.hss_tuning_set.argtypes = [C.c_int32] * 6
+        L.hss_tuning_clear.argtypes = []
+        L.hss_tuning_clear.restype = None
+        L.hss_tuning_candidates.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
         L.hss_plan_destroy.argtypes = [C.c_void_p]
         L.hss_plan_destroy.restype = None
         L.hss_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
@@ -450,3 +457,30 @@ def debug_row_id(Z, thresh, p_os=10, stream=None):
                               C.c_void_p(_stream_ptr(stream))))
     kk = k.value
     return kk, np.array(skel[:kk], dtype=np.int64), U.cpu().numpy().T[:, :kk], tm.value
+
+
+SCALAR_CODE = {"float32": 0, "float64": 1, "complex64": 2, "complex128": 3}
+
+
+def tuning_load(path):
+    """hss_tuning_load: read an autotuner JSON file into the process-wide table."""
+    _check(lib().hss_tuning_load(os.fsencode(path)))
+
+
+def tuning_set(scalar, rows_class, nb=0, rpt=0, nt=0, block=-1):
+    """hss_tuning_set: one entry of the table (scalar: a SCALAR_CODE key)."""
+    _check(lib().hss_tuning_set(SCALAR_CODE[scalar], rows_class, nb, rpt, nt, block))
+
+
+def tuning_clear():
+    lib().hss_tuning_clear()
+
+
+def tuning_candidates(scalar, rows):
+    """Compiled compact panel shapes (nb, rpt, nt) that hold `rows` rows."""
+    n = C.c_int32(0)
+    _check(lib().hss_tuning_candidates(SCALAR_CODE[scalar], rows, None, 0, C.byref(n)))
+    buf = (C.c_int32 * max(3 * n.value, 1))()
+    _check(lib().hss_tuning_candidates(SCALAR_CODE[scalar], rows, buf, n.value, C.byref(n)))
+    return [tuple(buf[3 * i:3 * i + 3]) for i in range(n.value)]
+

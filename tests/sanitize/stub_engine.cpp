@@ -19,6 +19,7 @@ void mlp_grad(const float*, const float*, const float*, int, float*, double*, hi
 void mlp_train(float*, const float*, const float*, int, int, float, float*, hipStream_t) { no_device(); }
 void mlp_grad_noalloc(const float*, const float*, const float*, int, float*, double*, hipStream_t) { no_device(); }
 int mlp_noalloc_max_n() { return 8192; }
+int panel_candidates(int, int, int32_t*, int) { return 0; }
 std::vector<float> mlp_read(const char*) { no_device(); }
 void rank_model_train(const float*, const float*, int, const char*, uint64_t) { no_device(); }
 void debug_gemm(int, int, const void* const*, const void* const*, void* const*, const int32_t*, const int32_t*,

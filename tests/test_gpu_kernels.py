@@ -2,6 +2,8 @@
 GEMM and the batched Gauss-Jordan elimination against NumPy on ragged,
 multi-tile shapes for every scalar type, and the row ID of one HSS node
 against the oracle's (including the strong-RRQR swaps on Kahan's matrix)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -134,6 +136,38 @@ def test_batched_gauss_jordan(name, block, sizes):
         if m:
             e2 = np.abs(got[:, n:] - X).max() / np.abs(X).max()
             assert e2 <= tol * cond * 50, (n, e2, cond)
+
+
+@pytest.mark.parametrize("name,rows", [("complex64", 1000), ("complex128", 900), ("float32", 3000),
+                                       ("float64", 500)])
+def test_every_tunable_panel_shape_inverts(name, rows):
+    """Every compiled compact panel shape that the tuning table may name for a size
+    class, with the block widths the autotuner tries, inverts the box."""
+    npdt, tdt, tol = DT[name]
+    cls = min(c for c in (128, 256, 512, 1024, 2048, 4096) if c >= rows)
+    cands = hss.tuning_candidates(name, rows)
+    assert cands
+    print(f"tunable shapes {name} rows={rows}: {cands}", flush=True)
+    rng = np.random.default_rng(21)
+    A = _rand(rng, (rows, rows), npdt) + np.sqrt(rows) * np.eye(rows, dtype=npdt)
+    B = _rand(rng, (rows, 7), npdt)
+    A64 = A.astype(np.complex128)
+    Ainv, X, cond = np.linalg.inv(A64), np.linalg.solve(A64, B.astype(np.complex128)), np.linalg.cond(A64)
+    try:
+        for nb, rpt, nt in cands:
+            for blk in (0, 64, 256):
+                hss.tuning_set(name, cls, nb, rpt, nt, blk)
+                Md = _dev(np.concatenate([A, B], axis=1), tdt)
+                assert hss.debug_gj([Md], [rows], [7]) == 0
+                got = Md.cpu().numpy().T
+                e1 = np.abs(got[:, :rows] - Ainv).max() / np.abs(Ainv).max()
+                e2 = np.abs(got[:, rows:] - X).max() / np.abs(X).max()
+                assert e1 <= tol * cond * 50 and e2 <= tol * cond * 50, (nb, rpt, nt, blk, e1, e2)
+    finally:
+        hss.tuning_clear()
+        default = os.path.join(os.path.dirname(hss.LIB_PATH), "tuning_gfx950.json")
+        if os.path.exists(default):
+            hss.tuning_load(default)
 
 
 TALL_COMPLEX64_SKIP = ("complex64 Gauss-Jordan above 2048 rows (register panel at 3,150 rows) faulted the GPU "

@@ -109,3 +109,32 @@ def test_factor_without_gpu_or_with_nan_fails_cleanly():
     with pytest.raises(hss.HssError) as e:
         hss.factor(P.op, P.tree, -1.0, stream=0)
     assert e.value.status == hss.HSS_EINVAL
+
+
+def test_tuning_table_io(tmp_path):
+    """The tuning table: compiled shapes per class, the JSON reader, and the checks."""
+    import json
+    c = hss.tuning_candidates("complex64", 1024)
+    assert (16, 4, 256) in c and all(r * t >= 1024 for _, r, t in c)
+    assert (8, 4, 256) in hss.tuning_candidates("complex128", 1000)
+    assert hss.tuning_candidates("complex64", 3000) == []
+    assert (16, 8, 512) in hss.tuning_candidates("float32", 4096)
+    good = tmp_path / "t.json"
+    good.write_text(json.dumps({"arch": "gfx950", "entries": [
+        {"scalar": "complex64", "rows": 1024, "nb": 16, "rpt": 4, "nt": 256, "block": 128, "ms": 1.5,
+         "tried": [{"nb": 16, "ms": 2.0}]},
+        {"scalar": "float64", "rows": 128, "nb": 0, "rpt": 0, "nt": 0, "block": -1}]}))
+    hss.tuning_load(str(good))
+    for text in ('{"entries": [{"scalar": "complex64", "rows": 1000}]}',   # not a size class
+                 '{"entries": [{"scalar": "int8", "rows": 128}]}',         # not a scalar type
+                 '{"entries": [{"scalar": "float32", "rows": 128}'):        # truncated
+        bad = tmp_path / "b.json"
+        bad.write_text(text)
+        with pytest.raises(hss.HssError) as e:
+            hss.tuning_load(str(bad))
+        assert e.value.status == hss.HSS_EINVAL
+    with pytest.raises(hss.HssError):
+        hss.tuning_set("float32", 100, 16, 1, 128, 0)
+    with pytest.raises(hss.HssError):
+        hss.tuning_load(str(tmp_path / "missing.json"))
+    hss.tuning_clear()

@@ -31,8 +31,8 @@ def driver(tmp_path_factory):
            "-fno-sanitize-recover=undefined", "-static-libasan", "-D__HIP_PLATFORM_AMD__",
            "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
            os.path.join(SAN, "plan_driver.cpp"), os.path.join(SAN, "stub_engine.cpp"),
-           os.path.join(CSRC, "capi.cpp"), os.path.join(CSRC, "planner.cpp"),
-           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lamdhip64", "-o", out]
+           os.path.join(CSRC, "capi.cpp"), os.path.join(CSRC, "planner.cpp"), os.path.join(CSRC, "tuning.cpp"),
+           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lamdhip64", "-ldl", "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-4000:]
     return out
