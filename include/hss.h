@@ -178,6 +178,8 @@ hss_status_t gmres_solve(hss_handle_t h, int32_t nrhs, const void* b, void* x, i
  * work of the explicit Gauss-Jordan form the library executes),
  * "bytes_apply", "bytes_spmv", "time_factor_ms", "host_wait_ms"
  * (time the factorization spent waiting for the device at its sync points),
+ * "root_block" (block width of the roots' block LDU form; 0: the roots, of at
+ * most 128 rows, are stored as explicit inverses),
  * "phase_ms" (8 values: host wall time of operator upload, features, gather,
  * Gauss-Jordan, Schur GEMM, compression, root, apply set-up),
  * "prof.<class>.ms|launches|flops|bytes" (HIP-event time, launch count and

@@ -356,13 +356,14 @@ template <class T> struct Engine : EngineBase {
   T* kept_S_ = nullptr;
   T* kept_St_ = nullptr;
   struct RootDev {
-    W* R = nullptr;      // (P A_root)^{-1}
+    W* R = nullptr;      // (P A_root)^{-1}, or its block LDU form (root_wb_ > 0)
     int* rowperm = nullptr;
     int64_t* gidx = nullptr;
     int32_t* src = nullptr;
     int n = 0;
   };
   std::vector<RootDev> rt;
+  int root_wb_ = 0;  // block width of the roots' LDU form; 0: explicit inverses
 
   // diagnostics
   std::vector<int> rank_v, attempts_v, l_v, l_init_v;
@@ -392,6 +393,16 @@ template <class T> struct Engine : EngineBase {
   };
   std::vector<ApplyWave> aw;
   GemvLaunch<W> root_gemv;
+  // root solve in the block LDU form: c = P r gathered into d_t; forward, per block
+  // J, c[>J] += M[>J, J] c_J; z_K = M_KK c_K into d_r; backward, per block K from
+  // the last, x_K -= M[K, >K] x[>K] in d_r; x copied to d_t
+  struct RootApply {
+    PermSeg* gather = nullptr;
+    PermSeg* copy = nullptr;
+    int nseg = 0, maxn = 0;
+    std::vector<GemvLaunch<W>> fwd, bwd;
+    GemvLaunch<W> diag;
+  } ra;
   int max_nr = 0;
   // tiles of 64 rows; an entry's columns are split so that a launch has about
   // 1024 work items (at least 128 columns per item), which keeps HBM busy even
@@ -731,9 +742,15 @@ template <class T> struct Engine : EngineBase {
   // more than kGjBlockMin rows take the pivot columns in blocks of wo: each block
   // is eliminated by the panel sweep on a copy of its columns, then applied to
   // the other columns with one product of depth wo. block > 0 forces that width.
+  // ldu (square boxes): the block LDU form instead of the inverse. Each block step
+  // updates only the rows and columns from the block on, so the box ends up with
+  // (P A)_JJ^{-1} in the diagonal blocks, -(P A)_{>J,J} (P A)_JJ^{-1} below them and
+  // (P A)_JJ^{-1} (P A)_{J,>J} right of them (the Schur complement of each step
+  // carried to the next): a third of the inverse's flops, applied by block sweeps.
+  // Returns the block width (0: unblocked, always the inverse).
   template <class X>
-  void gauss_jordan(std::vector<GjDesc<X>>& ds, Arena& ar, int block = 0) {
-    if (ds.empty()) return;
+  int gauss_jordan(std::vector<GjDesc<X>>& ds, Arena& ar, int block = 0, bool ldu = false) {
+    if (ds.empty()) return 0;
     constexpr bool wide = !std::is_same<X, T>::value;
     int nmax = 0, wmax = 0;
     for (auto& g : ds) {
@@ -766,7 +783,7 @@ template <class T> struct Engine : EngineBase {
     GjDesc<X>* dd = up(ds, ar);
     if (!wo) {
       gj_sweep<X>(ds, dd, c, ar);
-      return;
+      return 0;
     }
     const int nn = (int)ds.size(), nblk = cdiv(nmax, wo);
     // inner descriptors of every block (the boxes that still have pivot columns
@@ -787,7 +804,11 @@ template <class T> struct Engine : EngineBase {
         h.rbuf = ar.get<X>((size_t)nb * wb);
         h.rowperm = g.rp_in;
         inner.push_back(h);
-        gd.push_back({g.pb, g.rbuf, g.M, g.rows, g.W, wb, g.rows, wb, g.rows, J, J + wb});
+        if (ldu)  // rows and columns from J on; the block's own columns are written with beta 0
+          gd.push_back({g.pb + J, g.rbuf + (size_t)J * wb, g.M + J + (size_t)J * g.rows, g.rows - J, g.W - J, wb,
+                        g.rows, wb, g.rows, 0, wb});
+        else
+          gd.push_back({g.pb, g.rbuf, g.M, g.rows, g.W, wb, g.rows, wb, g.rows, J, J + wb});
       }
       ioff[b + 1] = (int)inner.size();
       outer.push_back(prep_gemm<X>(gd, ar));
@@ -815,11 +836,12 @@ template <class T> struct Engine : EngineBase {
       id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, bby);
       gj_block_moves_kernel<X><<<nn, 256, 0, st>>>(dd, J);
       check_launch("gj_block_moves");
-      gj_block_rows_kernel<X><<<dim3(cdiv(wmax, GJ_BLOCK_TILE), nn), 256, 0, st>>>(dd, J, wo);
+      gj_block_rows_kernel<X><<<dim3(cdiv(wmax, GJ_BLOCK_TILE), nn), 256, 0, st>>>(dd, J, wo, ldu ? 1 : 0);
       prof.stop(id);
       check_launch("gj_block_rows");
       run_gemm<X>(outer[b], p1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
     }
+    return wo;
   }
 
   // ---------------------------------------------------------------- input check
@@ -1164,7 +1186,7 @@ template <class T> struct Engine : EngineBase {
         g.flag = d_sing + nn + p;
         gj.push_back(g);
       }
-      gauss_jordan<W>(gj, tmp);
+      root_wb_ = gauss_jordan<W>(gj, tmp, 0, true);
       // singular pivots
       std::vector<int> sing(nn + nprob + 1);
       HIP_CHECK(hipMemcpyAsync(sing.data(), d_sing, sizeof(int) * sing.size(), hipMemcpyDeviceToHost, st));
@@ -1685,12 +1707,56 @@ template <class T> struct Engine : EngineBase {
       a.fwd2 = prep_gemv(f2, 1);
       a.bwd = prep_gemv(b1, 1);
     }
-    std::vector<GemvDesc<W>> rd;
+    root_gemv = GemvLaunch<W>{};
+    ra = RootApply{};
+    if (!root_wb_) {
+      std::vector<GemvDesc<W>> rd;
+      for (size_t p = 0; p < P.roots.size(); ++p) {
+        const int64_t ip = P.probs[p].dof_off + P.roots[p].ipos;
+        rd.push_back({rt[p].R, rt[p].n, rt[p].n, ip, nullptr, ip, nullptr, rt[p].rowperm, 0});
+      }
+      root_gemv = prep_gemv(rd, 0);
+      return;
+    }
+    // block LDU form (blocks of root_wb_ columns; every block of every root in
+    // one launch per block index)
+    const int wb = root_wb_;
+    std::vector<PermSeg> pg, pc;
+    int nblk = 0;
     for (size_t p = 0; p < P.roots.size(); ++p) {
       const int64_t ip = P.probs[p].dof_off + P.roots[p].ipos;
-      rd.push_back({rt[p].R, rt[p].n, rt[p].n, ip, nullptr, ip, nullptr, rt[p].rowperm});
+      const int n = rt[p].n;
+      if (n == 0) continue;
+      pg.push_back({ip, ip, rt[p].rowperm, n});
+      pc.push_back({ip, ip, nullptr, n});
+      ra.maxn = std::max(ra.maxn, n);
+      nblk = std::max(nblk, cdiv(n, wb));
     }
-    root_gemv = prep_gemv(rd, 0);
+    if (pg.empty()) return;
+    ra.nseg = (int)pg.size();
+    ra.gather = up(pg, persist);
+    ra.copy = up(pc, persist);
+    std::vector<GemvDesc<W>> dg;
+    for (int b = 0; b < nblk; ++b) {
+      std::vector<GemvDesc<W>> f, u;
+      for (size_t p = 0; p < P.roots.size(); ++p) {
+        const int64_t ip = P.probs[p].dof_off + P.roots[p].ipos;
+        const int n = rt[p].n, J = b * wb;
+        if (J >= n) continue;
+        const int w = std::min(wb, n - J);
+        W* M = rt[p].R;
+        dg.push_back({M + J + (size_t)J * n, w, w, ip + J, nullptr, ip + J, nullptr, nullptr, n});
+        if (J + w < n) {
+          f.push_back({M + (J + w) + (size_t)J * n, n - J - w, w, ip + J, nullptr, ip + J + w, nullptr, nullptr, n});
+          u.push_back({M + J + (size_t)(J + w) * n, w, n - J - w, ip + J + w, nullptr, ip + J, nullptr, nullptr, n});
+        }
+      }
+      if (!f.empty()) {
+        ra.fwd.push_back(prep_gemv(f, 2));
+        ra.bwd.push_back(prep_gemv(u, 1));
+      }
+    }
+    ra.diag = prep_gemv(dg, 0);
   }
 
   void ensure_work(int nrhs) {
@@ -1719,7 +1785,18 @@ template <class T> struct Engine : EngineBase {
       gemv<T>(aw[h].fwd1, d_r, d_t, nrhs, s);
       gemv<T>(aw[h].fwd2, d_t, d_r, nrhs, s);
     }
-    gemv<W>(root_gemv, d_r, d_t, nrhs, s);
+    if (!root_wb_) {
+      gemv<W>(root_gemv, d_r, d_t, nrhs, s);
+    } else if (ra.nseg) {
+      const dim3 pgrid(grid1((int64_t)ra.maxn * nrhs, 256), ra.nseg);
+      perm_gather_kernel<W><<<pgrid, 256, 0, s>>>(d_r, d_t, (int64_t)ntot, nrhs, ra.gather);
+      check_launch("root gather");
+      for (auto& L : ra.fwd) gemv<W>(L, d_t, d_t, nrhs, s);
+      gemv<W>(ra.diag, d_t, d_r, nrhs, s);
+      for (size_t i = ra.bwd.size(); i-- > 0;) gemv<W>(ra.bwd[i], d_r, d_r, nrhs, s);
+      perm_gather_kernel<W><<<pgrid, 256, 0, s>>>(d_r, d_t, (int64_t)ntot, nrhs, ra.copy);
+      check_launch("root copy");
+    }
     for (size_t h = aw.size(); h-- > 0;) gemv<T>(aw[h].bwd, d_t, d_t, nrhs, s);
   }
   // captured sweeps, one executable graph per right-hand-side count; captured on a
@@ -2052,6 +2129,7 @@ template <class T> struct Engine : EngineBase {
       for (int g = 0; g < nn; ++g) out.push_back((double)f(g));
     };
     if (key == "kept_n") out = {(double)kept_n_};
+    else if (key == "root_block") out = {(double)root_wb_};
     else if (key == "kept_S" || key == "kept_St") {
       const size_t ne = (size_t)kept_n_ * kept_n_;
       std::vector<T> h(ne);
@@ -2100,13 +2178,23 @@ template <class T> struct Engine : EngineBase {
       else out = {lu, trsm, gemm_, root, alg_sample, alg_cpqr};
     } else if (key == "flops_gj") {
       // the work the explicit Gauss-Jordan form executes: n_i^2 (n_i + n_b) for the
-      // interior inverse and X, n_b^2 n_i for the Schur product, n^3 for the root
+      // interior inverse and X, n_b^2 n_i for the Schur product; for the root n^3
+      // (inverse) or the sum over blocks J of (n - J)^2 w (block LDU form)
       double f = 0;
       for (auto& n : P.nodes) {
         double ni = (double)n.idof.size(), nbd = (double)n.bdof.size();
         f += Flop<T>::mac * (ni * ni * (ni + nbd) + nbd * nbd * ni);
       }
-      for (auto& r : rt) f += Flop<W>::mac * (double)r.n * r.n * r.n;
+      for (auto& r : rt) {
+        if (!root_wb_) {
+          f += Flop<W>::mac * (double)r.n * r.n * r.n;
+          continue;
+        }
+        for (int J = 0; J < r.n; J += root_wb_) {
+          const double m = r.n - J;
+          f += Flop<W>::mac * m * m * std::min(root_wb_, r.n - J);
+        }
+      }
       out = {f};
     } else if (key == "bytes_apply") out = {apply_bytes()};
     else if (key == "bytes_spmv") {

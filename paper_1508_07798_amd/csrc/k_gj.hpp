@@ -1039,9 +1039,11 @@ __global__ __launch_bounds__(256) void gj_block_moves_kernel(const GjDesc<T>* __
 // The block's moves on the columns outside [J, J + wb) (all moved entries of the
 // tile loaded, then stored), then the pivot rows J .. J + wb - 1 of those columns
 // copied to rbuf (wb x W) and zeroed in M; rbuf's block columns get the identity.
-// Grid (GJ_BLOCK_TILE-column tiles, box).
+// ldu: the block LDU form, whose columns left of the block keep their pivot rows
+// (only the moves apply there). Grid (GJ_BLOCK_TILE-column tiles, box).
 template <class T>
-__global__ __launch_bounds__(256) void gj_block_rows_kernel(const GjDesc<T>* __restrict__ descs, int J, int wo) {
+__global__ __launch_bounds__(256) void gj_block_rows_kernel(const GjDesc<T>* __restrict__ descs, int J, int wo,
+                                                            int ldu) {
   using R = typename traits<T>::real;
   const GjDesc<T> g = descs[blockIdx.y];
   if (J >= g.n) return;
@@ -1081,6 +1083,7 @@ __global__ __launch_bounds__(256) void gj_block_rows_kernel(const GjDesc<T>* __r
   __syncthreads();
   for (int idx = tid; idx < wb * cw; idx += 256) {
     const int i = idx % wb, col = c0 + idx / wb;
+    if (ldu && col < J) continue;
     T* mp = g.M + (J + i) + (size_t)col * g.rows;
     if (col >= J && col < J + wb) {
       g.rbuf[i + (size_t)col * wb] = col - J == i ? traits<T>::one() : traits<T>::zero();

@@ -10,13 +10,14 @@ namespace hss {
 // Batched GEMV y(out) = or -= Mat * x(in) on multi-vectors (nrhs columns, ld).
 // Rows / columns are either contiguous from an offset or listed by index.
 template <class T> struct GemvDesc {
-  const T* mat;          // rows x cols, column-major, ld = rows
+  const T* mat;          // rows x cols, column-major, ld = ldm (rows when ldm is 0)
   int rows, cols;
   int64_t in_off;        // contiguous input offset, or -1 to use in_idx
   const int64_t* in_idx;
   int64_t out_off;       // contiguous output offset, or -1 to use out_idx
   const int64_t* out_idx;
   const int* in_perm;    // if set: input c is in_off + in_perm[c] (a permuted contiguous segment)
+  int ldm;               // leading dimension of mat (0: rows)
 };
 
 // Work item of a GEMV launch: rows [r0, r0 + 64) and columns [c0, c1) of entry
@@ -34,8 +35,9 @@ template <> __device__ __forceinline__ void atomic_add_v<cd>(cd* p, cd v) {
 }
 
 // sub = 0: y = M x (outputs of split entries must be zero beforehand); sub = 1:
-// y -= M x. One workgroup per tile: 512 threads = 64 rows x 8 column groups,
-// matrix loads four at a time, x staged through LDS in chunks of 256 columns.
+// y -= M x; sub = 2: y += M x. One workgroup per tile: 512 threads = 64 rows x 8
+// column groups, matrix loads four at a time, x staged through LDS in chunks of
+// 256 columns.
 constexpr int GEMV_THREADS = 512;
 template <class T, class V, int NR>
 __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* __restrict__ ds,
@@ -67,12 +69,13 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* _
       }
       __syncthreads();
       if (row < d.rows) {
-        const T* mp = d.mat + row + (size_t)c0 * d.rows;
+        const size_t ldm = d.ldm > 0 ? (size_t)d.ldm : (size_t)d.rows;
+        const T* mp = d.mat + row + (size_t)c0 * ldm;
         int c = part;
         for (; c + 3 * NP < cw; c += 4 * NP) {
           T m4[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) m4[u] = mp[(size_t)(c + u * NP) * d.rows];
+          for (int u = 0; u < 4; ++u) m4[u] = mp[(size_t)(c + u * NP) * ldm];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const V mv = to_wide(m4[u]);
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* _
           }
         }
         for (; c < cw; c += NP) {
-          const V mv = to_wide(mp[(size_t)c * d.rows]);
+          const V mv = to_wide(mp[(size_t)c * ldm]);
 #pragma unroll
           for (int k = 0; k < NR; ++k)
             if (k < nr) acc[k] = acc[k] + sc_mul(mv, xs[k][c]);
@@ -98,11 +101,30 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* _
         V s = red[k][0][rl];
         for (int q = 1; q < NP; ++q) s = s + red[k][q][rl];
         V* yp = y + dst + (rb + k) * ld;
-        if (tl.split) atomic_add_v(yp, sub ? -s : s);
-        else *yp = sub ? (*yp - s) : s;
+        if (tl.split) atomic_add_v(yp, sub == 1 ? -s : s);
+        else *yp = sub == 1 ? (*yp - s) : sub == 2 ? (*yp + s) : s;
       }
     }
     __syncthreads();
+  }
+}
+
+// y[out_off + i] = x[in_off + perm[i]] (x[in_off + i] when perm is null), i < n, for
+// every segment and right-hand side; grid (chunks, segments)
+struct PermSeg {
+  int64_t in_off, out_off;
+  const int* perm;
+  int n;
+};
+template <class V>
+__global__ void perm_gather_kernel(const V* __restrict__ x, V* __restrict__ y, int64_t ld, int nrhs,
+                                   const PermSeg* __restrict__ segs) {
+  const PermSeg sg = segs[blockIdx.y];
+  const int64_t tot = (int64_t)sg.n * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int i = (int)(e % sg.n);
+    const int64_t k = e / sg.n;
+    y[sg.out_off + i + k * ld] = x[sg.in_off + (sg.perm ? sg.perm[i] : i) + k * ld];
   }
 }
 

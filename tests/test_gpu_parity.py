@@ -62,6 +62,10 @@ def test_exact_factorization(pde, p, prec):
     cond = np.linalg.cond(D)
     eps = 1e-16 if prec == "fp64" else 6e-8
     assert np.linalg.norm(x - xr) <= 50 * eps * cond * np.linalg.norm(xr)
+    # p = 1: a 96-row root kept as an explicit inverse; p = 2: a 216-row root in
+    # the block LDU form (several blocks: 128 columns, or the tuning table's width)
+    rb = h.query("root_block")[0]
+    assert rb == 0 if p == 1 else 0 < rb < 216
     if prec == "fp64":
         _, info = h.gmres(_t(b), tol=1e-10)
         assert info[0]["iters"] == 1 and info[0]["true_relres"] <= 1e-10
