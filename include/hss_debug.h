@@ -33,8 +33,10 @@ hss_status_t hss_debug_gemm(int32_t scalar, int32_t nbatch, const void* const* A
  * the blocked Gauss-Jordan elimination with partial pivoting that the
  * factorization uses for every A^_ii. block = 0 keeps the factorization's own
  * choice of second-level blocking; block in [1, 256] forces blocks of that many
- * pivot columns (HSS_EINVAL outside [0, 256]). *singular receives 1 if a pivot
- * was 0. */
+ * pivot columns (HSS_EINVAL outside [0, 256]). Complex64 batches whose largest
+ * box has more than 2048 rows run their panels in complex128 on a widened copy of
+ * each block (the block products stay complex64), as the factorization does.
+ * *singular receives 1 if a pivot was 0. */
 hss_status_t hss_debug_gj(int32_t scalar, int32_t nbatch, void* const* Mat, const int32_t* n,
                           const int32_t* m, int32_t block, int32_t* singular, void* hip_stream);
 

@@ -322,6 +322,9 @@ template <class T> struct Engine : EngineBase {
   // run about 15% faster than depth 128 (complex128, measured), and the extra work
   // on the block copy is a few percent at these sizes
   static constexpr int kGjBlockWideAbove = 2048;
+  // complex64 boxes above kGjWidenAbove rows: complex128 panels on the block copy
+  // (else the whole box is eliminated in complex128)
+  static constexpr bool kGjMixedPanels = true;
   static constexpr int kGjBlockWide = 256;
   // complex64 boxes above this many interior rows are eliminated in complex128
   static constexpr int kGjWidenAbove = 2048;
@@ -747,11 +750,15 @@ template <class T> struct Engine : EngineBase {
   // (P A)_JJ^{-1} in the diagonal blocks, -(P A)_{>J,J} (P A)_JJ^{-1} below them and
   // (P A)_JJ^{-1} (P A)_{J,>J} right of them (the Schur complement of each step
   // carried to the next): a third of the inverse's flops, applied by block sweeps.
+  // PX != X (blocked form only): the block copy is held in PX and its panel sweep
+  // runs in PX; the result is rounded back to X for the block's product, which
+  // runs in X like the rest of the box.
   // Returns the block width (0: unblocked, always the inverse).
-  template <class X>
+  template <class X, class PX = X>
   int gauss_jordan(std::vector<GjDesc<X>>& ds, Arena& ar, int block = 0, bool ldu = false) {
     if (ds.empty()) return 0;
     constexpr bool wide = !std::is_same<X, T>::value;
+    constexpr bool mixed = !std::is_same<X, PX>::value;
     int nmax = 0, wmax = 0;
     for (auto& g : ds) {
       g.rows = g.n;
@@ -759,18 +766,18 @@ template <class T> struct Engine : EngineBase {
       nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W);
     }
     const int sX = (int)sizeof(X);
-    GjCfg c = gj_config<X>(nmax);
+    GjCfg c = gj_config<PX>(nmax);
     const int nb = c.nb;
     if (c.tourn) c.cand = ar.get<int>(ds.size() * (size_t)c.nch * nb);
     int wo = block > 0 ? std::min(block, GJ_BLOCK_MAX)
                        : c.block >= 0 ? std::min(c.block, GJ_BLOCK_MAX)
                        : (nmax > kGjBlockWideAbove ? kGjBlockWide : nmax > kGjBlockMin ? kGjBlock : 0);
     if (wo >= nmax) wo = 0;
-    // scratch per box
-    for (auto& g : ds) {
-      g.pinv = ar.get<X>((size_t)nb * nb);
-      g.csave = ar.get<X>((size_t)g.rows * nb);
-      g.gpanel = c.lds ? nullptr : ar.get<X>((size_t)g.rows * nb);
+    if (mixed && !wo) throw Error(HSS_EDEVICE, "panels in another precision need the blocked form");
+    // scratch per box (for mixed panels, the panel sweep's own set in PX)
+    std::vector<GjDesc<PX>> px(ds.size());
+    for (size_t i = 0; i < ds.size(); ++i) {
+      GjDesc<X>& g = ds[i];
       g.mv = ar.get<int>(1 + 4 * (size_t)std::max(nb, wo));
       if (wo) {
         g.rbuf = ar.get<X>((size_t)wo * g.W);
@@ -779,29 +786,55 @@ template <class T> struct Engine : EngineBase {
       } else {
         g.rbuf = ar.get<X>((size_t)nb * g.W);
       }
+      if constexpr (mixed) {
+        GjDesc<PX>& h = px[i];
+        h.M = ar.get<PX>((size_t)g.rows * wo);
+        h.pinv = ar.get<PX>((size_t)nb * nb);
+        h.csave = ar.get<PX>((size_t)g.rows * nb);
+        h.gpanel = c.lds ? nullptr : ar.get<PX>((size_t)g.rows * nb);
+      } else {
+        g.pinv = ar.get<X>((size_t)nb * nb);
+        g.csave = ar.get<X>((size_t)g.rows * nb);
+        g.gpanel = c.lds ? nullptr : ar.get<X>((size_t)g.rows * nb);
+      }
     }
     GjDesc<X>* dd = up(ds, ar);
     if (!wo) {
-      gj_sweep<X>(ds, dd, c, ar);
+      if constexpr (!mixed) gj_sweep<X>(ds, dd, c, ar);
       return 0;
     }
     const int nn = (int)ds.size(), nblk = cdiv(nmax, wo);
     // inner descriptors of every block (the boxes that still have pivot columns
     // there): the block copy, pivots from row J on, its own row permutation
-    std::vector<GjDesc<X>> inner;
+    std::vector<GjDesc<PX>> inner;
     std::vector<int> ioff(nblk + 1, 0);
     std::vector<GemmLaunch> outer;
+    // mixed panels: the block's columns widened into the PX copy, and the copy
+    // rounded back into pb after its sweep
+    std::vector<CvtSeg<PX, X>> wsegs;
+    std::vector<CvtSeg<X, PX>> nsegs;
     for (int b = 0; b < nblk; ++b) {
       const int J = b * wo;
       std::vector<GemmDesc> gd;
-      for (auto& g : ds) {
+      for (size_t i = 0; i < ds.size(); ++i) {
+        const GjDesc<X>& g = ds[i];
         if (J >= g.n) continue;
         const int wb = std::min(wo, g.n - J);
-        GjDesc<X> h = g;
-        h.M = g.pb;
+        GjDesc<PX> h{};
+        if constexpr (mixed) {
+          h = px[i];
+          h.flag = g.flag;
+          h.mv = g.mv;
+          wsegs.push_back({h.M, g.M + (size_t)J * g.rows, (int64_t)g.rows * wb});
+          nsegs.push_back({g.pb, h.M, (int64_t)g.rows * wb});
+        } else {
+          h = g;
+          h.M = g.pb;
+        }
+        h.rows = g.rows;
         h.n = h.W = wb;
         h.poff = J;
-        h.rbuf = ar.get<X>((size_t)nb * wb);
+        h.rbuf = ar.get<PX>((size_t)nb * wb);
         h.rowperm = g.rp_in;
         inner.push_back(h);
         if (ldu)  // rows and columns from J on; the block's own columns are written with beta 0
@@ -813,7 +846,9 @@ template <class T> struct Engine : EngineBase {
       ioff[b + 1] = (int)inner.size();
       outer.push_back(prep_gemm<X>(gd, ar));
     }
-    GjDesc<X>* di = up(inner, ar);
+    GjDesc<PX>* di = up(inner, ar);
+    CvtSeg<PX, X>* dws = mixed ? up(wsegs, ar) : nullptr;
+    CvtSeg<X, PX>* dns = mixed ? up(nsegs, ar) : nullptr;
     const X p1 = traits<X>::one();
     for (int b = 0; b < nblk; ++b) {
       const int J = b * wo;
@@ -824,15 +859,26 @@ template <class T> struct Engine : EngineBase {
         for (auto& g : ds) {
           if (J >= g.n) continue;
           const double wb = std::min(wo, g.n - J);
-          cby += 2.0 * g.rows * wb * sX;
+          cby += mixed ? g.rows * wb * (sX + sizeof(PX)) : 2.0 * g.rows * wb * sX;
           bby += 3.0 * wb * g.W * sX;
         }
+      const int nbox = ioff[b + 1] - ioff[b];
+      const unsigned cgrid = std::min(cdiv(nmax * wo, 256), 256);
       int id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, cby);
-      gj_block_copy_kernel<X><<<dim3(std::min(cdiv(nmax * wo, 256), 256), nn), 256, 0, st>>>(dd, J, wo);
+      if constexpr (mixed)
+        convert_segs_kernel<PX, X><<<dim3(cgrid, nbox), 256, 0, st>>>(dws + ioff[b]);
+      else
+        gj_block_copy_kernel<X><<<dim3(cgrid, nn), 256, 0, st>>>(dd, J, wo);
       prof.stop(id);
       check_launch("gj_block_copy");
-      const std::vector<GjDesc<X>> blk(inner.begin() + ioff[b], inner.begin() + ioff[b + 1]);
-      gj_sweep<X>(blk, di + ioff[b], c, ar);
+      const std::vector<GjDesc<PX>> blk(inner.begin() + ioff[b], inner.begin() + ioff[b + 1]);
+      gj_sweep<PX>(blk, di + ioff[b], c, ar);
+      if constexpr (mixed) {
+        id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, cby);
+        convert_segs_kernel<X, PX><<<dim3(cgrid, nbox), 256, 0, st>>>(dns + ioff[b]);
+        prof.stop(id);
+        check_launch("gj_block_narrow");
+      }
       id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, bby);
       gj_block_moves_kernel<X><<<nn, 256, 0, st>>>(dd, J);
       check_launch("gj_block_moves");
@@ -922,10 +968,12 @@ template <class T> struct Engine : EngineBase {
       check_launch("gather");
     }
     // 2. Gauss-Jordan on [A_ii | A_ib]. Complex64 boxes with more than
-    //    kGjWidenAbove interior rows are eliminated in complex128: the block is
-    //    widened, eliminated and narrowed back into the factor storage.
+    //    kGjWidenAbove interior rows take their panels in complex128 (on the
+    //    widened block copy; the block products stay complex64), or with
+    //    kGjMixedPanels off are widened whole, eliminated in complex128 and
+    //    narrowed back into the factor storage.
     {
-      std::vector<GjDesc<X>> gj;
+      std::vector<GjDesc<X>> gj, big;
       std::vector<GjDesc<W>> wide;
       std::vector<std::pair<X*, int64_t>> narrow;  // factor block, element count
       for (size_t i = 0; i < nw; ++i) {
@@ -938,6 +986,10 @@ template <class T> struct Engine : EngineBase {
         g.rowperm = nd[wv[i]].rowperm;
         g.flag = d_sing_ + wv[i];
         if constexpr (std::is_same<X, cf>::value) {
+          if (g.n > kGjWidenAbove && kGjMixedPanels) {
+            big.push_back(g);
+            continue;
+          }
           if (g.n > kGjWidenAbove) {
             const int64_t ne = (int64_t)g.n * g.W;
             GjDesc<W> gw{};
@@ -956,6 +1008,7 @@ template <class T> struct Engine : EngineBase {
       lap(2);
       gauss_jordan<X>(gj, tmp);
       if constexpr (std::is_same<X, cf>::value) {
+        gauss_jordan<cf, cd>(big, tmp);
         if (!wide.empty()) {
           const double cby = [&] {
             double b = 0;
@@ -2328,7 +2381,14 @@ void debug_gj_t(int nb, void* const* Mat, const int32_t* n, const int32_t* m, in
     g.flag = flags + b;
     ds.push_back(g);
   }
-  eng.template gauss_jordan<X>(ds, ar, block);
+  int nmax = 0;
+  for (auto& g : ds) nmax = std::max(nmax, g.n);
+  if constexpr (std::is_same<X, cf>::value) {
+    if (nmax > Engine<X>::kGjWidenAbove) eng.template gauss_jordan<cf, cd>(ds, ar, block);
+    else eng.template gauss_jordan<X>(ds, ar, block);
+  } else {
+    eng.template gauss_jordan<X>(ds, ar, block);
+  }
   // explicit inverse: undo the pivoted column order through a copy
   if (!ds.empty()) {
     std::vector<X*> outs;

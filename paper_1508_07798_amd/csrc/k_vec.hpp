@@ -176,6 +176,19 @@ __global__ __launch_bounds__(256) void convert_kernel(const S* __restrict__ src,
     dst[e] = traits<D>::mk(traits<S>::re(src[e]), traits<S>::im(src[e]));
 }
 
+// dst = src converted for every segment (n elements each); grid (chunks, segments)
+template <class D, class S> struct CvtSeg {
+  D* dst;
+  const S* src;
+  int64_t n;
+};
+template <class D, class S>
+__global__ __launch_bounds__(256) void convert_segs_kernel(const CvtSeg<D, S>* __restrict__ segs) {
+  const CvtSeg<D, S> sg = segs[blockIdx.y];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < sg.n; e += (int64_t)gridDim.x * 256)
+    sg.dst[e] = traits<D>::mk(traits<S>::re(sg.src[e]), traits<S>::im(sg.src[e]));
+}
+
 // y = A x (mode 0) or y = b - A x (mode 1) for the element-block operator.
 // dof_elem[d]: global element of global dof d; elem_dof[e]: first global dof of e.
 template <class V>

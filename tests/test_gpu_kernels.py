@@ -170,20 +170,22 @@ def test_every_tunable_panel_shape_inverts(name, rows):
             hss.tuning_load(default)
 
 
-TALL_COMPLEX64_SKIP = ("complex64 Gauss-Jordan above 2048 rows (register panel at 3,150 rows) faulted the GPU "
-                       "and its cause is not found; that path is switched off (HSS_EUNSUPPORTED)")
+TALL_COMPLEX64_SKIP = ("complex64 Gauss-Jordan above 2048 rows on the register panel kernel (3,150 rows) faulted "
+                       "the GPU and its cause is not found; that kernel stays off (such boxes take complex128 "
+                       "panels), and this case stays off the GPU")
 
 
 @pytest.mark.parametrize("name,n,m", [
     pytest.param("complex64", 3150, 40, marks=pytest.mark.skip(reason=TALL_COMPLEX64_SKIP)),
     pytest.param("complex64", 6350, 16, marks=pytest.mark.skip(reason=TALL_COMPLEX64_SKIP)),
-    ("complex128", 4200, 8)])
+    ("complex64", 2100, 24), ("complex64", 4500, 16), ("complex128", 4200, 8)])
 def test_gauss_jordan_tall_boxes_residual(name, n, m):
-    """Boxes of the p = 4 Helmholtz configuration's top levels (3,150 and 6,350
-    interior rows in complex64; a complex128 block) beyond the register-resident
-    panels: checked on the host, in complex128, by the residual of the inverse on
-    random probe vectors, ||A (Ainv V) - V||, and by ||A X - B||, which bound the
-    error at any size (no dense reference inverse is formed)."""
+    """Boxes beyond the register-resident panels (complex64 above 2,048 rows, whose
+    panels run in complex128 on the widened block copy while the block products stay
+    complex64; a complex128 block on tournament panels): checked on the host, in
+    complex128, by the residual of the inverse on random probe vectors,
+    ||A (Ainv V) - V||, and by ||A X - B||, which bound the error at any size (no
+    dense reference inverse is formed)."""
     npdt, tdt, tol = DT[name]
     print(f"gj tall {name} n={n} m={m}", flush=True)
     rng = np.random.default_rng(13)
@@ -202,15 +204,6 @@ def test_gauss_jordan_tall_boxes_residual(name, n, m):
     eps = 6e-8 if npdt == np.complex64 else 1.1e-16
     assert r1 <= 20 * eps * np.sqrt(n), r1
     assert r2 <= 20 * eps * np.sqrt(n), r2
-
-
-def test_gauss_jordan_tall_complex64_is_refused():
-    """The switched-off path raises before any panel kernel runs."""
-    n = 2100
-    M = torch.zeros((n + 1, n), dtype=torch.complex64, device="cuda")
-    with pytest.raises(hss.HssError) as e:
-        hss.debug_gj([M], [n], [1])
-    assert e.value.status == hss.HSS_EUNSUPPORTED
 
 
 def test_gauss_jordan_needs_pivoting_and_flags_singular():
