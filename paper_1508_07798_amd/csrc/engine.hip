@@ -325,6 +325,8 @@ template <class T> struct Engine : EngineBase {
   // complex64 boxes above kGjWidenAbove rows: complex128 panels on the block copy
   // (else the whole box is eliminated in complex128)
   static constexpr bool kGjMixedPanels = true;
+  // blocked Gauss-Jordan: the next block's panel sweep overlaps the block product
+  static constexpr bool kGjLookahead = true;
   static constexpr int kGjBlockWide = 256;
   // complex64 boxes above this many interior rows are eliminated in complex128
   static constexpr int kGjWidenAbove = 2048;
@@ -480,6 +482,7 @@ template <class T> struct Engine : EngineBase {
   ~Engine() override {
     flushq.clear();
     (void)hipStreamSynchronize(st);
+    release_side();
     release_graphs();
     work.release();
     scratch.release();
@@ -690,38 +693,44 @@ template <class T> struct Engine : EngineBase {
   }
 
   // The panel sweep over the pivot columns of a batch of descriptors (uploaded
-  // as dd): panel LU, row movement and scaled pivot rows, trailing GEMM.
-  template <class X>
-  void gj_sweep(const std::vector<GjDesc<X>>& ds, const GjDesc<X>* dd, const GjCfg& c, Arena& ar) {
-    const int nn = (int)ds.size(), nb = c.nb, sX = (int)sizeof(X);
-    constexpr bool wide = !std::is_same<X, T>::value;
-    int nmax = 0, wmax = 0, rmax = 0;
-    for (auto& g : ds) nmax = std::max(nmax, g.n), wmax = std::max(wmax, g.W), rmax = std::max(rmax, g.rows);
-    // every panel's trailing-update descriptors, uploaded together
+  // as dd): panel LU, row movement and scaled pivot rows, trailing GEMM. The
+  // plan holds every panel step's trailing-update lists (uploaded when built)
+  // and the algorithmic work of its panel and row kernels.
+  struct SweepPlan {
     std::vector<GemmLaunch> upd;
-    for (int j0 = 0; j0 < nmax; j0 += nb) {
+    std::vector<double> pfl, rby;
+    int nn = 0, nmax = 0, wmax = 0, rmax = 0;
+  };
+  template <class X> SweepPlan prep_sweep(const std::vector<GjDesc<X>>& ds, int nb, Arena& ar) {
+    SweepPlan sp;
+    const int sX = (int)sizeof(X);
+    sp.nn = (int)ds.size();
+    for (auto& g : ds)
+      sp.nmax = std::max(sp.nmax, g.n), sp.wmax = std::max(sp.wmax, g.W), sp.rmax = std::max(sp.rmax, g.rows);
+    for (int j0 = 0; j0 < sp.nmax; j0 += nb) {
       std::vector<GemmDesc> gd;
+      double pfl = 0, rby = 0;
       for (auto& g : ds) {
         if (j0 >= g.n) continue;
-        int w = std::min(nb, g.n - j0);
+        const int w = std::min(nb, g.n - j0);
         gd.push_back({g.csave, g.rbuf, g.M, g.rows, g.W, w, g.rows, w, g.rows, j0, j0 + w});
+        const double R = g.rows - g.poff - j0;
+        for (int cc = 0; cc < w; ++cc) pfl += Flop<X>::mac * (R - cc - 1) * (w - cc - 1);
+        rby += (2.0 * g.rows * w + 3.0 * w * g.W) * sX;
       }
-      upd.push_back(prep_gemm<X>(gd, ar));
+      sp.upd.push_back(prep_gemm<X>(gd, ar));
+      sp.pfl.push_back(pfl);
+      sp.rby.push_back(rby);
     }
+    return sp;
+  }
+  template <class X> void run_sweep(const SweepPlan& sp, const GjDesc<X>* dd, const GjCfg& c) {
+    const int nn = sp.nn, nb = c.nb;
+    constexpr bool wide = !std::is_same<X, T>::value;
     const X m1 = traits<X>::mk(-1.0, 0.0), p1 = traits<X>::one();
-    for (int j0 = 0, pi = 0; j0 < nmax; j0 += nb, ++pi) {
+    for (int j0 = 0, pi = 0; j0 < sp.nmax; j0 += nb, ++pi) {
       fl();
-      // algorithmic work of this panel step: LU flops of the panels, bytes of gj_rows
-      double pfl = 0, rby = 0;
-      if (prof.on) {
-        for (auto& g : ds) {
-          if (j0 >= g.n) continue;
-          const double w = std::min(nb, g.n - j0), R = g.rows - g.poff - j0;
-          for (int cc = 0; cc < (int)w; ++cc) pfl += Flop<X>::mac * (R - cc - 1) * (w - cc - 1);
-          rby += (2.0 * g.rows * w + 3.0 * w * g.W) * sX;
-        }
-      }
-      int id = prof.start(wide ? C_GJ_PANEL_W : C_GJ_PANEL, pfl, 0);
+      int id = prof.start(wide ? C_GJ_PANEL_W : C_GJ_PANEL, sp.pfl[pi], 0);
       if (c.rot) launch_panel_rot<X>(dd, nn, j0, nb, c.ps, st);
       else if (c.tourn) {
         if constexpr (!std::is_same<X, cf>::value) launch_panel_tourn<X>(dd, nn, j0, nb, c.nch, c.cand, st);
@@ -732,13 +741,39 @@ template <class T> struct Engine : EngineBase {
       else gj_panel_kernel<X, false, 32><<<nn, GJ_PANEL_THREADS, 0, st>>>(dd, j0, nb);
       prof.stop(id);
       check_launch("gj_panel");
-      id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, rby);
-      gj_rows_kernel<X><<<dim3(cdiv(wmax, 64) + cdiv(rmax, 256), nn), 256, 0, st>>>(dd, j0, nb, cdiv(wmax, 64),
-                                                                                   c.rot || c.tourn ? 1 : 0);
+      id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, sp.rby[pi]);
+      gj_rows_kernel<X><<<dim3(cdiv(sp.wmax, 64) + cdiv(sp.rmax, 256), nn), 256, 0, st>>>(
+          dd, j0, nb, cdiv(sp.wmax, 64), c.rot || c.tourn ? 1 : 0);
       prof.stop(id);
       check_launch("gj_rows");
-      run_gemm<X>(upd[pi], m1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
+      run_gemm<X>(sp.upd[pi], m1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
     }
+  }
+  template <class X>
+  void gj_sweep(const std::vector<GjDesc<X>>& ds, const GjDesc<X>* dd, const GjCfg& c, Arena& ar) {
+    const SweepPlan sp = prep_sweep<X>(ds, c.nb, ar);
+    run_sweep<X>(sp, dd, c);
+  }
+  // launches of the enclosing scope go to another stream (and are timed there)
+  struct OnStream {
+    Engine& e;
+    hipStream_t s0, p0;
+    OnStream(Engine& e_, hipStream_t s) : e(e_), s0(e_.st), p0(e_.prof.st) {
+      e.st = s;
+      e.prof.st = s;
+    }
+    ~OnStream() {
+      e.st = s0;
+      e.prof.st = p0;
+    }
+  };
+  hipStream_t side_st = nullptr;
+  hipEvent_t ev_next = nullptr, ev_swept = nullptr;
+  void ensure_side() {
+    if (side_st) return;
+    HIP_CHECK(hipStreamCreateWithFlags(&side_st, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&ev_next, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&ev_swept, hipEventDisableTiming));
   }
 
   // In-place [M_ii | M_ib] -> [M_ii^{-1} | M_ii^{-1} M_ib] for a batch. Blocks of
@@ -804,88 +839,148 @@ template <class T> struct Engine : EngineBase {
       return 0;
     }
     const int nn = (int)ds.size(), nblk = cdiv(nmax, wo);
-    // inner descriptors of every block (the boxes that still have pivot columns
-    // there): the block copy, pivots from row J on, its own row permutation
+    // lookahead: while block b's product runs on st, block b + 1's columns, updated
+    // first by a product of their own, are copied and swept on the side stream;
+    // the block copies pb alternate between two buffers (descriptor sets dv[0|1])
+    const bool la = kGjLookahead && nblk > 1;
+    std::vector<X*> pbuf[2];
+    for (auto& g : ds) {
+      pbuf[0].push_back(g.pb);
+      pbuf[1].push_back(la ? ar.get<X>((size_t)g.rows * wo) : g.pb);
+    }
+    GjDesc<X>* dv[2] = {dd, dd};
+    if (la) {
+      std::vector<GjDesc<X>> ds1 = ds;
+      for (size_t i = 0; i < ds.size(); ++i) ds1[i].pb = pbuf[1][i];
+      dv[1] = up(ds1, ar);
+    }
+    // per block: inner descriptors (the boxes that still have pivot columns there:
+    // the block copy, pivots from row J on, its own row permutation), their sweep
+    // plan, and the block's product, split under lookahead into the next block's
+    // columns (nxt) and the rest (all)
     std::vector<GjDesc<PX>> inner;
     std::vector<int> ioff(nblk + 1, 0);
-    std::vector<GemmLaunch> outer;
+    std::vector<GemmLaunch> all(nblk), nxt(nblk);
+    std::vector<SweepPlan> plans(nblk);
     // mixed panels: the block's columns widened into the PX copy, and the copy
     // rounded back into pb after its sweep
     std::vector<CvtSeg<PX, X>> wsegs;
     std::vector<CvtSeg<X, PX>> nsegs;
     for (int b = 0; b < nblk; ++b) {
-      const int J = b * wo;
-      std::vector<GemmDesc> gd;
+      const int J = b * wo, Jn = J + wo;
+      std::vector<GemmDesc> ga, gn;
+      std::vector<GjDesc<PX>> blk;
       for (size_t i = 0; i < ds.size(); ++i) {
         const GjDesc<X>& g = ds[i];
         if (J >= g.n) continue;
         const int wb = std::min(wo, g.n - J);
+        X* pb = pbuf[b & 1][i];
         GjDesc<PX> h{};
         if constexpr (mixed) {
           h = px[i];
           h.flag = g.flag;
           h.mv = g.mv;
           wsegs.push_back({h.M, g.M + (size_t)J * g.rows, (int64_t)g.rows * wb});
-          nsegs.push_back({g.pb, h.M, (int64_t)g.rows * wb});
+          nsegs.push_back({pb, h.M, (int64_t)g.rows * wb});
         } else {
           h = g;
-          h.M = g.pb;
+          h.M = pb;
         }
         h.rows = g.rows;
         h.n = h.W = wb;
         h.poff = J;
         h.rbuf = ar.get<PX>((size_t)nb * wb);
         h.rowperm = g.rp_in;
-        inner.push_back(h);
-        if (ldu)  // rows and columns from J on; the block's own columns are written with beta 0
-          gd.push_back({g.pb + J, g.rbuf + (size_t)J * wb, g.M + J + (size_t)J * g.rows, g.rows - J, g.W - J, wb,
-                        g.rows, wb, g.rows, 0, wb});
-        else
-          gd.push_back({g.pb, g.rbuf, g.M, g.rows, g.W, wb, g.rows, wb, g.rows, J, J + wb});
+        blk.push_back(h);
+        // the product: rows r0.., columns c0.. (ldu: both from J), the block's own
+        // columns written with beta 0
+        const int r0 = ldu ? J : 0, c0 = ldu ? J : 0;
+        auto part = [&](int ca, int cb, std::vector<GemmDesc>& out) {
+          if (cb <= ca) return;
+          const int z0 = std::max(J, ca) - ca, z1 = std::max(std::min(J + wb, cb) - ca, z0);
+          out.push_back({pb + r0, g.rbuf + (size_t)ca * wb, g.M + r0 + (size_t)ca * g.rows, g.rows - r0, cb - ca, wb,
+                         g.rows, wb, g.rows, z0, z1});
+        };
+        if (la && Jn < g.n) {
+          const int wn = std::min(wo, g.n - Jn);
+          part(Jn, Jn + wn, gn);
+          part(c0, Jn, ga);
+          part(Jn + wn, g.W, ga);
+        } else {
+          part(c0, g.W, ga);
+        }
       }
-      ioff[b + 1] = (int)inner.size();
-      outer.push_back(prep_gemm<X>(gd, ar));
+      ioff[b + 1] = ioff[b] + (int)blk.size();
+      inner.insert(inner.end(), blk.begin(), blk.end());
+      plans[b] = prep_sweep<PX>(blk, nb, ar);
+      all[b] = prep_gemm<X>(ga, ar);
+      nxt[b] = prep_gemm<X>(gn, ar);
     }
     GjDesc<PX>* di = up(inner, ar);
     CvtSeg<PX, X>* dws = mixed ? up(wsegs, ar) : nullptr;
     CvtSeg<X, PX>* dns = mixed ? up(nsegs, ar) : nullptr;
     const X p1 = traits<X>::one();
-    for (int b = 0; b < nblk; ++b) {
-      const int J = b * wo;
-      fl();
-      // bytes of the block copy and of the block's pivot rows (read, zeroed, staged)
-      double cby = 0, bby = 0;
-      if (prof.on)
-        for (auto& g : ds) {
-          if (J >= g.n) continue;
+    const unsigned cgrid = std::min(cdiv(nmax * wo, 256), 256);
+    if (la) ensure_side();
+    fl();  // every list is on the device before the first launch (none is built below)
+    // bytes of a block's copy and of its pivot rows (read, zeroed, staged)
+    auto copy_bytes = [&](int J) {
+      double b = 0;
+      for (auto& g : ds)
+        if (J < g.n) {
           const double wb = std::min(wo, g.n - J);
-          cby += mixed ? g.rows * wb * (sX + sizeof(PX)) : 2.0 * g.rows * wb * sX;
-          bby += 3.0 * wb * g.W * sX;
+          b += mixed ? g.rows * wb * (sX + sizeof(PX)) : 2.0 * g.rows * wb * sX;
         }
-      const int nbox = ioff[b + 1] - ioff[b];
-      const unsigned cgrid = std::min(cdiv(nmax * wo, 256), 256);
+      return b;
+    };
+    // copy, sweep and (mixed) narrow of block b on the current stream
+    auto sweep_block = [&](int b) {
+      const int J = b * wo, nbox = ioff[b + 1] - ioff[b];
+      const double cby = prof.on ? copy_bytes(J) : 0.0;
       int id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, cby);
       if constexpr (mixed)
         convert_segs_kernel<PX, X><<<dim3(cgrid, nbox), 256, 0, st>>>(dws + ioff[b]);
       else
-        gj_block_copy_kernel<X><<<dim3(cgrid, nn), 256, 0, st>>>(dd, J, wo);
+        gj_block_copy_kernel<X><<<dim3(cgrid, nn), 256, 0, st>>>(dv[b & 1], J, wo);
       prof.stop(id);
       check_launch("gj_block_copy");
-      const std::vector<GjDesc<PX>> blk(inner.begin() + ioff[b], inner.begin() + ioff[b + 1]);
-      gj_sweep<PX>(blk, di + ioff[b], c, ar);
+      run_sweep<PX>(plans[b], di + ioff[b], c);
       if constexpr (mixed) {
         id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, cby);
         convert_segs_kernel<X, PX><<<dim3(cgrid, nbox), 256, 0, st>>>(dns + ioff[b]);
         prof.stop(id);
         check_launch("gj_block_narrow");
       }
-      id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, bby);
-      gj_block_moves_kernel<X><<<nn, 256, 0, st>>>(dd, J);
+    };
+    sweep_block(0);
+    for (int b = 0; b < nblk; ++b) {
+      const int J = b * wo;
+      if (la && b > 0) HIP_CHECK(hipStreamWaitEvent(st, ev_swept, 0));
+      double bby = 0;
+      if (prof.on)
+        for (auto& g : ds)
+          if (J < g.n) bby += 3.0 * std::min(wo, g.n - J) * g.W * sX;
+      int id = prof.start(wide ? C_GJ_ROWS_W : C_GJ_ROWS, 0, bby);
+      gj_block_moves_kernel<X><<<nn, 256, 0, st>>>(dv[b & 1], J);
       check_launch("gj_block_moves");
-      gj_block_rows_kernel<X><<<dim3(cdiv(wmax, GJ_BLOCK_TILE), nn), 256, 0, st>>>(dd, J, wo, ldu ? 1 : 0);
+      gj_block_rows_kernel<X><<<dim3(cdiv(wmax, GJ_BLOCK_TILE), nn), 256, 0, st>>>(dv[b & 1], J, wo, ldu ? 1 : 0);
       prof.stop(id);
       check_launch("gj_block_rows");
-      run_gemm<X>(outer[b], p1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
+      if (la && b + 1 < nblk) {
+        run_gemm<X>(nxt[b], p1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
+        HIP_CHECK(hipEventRecord(ev_next, st));
+        {
+          OnStream os(*this, side_st);
+          HIP_CHECK(hipStreamWaitEvent(st, ev_next, 0));
+          sweep_block(b + 1);
+          HIP_CHECK(hipEventRecord(ev_swept, st));
+        }
+      } else if (!la && b + 1 < nblk) {
+        run_gemm<X>(all[b], p1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
+        sweep_block(b + 1);
+        continue;
+      }
+      run_gemm<X>(all[b], p1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
     }
     return wo;
   }
@@ -1886,6 +1981,14 @@ template <class T> struct Engine : EngineBase {
     agraphs.clear();
     if (cap_st) (void)hipStreamDestroy(cap_st);
     cap_st = nullptr;
+  }
+  void release_side() {
+    if (!side_st) return;
+    (void)hipStreamSynchronize(side_st);
+    (void)hipStreamDestroy(side_st);
+    (void)hipEventDestroy(ev_next);
+    (void)hipEventDestroy(ev_swept);
+    side_st = nullptr;
   }
 
   // y = M^{-t} D^{-1} L^{-1} x with device x, y
