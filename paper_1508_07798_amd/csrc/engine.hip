@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -326,7 +327,11 @@ template <class T> struct Engine : EngineBase {
   // (else the whole box is eliminated in complex128)
   static constexpr bool kGjMixedPanels = true;
   // blocked Gauss-Jordan: the next block's panel sweep overlaps the block product
+  // for batches whose largest box has more than la_above rows (HSS_GJ_LOOKAHEAD_ABOVE
+  // overrides the default)
   static constexpr bool kGjLookahead = true;
+  static constexpr int kGjLookaheadAbove = 2048;
+  int la_above = kGjLookaheadAbove;
   static constexpr int kGjBlockWide = 256;
   // complex64 boxes above this many interior rows are eliminated in complex128
   static constexpr int kGjWidenAbove = 2048;
@@ -459,6 +464,7 @@ template <class T> struct Engine : EngineBase {
     prof.on = o.profile != 0;
     prof.mask = o.profile == 1 ? ~0u : ((unsigned)o.profile >> 1);
     prof.st = st;
+    if (const char* e = std::getenv("HSS_GJ_LOOKAHEAD_ABOVE")) la_above = std::atoi(e);
     int dev = 0;
     HIP_CHECK(hipGetDevice(&dev));
     int v = 0;
@@ -842,7 +848,7 @@ template <class T> struct Engine : EngineBase {
     // lookahead: while block b's product runs on st, block b + 1's columns, updated
     // first by a product of their own, are copied and swept on the side stream;
     // the block copies pb alternate between two buffers (descriptor sets dv[0|1])
-    const bool la = kGjLookahead && nblk > 1;
+    const bool la = kGjLookahead && nblk > 1 && nmax > la_above;
     std::vector<X*> pbuf[2];
     for (auto& g : ds) {
       pbuf[0].push_back(g.pb);
