@@ -175,7 +175,9 @@ hss_status_t gmres_solve(hss_handle_t h, int32_t nrhs, const void* b, void* x, i
  * (2/3) n_i^3 + triangular solves 2 n_i^2 n_b + Schur product 2 n_b^2 n_i per box,
  * the root's LU, and the sampling and truncated QR of every compression attempt
  * from the ranks chosen), "flops_factor_parts" (those six terms), "flops_gj" (the
- * work of the explicit Gauss-Jordan form the library executes),
+ * work of the elimination the library executes: Gauss-Jordan inverses of the
+ * interiors of at most 128 rows, the block LDU form of the larger ones and of the
+ * root, and the Schur products),
  * "bytes_apply", "bytes_spmv", "time_factor_ms", "host_wait_ms"
  * (time the factorization spent waiting for the device at its sync points),
  * "root_block" (block width of the roots' block LDU form; 0: the roots, of at

@@ -330,6 +330,8 @@ template <class T> struct Engine : EngineBase {
   // for batches whose largest box has more than la_above rows (HSS_GJ_LOOKAHEAD_ABOVE
   // overrides the default)
   static constexpr bool kGjLookahead = true;
+  // blocked interior boxes are kept in the block LDU form (else as explicit inverses)
+  static constexpr bool kBoxLdu = true;
   static constexpr int kGjLookaheadAbove = 2048;
   int la_above = kGjLookaheadAbove;
   static constexpr int kGjBlockWide = 256;
@@ -352,7 +354,8 @@ template <class T> struct Engine : EngineBase {
   int q = 0;
 
   struct NodeDev {
-    T* G = nullptr;      // [(P A_ii)^{-1} | X], n_i x (n_i + n_b)
+    T* G = nullptr;      // [(P A_ii)^{-1} or its block LDU form | X], n_i x (n_i + n_b)
+    int wb = 0;          // block width of the LDU form (0: explicit inverse)
     T* Abi = nullptr;    // n_b x n_i
     int* rowperm = nullptr;  // P: row rowperm[i] of A_ii is row i of P A_ii
     int64_t* gidx = nullptr;
@@ -398,21 +401,30 @@ template <class T> struct Engine : EngineBase {
     int nz = 0, maxz = 0;
     int sub = 0;
   };
-  struct ApplyWave {
-    GemvLaunch<T> fwd1, fwd2, bwd;
-  };
-  std::vector<ApplyWave> aw;
-  GemvLaunch<W> root_gemv;
-  // root solve in the block LDU form: c = P r gathered into d_t; forward, per block
-  // J, c[>J] += M[>J, J] c_J; z_K = M_KK c_K into d_r; backward, per block K from
-  // the last, x_K -= M[K, >K] x[>K] in d_r; x copied to d_t
-  struct RootApply {
+  // solves with boxes in the block LDU form (the interiors of a wave, or the
+  // roots): c = P r gathered into d_t; forward, per block J, c[>J] += M[>J, J] c_J;
+  // z_K = M_KK c_K into d_r; backward, per block K from the last, x_K -= M[K, >K]
+  // x[>K] in d_r; x copied to d_t. Every box's block b goes into launch b.
+  template <class X> struct LduApply {
     PermSeg* gather = nullptr;
     PermSeg* copy = nullptr;
     int nseg = 0, maxn = 0;
-    std::vector<GemvLaunch<W>> fwd, bwd;
-    GemvLaunch<W> diag;
-  } ra;
+    std::vector<GemvLaunch<X>> fwd, bwd;
+    GemvLaunch<X> diag;
+  };
+  template <class X> struct LduBox {
+    const X* M;  // n x n block of a column-major array with leading dimension ld
+    int n, ld, wb;
+    int64_t ip;  // position of the box's unknowns in the work vectors
+    const int* rowperm;
+  };
+  struct ApplyWave {
+    GemvLaunch<T> fwd1, fwd2, bwd;
+    LduApply<T> ldu;
+  };
+  std::vector<ApplyWave> aw;
+  GemvLaunch<W> root_gemv;
+  LduApply<W> ra;
   int max_nr = 0;
   // tiles of 64 rows; an entry's columns are split so that a launch has about
   // 1024 work items (at least 128 columns per item), which keeps HBM busy even
@@ -988,6 +1000,23 @@ template <class T> struct Engine : EngineBase {
       }
       run_gemm<X>(all[b], p1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
     }
+    if (ldu) {
+      // the columns right of A hold the block rows D_K^{-1} (L^{-1} P B)_K; X = A^{-1} B
+      // by the backward block substitution B_K -= M[K, >K] B_{>K}, from the last
+      // block, every box's block K in one product
+      const X m1 = traits<X>::mk(-1.0, 0.0);
+      for (int b = nblk - 2; b >= 0; --b) {
+        const int K = b * wo;
+        std::vector<GemmDesc> gd;
+        for (auto& g : ds) {
+          if (g.W <= g.n || K + wo >= g.n) continue;
+          const int r = K + wo;
+          gd.push_back({g.M + K + (size_t)r * g.rows, g.M + r + (size_t)g.n * g.rows, g.M + K + (size_t)g.n * g.rows,
+                        wo, g.W - g.n, g.n - r, g.rows, g.rows, g.rows, 0, 0});
+        }
+        run_gemm<X>(prep_gemm<X>(gd, ar), m1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
+      }
+    }
     return wo;
   }
 
@@ -1077,6 +1106,7 @@ template <class T> struct Engine : EngineBase {
       std::vector<GjDesc<X>> gj, big;
       std::vector<GjDesc<W>> wide;
       std::vector<std::pair<X*, int64_t>> narrow;  // factor block, element count
+      std::vector<int> gj_g, big_g, wide_g;        // their boxes
       for (size_t i = 0; i < nw; ++i) {
         const PNode& n = P.nodes[wv[i]];
         if (n.idof.empty()) continue;
@@ -1089,6 +1119,7 @@ template <class T> struct Engine : EngineBase {
         if constexpr (std::is_same<X, cf>::value) {
           if (g.n > kGjWidenAbove && kGjMixedPanels) {
             big.push_back(g);
+            big_g.push_back(wv[i]);
             continue;
           }
           if (g.n > kGjWidenAbove) {
@@ -1100,16 +1131,22 @@ template <class T> struct Engine : EngineBase {
             gw.rowperm = g.rowperm;
             gw.flag = g.flag;
             wide.push_back(gw);
+            wide_g.push_back(wv[i]);
             narrow.push_back({g.M, ne});
             continue;
           }
         }
         gj.push_back(g);
+        gj_g.push_back(wv[i]);
       }
       lap(2);
-      gauss_jordan<X>(gj, tmp);
+      // blocked boxes end in the block LDU form with X = A_ii^{-1} A_ib beside it
+      auto mark = [&](const std::vector<int>& gs, int wo) {
+        for (int g : gs) nd[g].wb = wo;
+      };
+      mark(gj_g, gauss_jordan<X>(gj, tmp, 0, kBoxLdu));
       if constexpr (std::is_same<X, cf>::value) {
-        gauss_jordan<cf, cd>(big, tmp);
+        mark(big_g, gauss_jordan<cf, cd>(big, tmp, 0, kBoxLdu));
         if (!wide.empty()) {
           const double cby = [&] {
             double b = 0;
@@ -1122,7 +1159,7 @@ template <class T> struct Engine : EngineBase {
                                                                                 narrow[k].second);
           prof.stop(id);
           check_launch("widen");
-          gauss_jordan<W>(wide, tmp);
+          mark(wide_g, gauss_jordan<W>(wide, tmp, 0, kBoxLdu));
           id = prof.start(C_GJ_ROWS_W, 0, cby / 2);
           for (size_t k = 0; k < wide.size(); ++k)
             convert_kernel<X, W><<<grid1(narrow[k].second, 4096), 256, 0, st>>>(wide[k].M, narrow[k].first,
@@ -1840,10 +1877,60 @@ template <class T> struct Engine : EngineBase {
   }
 
   // ---------------------------------------------------------------- apply
+  template <class X> LduApply<X> prep_ldu_apply(const std::vector<LduBox<X>>& bx) {
+    LduApply<X> A;
+    std::vector<PermSeg> pg, pc;
+    int nblk = 0;
+    for (auto& b : bx) {
+      pg.push_back({b.ip, b.ip, b.rowperm, b.n});
+      pc.push_back({b.ip, b.ip, nullptr, b.n});
+      A.maxn = std::max(A.maxn, b.n);
+      nblk = std::max(nblk, cdiv(b.n, b.wb));
+    }
+    if (pg.empty()) return A;
+    A.nseg = (int)pg.size();
+    A.gather = up(pg, persist);
+    A.copy = up(pc, persist);
+    std::vector<GemvDesc<X>> dg;
+    for (int k = 0; k < nblk; ++k) {
+      std::vector<GemvDesc<X>> f, u;
+      for (auto& b : bx) {
+        const int n = b.n, J = k * b.wb, ld = b.ld;
+        if (J >= n) continue;
+        const int w = std::min(b.wb, n - J);
+        const X* M = b.M;
+        const int64_t ip = b.ip;
+        dg.push_back({M + J + (size_t)J * ld, w, w, ip + J, nullptr, ip + J, nullptr, nullptr, ld});
+        if (J + w < n) {
+          f.push_back({M + (J + w) + (size_t)J * ld, n - J - w, w, ip + J, nullptr, ip + J + w, nullptr, nullptr, ld});
+          u.push_back({M + J + (size_t)(J + w) * ld, w, n - J - w, ip + J + w, nullptr, ip + J, nullptr, nullptr, ld});
+        }
+      }
+      if (!f.empty()) {
+        A.fwd.push_back(prep_gemv(f, 2));
+        A.bwd.push_back(prep_gemv(u, 1));
+      }
+    }
+    A.diag = prep_gemv(dg, 0);
+    return A;
+  }
+  template <class X> void run_ldu(const LduApply<X>& A, int nrhs, hipStream_t s) {
+    if (!A.nseg) return;
+    const dim3 pgrid(grid1((int64_t)A.maxn * nrhs, 256), A.nseg);
+    perm_gather_kernel<W><<<pgrid, 256, 0, s>>>(d_r, d_t, (int64_t)ntot, nrhs, A.gather);
+    check_launch("ldu gather");
+    for (auto& L : A.fwd) gemv<X>(L, d_t, d_t, nrhs, s);
+    gemv<X>(A.diag, d_t, d_r, nrhs, s);
+    for (size_t i = A.bwd.size(); i-- > 0;) gemv<X>(A.bwd[i], d_r, d_r, nrhs, s);
+    perm_gather_kernel<W><<<pgrid, 256, 0, s>>>(d_r, d_t, (int64_t)ntot, nrhs, A.copy);
+    check_launch("ldu copy");
+  }
+
   void build_apply() {
     aw.assign(P.waves.size(), ApplyWave{});
     for (size_t h = 0; h < P.waves.size(); ++h) {
       std::vector<GemvDesc<T>> f1, f2, b1;
+      std::vector<LduBox<T>> lb;
       ApplyWave& a = aw[h];
       for (int g : P.waves[h]) {
         const PNode& n = P.nodes[g];
@@ -1851,18 +1938,20 @@ template <class T> struct Engine : EngineBase {
         const int ni = (int)n.idof.size(), nbd = (int)n.bdof.size();
         if (ni == 0) continue;
         const int64_t ip = pr.dof_off + n.ipos;
-        f1.push_back({nd[g].G, ni, ni, ip, nullptr, ip, nullptr, nd[g].rowperm});
+        if (nd[g].wb) lb.push_back({nd[g].G, ni, ni, nd[g].wb, ip, nd[g].rowperm});
+        else f1.push_back({nd[g].G, ni, ni, ip, nullptr, ip, nullptr, nd[g].rowperm});
         if (nbd > 0) {
           f2.push_back({nd[g].Abi, nbd, ni, ip, nullptr, -1, nd[g].bpos});
           b1.push_back({nd[g].G + (size_t)ni * ni, ni, nbd, -1, nd[g].bpos, ip, nullptr});
         }
       }
       a.fwd1 = prep_gemv(f1, 0);
+      a.ldu = prep_ldu_apply<T>(lb);
       a.fwd2 = prep_gemv(f2, 1);
       a.bwd = prep_gemv(b1, 1);
     }
     root_gemv = GemvLaunch<W>{};
-    ra = RootApply{};
+    ra = LduApply<W>{};
     if (!root_wb_) {
       std::vector<GemvDesc<W>> rd;
       for (size_t p = 0; p < P.roots.size(); ++p) {
@@ -1872,45 +1961,11 @@ template <class T> struct Engine : EngineBase {
       root_gemv = prep_gemv(rd, 0);
       return;
     }
-    // block LDU form (blocks of root_wb_ columns; every block of every root in
-    // one launch per block index)
-    const int wb = root_wb_;
-    std::vector<PermSeg> pg, pc;
-    int nblk = 0;
-    for (size_t p = 0; p < P.roots.size(); ++p) {
-      const int64_t ip = P.probs[p].dof_off + P.roots[p].ipos;
-      const int n = rt[p].n;
-      if (n == 0) continue;
-      pg.push_back({ip, ip, rt[p].rowperm, n});
-      pc.push_back({ip, ip, nullptr, n});
-      ra.maxn = std::max(ra.maxn, n);
-      nblk = std::max(nblk, cdiv(n, wb));
-    }
-    if (pg.empty()) return;
-    ra.nseg = (int)pg.size();
-    ra.gather = up(pg, persist);
-    ra.copy = up(pc, persist);
-    std::vector<GemvDesc<W>> dg;
-    for (int b = 0; b < nblk; ++b) {
-      std::vector<GemvDesc<W>> f, u;
-      for (size_t p = 0; p < P.roots.size(); ++p) {
-        const int64_t ip = P.probs[p].dof_off + P.roots[p].ipos;
-        const int n = rt[p].n, J = b * wb;
-        if (J >= n) continue;
-        const int w = std::min(wb, n - J);
-        W* M = rt[p].R;
-        dg.push_back({M + J + (size_t)J * n, w, w, ip + J, nullptr, ip + J, nullptr, nullptr, n});
-        if (J + w < n) {
-          f.push_back({M + (J + w) + (size_t)J * n, n - J - w, w, ip + J, nullptr, ip + J + w, nullptr, nullptr, n});
-          u.push_back({M + J + (size_t)(J + w) * n, w, n - J - w, ip + J + w, nullptr, ip + J, nullptr, nullptr, n});
-        }
-      }
-      if (!f.empty()) {
-        ra.fwd.push_back(prep_gemv(f, 2));
-        ra.bwd.push_back(prep_gemv(u, 1));
-      }
-    }
-    ra.diag = prep_gemv(dg, 0);
+    std::vector<LduBox<W>> rb;
+    for (size_t p = 0; p < P.roots.size(); ++p)
+      if (rt[p].n > 0)
+        rb.push_back({rt[p].R, rt[p].n, rt[p].n, root_wb_, P.probs[p].dof_off + P.roots[p].ipos, rt[p].rowperm});
+    ra = prep_ldu_apply<W>(rb);
   }
 
   void ensure_work(int nrhs) {
@@ -1935,22 +1990,15 @@ template <class T> struct Engine : EngineBase {
   // the forward sweep, the root solve and the backward sweep on the tree-ordered
   // work vectors (d_r in, d_t out): fixed buffers, so the sequence can be captured
   void sweeps(int nrhs, hipStream_t s) {
+    // an interior's LDU solve uses its own segment of d_r as scratch: nothing reads
+    // that segment after the wave's forward step
     for (size_t h = 0; h < aw.size(); ++h) {
       gemv<T>(aw[h].fwd1, d_r, d_t, nrhs, s);
+      run_ldu<T>(aw[h].ldu, nrhs, s);
       gemv<T>(aw[h].fwd2, d_t, d_r, nrhs, s);
     }
-    if (!root_wb_) {
-      gemv<W>(root_gemv, d_r, d_t, nrhs, s);
-    } else if (ra.nseg) {
-      const dim3 pgrid(grid1((int64_t)ra.maxn * nrhs, 256), ra.nseg);
-      perm_gather_kernel<W><<<pgrid, 256, 0, s>>>(d_r, d_t, (int64_t)ntot, nrhs, ra.gather);
-      check_launch("root gather");
-      for (auto& L : ra.fwd) gemv<W>(L, d_t, d_t, nrhs, s);
-      gemv<W>(ra.diag, d_t, d_r, nrhs, s);
-      for (size_t i = ra.bwd.size(); i-- > 0;) gemv<W>(ra.bwd[i], d_r, d_r, nrhs, s);
-      perm_gather_kernel<W><<<pgrid, 256, 0, s>>>(d_r, d_t, (int64_t)ntot, nrhs, ra.copy);
-      check_launch("root copy");
-    }
+    if (!root_wb_) gemv<W>(root_gemv, d_r, d_t, nrhs, s);
+    else run_ldu<W>(ra, nrhs, s);
     for (size_t h = aw.size(); h-- > 0;) gemv<T>(aw[h].bwd, d_t, d_t, nrhs, s);
   }
   // captured sweeps, one executable graph per right-hand-side count; captured on a
@@ -2339,13 +2387,26 @@ template <class T> struct Engine : EngineBase {
       if (key == "flops_factor") out = {lu + trsm + gemm_ + root + alg_sample + alg_cpqr};
       else out = {lu, trsm, gemm_, root, alg_sample, alg_cpqr};
     } else if (key == "flops_gj") {
-      // the work the explicit Gauss-Jordan form executes: n_i^2 (n_i + n_b) for the
-      // interior inverse and X, n_b^2 n_i for the Schur product; for the root n^3
-      // (inverse) or the sum over blocks J of (n - J)^2 w (block LDU form)
+      // the work the elimination executes: n_b^2 n_i for the Schur product, and for
+      // each interior n_i^2 (n_i + n_b) (explicit inverse and X) or the block LDU
+      // form's products; for the root n^3 (inverse) or the sum over blocks J of
+      // (n - J)^2 w (block LDU form)
       double f = 0;
-      for (auto& n : P.nodes) {
-        double ni = (double)n.idof.size(), nbd = (double)n.bdof.size();
-        f += Flop<T>::mac * (ni * ni * (ni + nbd) + nbd * nbd * ni);
+      for (size_t g = 0; g < P.nodes.size(); ++g) {
+        const PNode& n = P.nodes[g];
+        const double ni = (double)n.idof.size(), nbd = (double)n.bdof.size();
+        f += Flop<T>::mac * nbd * nbd * ni;
+        const int wb = nd.size() > g ? nd[g].wb : 0;
+        if (!wb) {
+          f += Flop<T>::mac * ni * ni * (ni + nbd);
+          continue;
+        }
+        // block LDU: each block's product over the rows and columns from the block
+        // on, then the backward substitution for X
+        for (int J = 0; J < (int)ni; J += wb) {
+          const double m = ni - J, w = std::min(wb, (int)ni - J);
+          f += Flop<T>::mac * (m * (m + nbd) * w + w * nbd * std::max(0.0, m - w));
+        }
       }
       for (auto& r : rt) {
         if (!root_wb_) {
