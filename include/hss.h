@@ -112,6 +112,12 @@ typedef struct {
                               S (symmetrized, before compression) and compressed S~
                               the handle keeps for hss_query "kept_S" / "kept_St"
                               (0: none; HSS_EINVAL if no such box)                */
+  int32_t ldu;             /* storage of the eliminated interiors of more than 128
+                              rows and of the root: 0 explicit inverses, 1 block LDU
+                              form (a third of the inverse's work, two GEMV launches
+                              per block in each apply), 2 (default) the LDU form for
+                              the batches where the work saved outweighs the added
+                              launches                                            */
 } hss_opts_t;
 
 typedef struct {

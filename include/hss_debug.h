@@ -7,8 +7,10 @@
  * scalar codes: 0 = float, 1 = double, 2 = complex float, 3 = complex double;
  * hss_debug_gemm also takes 4 = float operands on BF16 matrix cores (each value
  * split into bf16 hi + lo parts, three products, FP32 accumulation: the Schur
- * update of the HSS_PREC_BF16 factorization) and 5 = complex float operands on
- * BF16 matrix cores (the same split for each of the four real products).
+ * update of the HSS_PREC_BF16 factorization), 5 = complex float operands on
+ * BF16 matrix cores (the same split for each of the four real products), and
+ * 6 = float on the 128 x 128-tile MFMA kernel that the factorization uses for its
+ * large real FP32 products.
  */
 #ifndef HSS_DEBUG_H
 #define HSS_DEBUG_H

@@ -159,6 +159,7 @@ void hss_default_opts(hss_opts_t* o) {
   o->hss_leaf_elems = 4;
   o->rank_model_path = nullptr;
   o->keep_box = 0;
+  o->ldu = 2;
 }
 
 const char* hss_last_error(void) { return g_err.c_str(); }
@@ -172,7 +173,8 @@ hss_status_t hss_factor_batched(int32_t nprob, const hss_block_op_t* A, const hs
     hss_opts_t opts;
     hss_default_opts(&opts);
     if (o) opts = *o;
-    if (opts.p_os < 1 || opts.l0 < 1 || opts.max_attempts < 1 || opts.hss_leaf_elems < 0 || opts.keep_box < 0)
+    if (opts.p_os < 1 || opts.l0 < 1 || opts.max_attempts < 1 || opts.hss_leaf_elems < 0 || opts.keep_box < 0 ||
+        opts.ldu < 0 || opts.ldu > 2)
       return fail(HSS_EINVAL, "bad options");
     const int leaf = opts.hss_leaf_elems > 0 ? opts.hss_leaf_elems : 4;
     if (opts.prec != HSS_PREC_FP64 && opts.prec != HSS_PREC_FP32 && opts.prec != HSS_PREC_BF16)

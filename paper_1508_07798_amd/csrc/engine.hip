@@ -330,10 +330,15 @@ template <class T> struct Engine : EngineBase {
   // for batches whose largest box has more than la_above rows (HSS_GJ_LOOKAHEAD_ABOVE
   // overrides the default)
   static constexpr bool kGjLookahead = true;
-  // blocked interior boxes are kept in the block LDU form (else as explicit inverses)
-  static constexpr bool kBoxLdu = true;
+  // blocked interior boxes and roots in the block LDU form (hss_opts_t.ldu; mode 2
+  // of gauss_jordan prices one extra GEMV launch per solve iteration as 5 us at 50
+  // TFLOP/s over 20 iterations)
+  static constexpr double kLduLaunchFlops = 5e9;
   static constexpr int kGjLookaheadAbove = 2048;
   int la_above = kGjLookaheadAbove;
+  // 128 x 128 GEMM tiles for large real FP32 products (HSS_GEMM_BIG=0: off)
+  static constexpr int kGemmBigMinTiles = 256;
+  bool gemm_big_on = true;
   static constexpr int kGjBlockWide = 256;
   // complex64 boxes above this many interior rows are eliminated in complex128
   static constexpr int kGjWidenAbove = 2048;
@@ -477,6 +482,7 @@ template <class T> struct Engine : EngineBase {
     prof.mask = o.profile == 1 ? ~0u : ((unsigned)o.profile >> 1);
     prof.st = st;
     if (const char* e = std::getenv("HSS_GJ_LOOKAHEAD_ABOVE")) la_above = std::atoi(e);
+    if (const char* e = std::getenv("HSS_GEMM_BIG")) gemm_big_on = std::atoi(e) != 0;
     int dev = 0;
     HIP_CHECK(hipGetDevice(&dev));
     int v = 0;
@@ -556,19 +562,35 @@ template <class T> struct Engine : EngineBase {
     int* pre = nullptr;
     int n = 0, tiles = 0;
     double flops = 0;
+    bool big = false;  // 128 x 128 tiles
   };
   // uploads the descriptors (copied at the next launch point)
-  template <class X> GemmLaunch prep_gemm(const std::vector<GemmDesc>& ds, Arena& ar) {
+  // big_ok: the launch goes through run_gemm, which may take 128 x 128 tiles (the
+  // tile prefix then counts those); other consumers launch 64 x 64 kernels
+  template <class X> GemmLaunch prep_gemm(const std::vector<GemmDesc>& ds, Arena& ar, bool big_ok = false) {
     std::vector<GemmDesc> v;
-    std::vector<int> pre{0};
     GemmLaunch L;
+    int64_t t64 = 0;
     for (auto& g : ds) {
       if (g.M <= 0 || g.N <= 0) continue;
       v.push_back(g);
-      pre.push_back(pre.back() + cdiv(g.M, GBM) * cdiv(g.N, GBN));
+      t64 += (int64_t)cdiv(g.M, GBM) * cdiv(g.N, GBN);
       L.flops += Flop<X>::mac * (double)g.M * g.N * g.K;
     }
     if (v.empty()) return L;
+    // 128 x 128 tiles for real FP32 products deep and wide enough that the launch
+    // still fills the chip with them (measured 20% faster there; for complex64,
+    // whose three planes hold the kernel to one wave per SIMD, slower at every
+    // size measured, so never)
+    if constexpr (std::is_same<X, float>::value) {
+      double kmean = 0, mn = 0;
+      for (auto& g : v) kmean += (double)g.K * g.M * g.N, mn += (double)g.M * g.N;
+      kmean /= std::max(mn, 1.0);
+      L.big = big_ok && gemm_big_on && t64 >= 4 * kGemmBigMinTiles && kmean >= 1024;
+    }
+    const int tm = L.big ? GBM_BIG : GBM, tn = L.big ? GBN_BIG : GBN;
+    std::vector<int> pre{0};
+    for (auto& g : v) pre.push_back(pre.back() + cdiv(g.M, tm) * cdiv(g.N, tn));
     L.d = up(v, ar);
     L.pre = up(pre, ar);
     L.n = (int)v.size();
@@ -579,7 +601,20 @@ template <class T> struct Engine : EngineBase {
     if (L.n == 0) return;
     fl();
     int id = prof.start(cls, L.flops, 0);
-    if (cls == C_SCHUR) gemm_nn_kernel<X, GEMM_SCHUR><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+    bool done = false;
+    if constexpr (std::is_same<X, float>::value) {
+      if (L.big) {
+        if (cls == C_SCHUR) gemm_big_kernel<X, GEMM_SCHUR><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+        else if (cls == C_GJ_UPDATE || cls == C_GJ_UPDATE_W)
+          gemm_big_kernel<X, GEMM_GJ_UPDATE><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+        else if (cls == C_SAMPLE_GEMM)
+          gemm_big_kernel<X, GEMM_SAMPLE><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+        else gemm_big_kernel<X, GEMM_GENERIC><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
+        done = true;
+      }
+    }
+    if (done) {
+    } else if (cls == C_SCHUR) gemm_nn_kernel<X, GEMM_SCHUR><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
     else if (cls == C_GJ_UPDATE || cls == C_GJ_UPDATE_W)
       gemm_nn_kernel<X, GEMM_GJ_UPDATE><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
     else if (cls == C_SAMPLE_GEMM) gemm_nn_kernel<X, GEMM_SAMPLE><<<L.tiles, 256, 0, st>>>(L.d, L.pre, L.n, alpha, beta);
@@ -613,7 +648,7 @@ template <class T> struct Engine : EngineBase {
   }
   template <class X>
   void gemm(const std::vector<GemmDesc>& ds, X alpha, X beta, int cls, Arena& ar) {
-    run_gemm<X>(prep_gemm<X>(ds, ar), alpha, beta, cls);
+    run_gemm<X>(prep_gemm<X>(ds, ar, true), alpha, beta, cls);
   }
 
   // ---------------------------------------------------------------- GJ
@@ -736,7 +771,7 @@ template <class T> struct Engine : EngineBase {
         for (int cc = 0; cc < w; ++cc) pfl += Flop<X>::mac * (R - cc - 1) * (w - cc - 1);
         rby += (2.0 * g.rows * w + 3.0 * w * g.W) * sX;
       }
-      sp.upd.push_back(prep_gemm<X>(gd, ar));
+      sp.upd.push_back(prep_gemm<X>(gd, ar, true));
       sp.pfl.push_back(pfl);
       sp.rby.push_back(rby);
     }
@@ -806,9 +841,12 @@ template <class T> struct Engine : EngineBase {
   // PX != X (blocked form only): the block copy is held in PX and its panel sweep
   // runs in PX; the result is rounded back to X for the block's product, which
   // runs in X like the rest of the box.
-  // Returns the block width (0: unblocked, always the inverse).
+  // ldu_mode: 0 the inverse, 1 the LDU form, 2 the LDU form where the work it
+  // saves, (2/3) n^3 per box, outweighs the apply launches it adds (two per block
+  // and solve iteration), priced at kLduLaunchFlops each.
+  // Returns the block width of the LDU form (0: the inverse).
   template <class X, class PX = X>
-  int gauss_jordan(std::vector<GjDesc<X>>& ds, Arena& ar, int block = 0, bool ldu = false) {
+  int gauss_jordan(std::vector<GjDesc<X>>& ds, Arena& ar, int block = 0, int ldu_mode = 0) {
     if (ds.empty()) return 0;
     constexpr bool wide = !std::is_same<X, T>::value;
     constexpr bool mixed = !std::is_same<X, PX>::value;
@@ -827,6 +865,12 @@ template <class T> struct Engine : EngineBase {
                        : (nmax > kGjBlockWideAbove ? kGjBlockWide : nmax > kGjBlockMin ? kGjBlock : 0);
     if (wo >= nmax) wo = 0;
     if (mixed && !wo) throw Error(HSS_EDEVICE, "panels in another precision need the blocked form");
+    bool ldu = wo > 0 && ldu_mode == 1;
+    if (wo > 0 && ldu_mode == 2) {
+      double saved = 0;
+      for (auto& g : ds) saved += (2.0 / 3.0) * Flop<X>::mac * (double)g.n * g.n * g.n;
+      ldu = saved > (2.0 * cdiv(nmax, wo) + 1.0) * kLduLaunchFlops;
+    }
     // scratch per box (for mixed panels, the panel sweep's own set in PX)
     std::vector<GjDesc<PX>> px(ds.size());
     for (size_t i = 0; i < ds.size(); ++i) {
@@ -931,8 +975,8 @@ template <class T> struct Engine : EngineBase {
       ioff[b + 1] = ioff[b] + (int)blk.size();
       inner.insert(inner.end(), blk.begin(), blk.end());
       plans[b] = prep_sweep<PX>(blk, nb, ar);
-      all[b] = prep_gemm<X>(ga, ar);
-      nxt[b] = prep_gemm<X>(gn, ar);
+      all[b] = prep_gemm<X>(ga, ar, true);
+      nxt[b] = prep_gemm<X>(gn, ar, true);
     }
     GjDesc<PX>* di = up(inner, ar);
     CvtSeg<PX, X>* dws = mixed ? up(wsegs, ar) : nullptr;
@@ -1014,10 +1058,10 @@ template <class T> struct Engine : EngineBase {
           gd.push_back({g.M + K + (size_t)r * g.rows, g.M + r + (size_t)g.n * g.rows, g.M + K + (size_t)g.n * g.rows,
                         wo, g.W - g.n, g.n - r, g.rows, g.rows, g.rows, 0, 0});
         }
-        run_gemm<X>(prep_gemm<X>(gd, ar), m1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
+        run_gemm<X>(prep_gemm<X>(gd, ar, true), m1, p1, wide ? C_GJ_UPDATE_W : C_GJ_UPDATE);
       }
     }
-    return wo;
+    return ldu ? wo : 0;
   }
 
   // ---------------------------------------------------------------- input check
@@ -1144,9 +1188,9 @@ template <class T> struct Engine : EngineBase {
       auto mark = [&](const std::vector<int>& gs, int wo) {
         for (int g : gs) nd[g].wb = wo;
       };
-      mark(gj_g, gauss_jordan<X>(gj, tmp, 0, kBoxLdu));
+      mark(gj_g, gauss_jordan<X>(gj, tmp, 0, o.ldu));
       if constexpr (std::is_same<X, cf>::value) {
-        mark(big_g, gauss_jordan<cf, cd>(big, tmp, 0, kBoxLdu));
+        mark(big_g, gauss_jordan<cf, cd>(big, tmp, 0, o.ldu));
         if (!wide.empty()) {
           const double cby = [&] {
             double b = 0;
@@ -1159,7 +1203,7 @@ template <class T> struct Engine : EngineBase {
                                                                                 narrow[k].second);
           prof.stop(id);
           check_launch("widen");
-          mark(wide_g, gauss_jordan<W>(wide, tmp, 0, kBoxLdu));
+          mark(wide_g, gauss_jordan<W>(wide, tmp, 0, o.ldu));
           id = prof.start(C_GJ_ROWS_W, 0, cby / 2);
           for (size_t k = 0; k < wide.size(); ++k)
             convert_kernel<X, W><<<grid1(narrow[k].second, 4096), 256, 0, st>>>(wide[k].M, narrow[k].first,
@@ -1377,7 +1421,7 @@ template <class T> struct Engine : EngineBase {
         g.flag = d_sing + nn + p;
         gj.push_back(g);
       }
-      root_wb_ = gauss_jordan<W>(gj, tmp, 0, true);
+      root_wb_ = gauss_jordan<W>(gj, tmp, 0, o.ldu);
       // singular pivots
       std::vector<int> sing(nn + nprob + 1);
       HIP_CHECK(hipMemcpyAsync(sing.data(), d_sing, sizeof(int) * sing.size(), hipMemcpyDeviceToHost, st));
@@ -2472,13 +2516,16 @@ template <class X> struct DebugRunner : Engine<X> {
 template <class X>
 void debug_gemm_t(int nb, const void* const* A, const void* const* B, void* const* C, const int32_t* M,
                   const int32_t* N, const int32_t* K, const int32_t* lda, const int32_t* ldb, const int32_t* ldc,
-                  const double* al, const double* be, hipStream_t st, bool bf16x3 = false) {
+                  const double* al, const double* be, hipStream_t st, int variant = 0) {
+  // variant: 0 the 64 x 64 MFMA kernel, 1 BF16 x 3, 2 the 128 x 128 MFMA kernel
+  const bool bf16x3 = variant == 1, big = variant == 2;
+  const int tm = big ? GBM_BIG : GBM, tn = big ? GBN_BIG : GBN;
   std::vector<GemmDesc> v;
   std::vector<int> pre{0};
   for (int b = 0; b < nb; ++b) {
     if (M[b] <= 0 || N[b] <= 0) continue;
     v.push_back({A[b], B[b], C[b], M[b], N[b], K[b], lda[b], ldb[b], ldc[b]});
-    pre.push_back(pre.back() + cdiv(M[b], GBM) * cdiv(N[b], GBN));
+    pre.push_back(pre.back() + cdiv(M[b], tm) * cdiv(N[b], tn));
   }
   if (v.empty()) return;
   Arena ar;
@@ -2490,6 +2537,8 @@ void debug_gemm_t(int nb, const void* const* A, const void* const* B, void* cons
   if constexpr (std::is_same<X, float>::value) {
     if (bf16x3)
       gemm_bf16x3_kernel<GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), (float)al[0], (float)be[0]);
+    else if (big)
+      gemm_big_kernel<X, GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), (float)al[0], (float)be[0]);
     else
       gemm_nn_kernel<X, GEMM_GENERIC><<<pre.back(), 256, 0, st>>>(dd, dp, (int)v.size(), (float)al[0], (float)be[0]);
   } else if constexpr (std::is_same<X, cf>::value) {
@@ -2519,8 +2568,9 @@ void debug_gemm(int scalar, int nb, const void* const* A, const void* const* B, 
     case 1: debug_gemm_t<double>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
     case 2: debug_gemm_t<cf>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
     case 3: debug_gemm_t<cd>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st); break;
-    case 4: debug_gemm_t<float>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st, true); break;
-    case 5: debug_gemm_t<cf>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st, true); break;
+    case 4: debug_gemm_t<float>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st, 1); break;
+    case 5: debug_gemm_t<cf>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st, 1); break;
+    case 6: debug_gemm_t<float>(nb, A, B, C, M, N, K, lda, ldb, ldc, al, be, st, 2); break;
     default: throw Error(HSS_EINVAL, "unknown scalar code");
   }
 }

@@ -4,7 +4,8 @@
 // for every entry b of a descriptor array, one launch for all entries.
 //
 // Tiles of 64 x 64 outputs per 256-thread workgroup (4 wavefronts, each a
-// 32 x 32 quadrant made of 2 x 2 MFMA 16x16 blocks). K advances in slabs of
+// 32 x 32 quadrant made of 2 x 2 MFMA 16x16 blocks), or 128 x 128 for large
+// real FP32 products (each wave 4 x 4 blocks). K advances in slabs of
 // BK, staged through LDS with the next slab prefetched into registers while
 // the current one is consumed. FP32 uses v_mfma_f32_16x16x4_f32, FP64 uses
 // v_mfma_f64_16x16x4_f64; complex operands use four real products
@@ -65,11 +66,14 @@ template <class T> struct gemm_cfg {
 // tells the Schur update, the Gauss-Jordan trailing update and the sampling apart.
 enum GemmRole { GEMM_GENERIC = 0, GEMM_SCHUR = 1, GEMM_GJ_UPDATE = 2, GEMM_SAMPLE = 3 };
 
-// One 64 x 64 tile of C.
-template <class T, int ROLE>
-__global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict__ descs,
-                                                      const int* __restrict__ tprefix, int nent,
-                                                      T alpha, T beta) {
+// One (32 WI) x (32 WI) tile of C per workgroup: the four waves in a 2 x 2 grid,
+// each owning WI x WI MFMA 16x16 blocks. WI = 2 (64 x 64 tiles) serves every
+// launch; WI = 4 (128 x 128 tiles) the large real FP32 products, where each
+// staged value then serves twice as many outputs. (For complex64 that tile needs
+// 424 registers, one wave per SIMD, and measured slower at every size.)
+template <class T, int WI>
+__device__ __forceinline__ void gemm_tile(const GemmDesc* __restrict__ descs, const int* __restrict__ tprefix,
+                                          int nent, T alpha, T beta) {
   using R = typename traits<T>::real;
   using Acc = typename mfma_acc<R>::type;
   constexpr bool CX = traits<T>::cplx;
@@ -80,7 +84,8 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict
   constexpr bool G3 = CX && std::is_same<R, float>::value;
   constexpr int NP = CX ? (G3 ? 3 : 2) : 1;
   constexpr int BK = gemm_cfg<T>::BK;
-  constexpr int LDA_S = GBM + 4, LDB_S = GBN + 4;
+  constexpr int TM = 32 * WI, TN = 32 * WI, WT = 16 * WI;  // tile, wave tile
+  constexpr int LDA_S = TM + 4, LDB_S = TN + 4;
   __shared__ R As[NP][BK][LDA_S];
   __shared__ R Bs[NP][BK][LDB_S];
 
@@ -93,31 +98,31 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict
   }
   const GemmDesc g = descs[lo];
   const int t = bid - tprefix[lo];
-  const int tmc = (g.M + GBM - 1) / GBM;
-  const int m0 = (t % tmc) * GBM, n0 = (t / tmc) * GBN;
+  const int tmc = (g.M + TM - 1) / TM;
+  const int m0 = (t % tmc) * TM, n0 = (t / tmc) * TN;
   const T* __restrict__ Ag = (const T*)g.A;
   const T* __restrict__ Bg = (const T*)g.B;
   T* __restrict__ Cg = (T*)g.C;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int wm = (wave & 1) * WT, wn = (wave >> 1) * WT;
   const int li = lane & 15, lk = lane >> 4;
 
-  Acc acc[NP][2][2];
+  Acc acc[NP][WI][WI];
   for (int p = 0; p < NP; ++p)
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) acc[p][i][j] = Acc{0, 0, 0, 0};
+    for (int i = 0; i < WI; ++i)
+      for (int j = 0; j < WI; ++j) acc[p][i][j] = Acc{0, 0, 0, 0};
 
-  // global -> register staging: A slab GBM x BK, B slab BK x GBN
-  constexpr int AE = GBM * BK / 256;  // elements per thread
-  constexpr int BE = BK * GBN / 256;
+  // global -> register staging: A slab TM x BK, B slab BK x TN
+  constexpr int AE = TM * BK / 256;  // elements per thread
+  constexpr int BE = BK * TN / 256;
   T ra[AE], rb[BE];
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < AE; ++e) {
       int idx = tid + e * 256;
-      int i = idx % GBM, k = idx / GBM;
+      int i = idx % TM, k = idx / TM;
       int gi = m0 + i, gk = k0 + k;
       ra[e] = (gi < g.M && gk < g.K) ? Ag[gi + (size_t)gk * g.lda] : traits<T>::zero();
     }
@@ -133,7 +138,7 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict
 #pragma unroll
     for (int e = 0; e < AE; ++e) {
       int idx = tid + e * 256;
-      int i = idx % GBM, k = idx / GBM;
+      int i = idx % TM, k = idx / TM;
       R re, im;
       split(ra[e], re, im);
       As[0][k][i] = re;
@@ -160,18 +165,18 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kk = ks + lk;
-      R a[NP][2], b[NP][2];
+      R a[NP][WI], b[NP][WI];
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        a[p][0] = As[p][kk][wm + li];
-        a[p][1] = As[p][kk][wm + 16 + li];
-        b[p][0] = Bs[p][kk][wn + li];
-        b[p][1] = Bs[p][kk][wn + 16 + li];
-      }
+      for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < WI; ++i) {
+          a[p][i] = As[p][kk][wm + 16 * i + li];
+          b[p][i] = Bs[p][kk][wn + 16 * i + li];
+        }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+      for (int i = 0; i < WI; ++i)
+#pragma unroll
+        for (int j = 0; j < WI; ++j) {
           if constexpr (G3) {
             acc[0][i][j] = mfma_acc<R>::mac(a[0][i], b[0][j], acc[0][i][j]);
             acc[1][i][j] = mfma_acc<R>::mac(a[1][i], b[1][j], acc[1][i][j]);
@@ -189,47 +194,71 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict
     __syncthreads();
   }
 
-  // epilogue: lane holds column lane%16 and four rows of each 16x16 block. All
-  // reads of C are issued before the first store (the stores could alias the
-  // reads as far as the compiler knows, which would serialize read-store pairs).
+  // epilogue: lane holds column lane%16 and four rows of each 16x16 block. Per
+  // group of RG rows of blocks (all of them for 64 x 64 tiles, one for 128 x 128,
+  // which bounds the registers held), all reads of C are issued before the first
+  // store (the stores could alias the reads as far as the compiler knows, which
+  // would serialize read-store pairs).
+  constexpr int RG = WI <= 2 ? WI : 1;
   const bool rdc = !(traits<T>::re(beta) == 0 && traits<T>::im(beta) == 0);
-  R cre[2][2][4], cim[2][2][4];
-  static_for<0, 2>([&](auto ii) {
-    static_for<0, 2>([&](auto jj) {
-      constexpr int i = decltype(ii)::value, j = decltype(jj)::value;
-      const int col = n0 + wn + j * 16 + li;
-      const bool keep = col < g.N && (col < g.z0 || col >= g.z1) && rdc;
-      static_for<0, 4>([&](auto vv) {
-        constexpr int v = decltype(vv)::value;
-        const int row = m0 + wm + i * 16 + mfma_acc<R>::row(lk, v);
-        const T c = (keep && row < g.M) ? Cg[row + (size_t)col * g.ldc] : traits<T>::zero();
-        cre[i][j][v] = traits<T>::re(c);
-        cim[i][j][v] = traits<T>::im(c);
+  static_for<0, WI / RG>([&](auto gg) {
+    constexpr int i0 = decltype(gg)::value * RG;
+    R cre[RG][WI][4], cim[RG][WI][4];
+    static_for<0, RG>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      static_for<0, WI>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        const int col = n0 + wn + j * 16 + li;
+        const bool keep = col < g.N && (col < g.z0 || col >= g.z1) && rdc;
+        static_for<0, 4>([&](auto vv) {
+          constexpr int v = decltype(vv)::value;
+          const int row = m0 + wm + (i0 + i) * 16 + mfma_acc<R>::row(lk, v);
+          const T c = (keep && row < g.M) ? Cg[row + (size_t)col * g.ldc] : traits<T>::zero();
+          cre[i][j][v] = traits<T>::re(c);
+          cim[i][j][v] = traits<T>::im(c);
+        });
       });
     });
-  });
-  static_for<0, 2>([&](auto ii) {
-    static_for<0, 2>([&](auto jj) {
-      constexpr int i = decltype(ii)::value, j = decltype(jj)::value;
-      const int col = n0 + wn + j * 16 + li;
-      static_for<0, 4>([&](auto vv) {
-        constexpr int v = decltype(vv)::value;
-        const int row = m0 + wm + i * 16 + mfma_acc<R>::row(lk, v);
-        if (col < g.N && row < g.M) {
-          T val;
-          if constexpr (G3) {
-            const R t0 = acc[0][i][j][v], t1 = acc[1][i][j][v];
-            val = traits<T>::mk(t0 - t1, acc[2][i][j][v] - t0 - t1);
-          } else if constexpr (CX) {
-            val = traits<T>::mk(acc[0][i][j][v], acc[1][i][j][v]);
-          } else {
-            val = acc[0][i][j][v];
+    static_for<0, RG>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      static_for<0, WI>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        const int col = n0 + wn + j * 16 + li;
+        static_for<0, 4>([&](auto vv) {
+          constexpr int v = decltype(vv)::value;
+          const int row = m0 + wm + (i0 + i) * 16 + mfma_acc<R>::row(lk, v);
+          if (col < g.N && row < g.M) {
+            T val;
+            if constexpr (G3) {
+              const R t0 = acc[0][i0 + i][j][v], t1 = acc[1][i0 + i][j][v];
+              val = traits<T>::mk(t0 - t1, acc[2][i0 + i][j][v] - t0 - t1);
+            } else if constexpr (CX) {
+              val = traits<T>::mk(acc[0][i0 + i][j][v], acc[1][i0 + i][j][v]);
+            } else {
+              val = acc[0][i0 + i][j][v];
+            }
+            Cg[row + (size_t)col * g.ldc] =
+                sc_mul(alpha, val) + sc_mul(beta, traits<T>::mk(cre[i][j][v], cim[i][j][v]));
           }
-          Cg[row + (size_t)col * g.ldc] = sc_mul(alpha, val) + sc_mul(beta, traits<T>::mk(cre[i][j][v], cim[i][j][v]));
-        }
+        });
       });
     });
   });
+}
+
+// 64 x 64 tiles (GBM x GBN)
+template <class T, int ROLE>
+__global__ __launch_bounds__(256) void gemm_nn_kernel(const GemmDesc* __restrict__ descs,
+                                                      const int* __restrict__ tprefix, int nent, T alpha, T beta) {
+  gemm_tile<T, 2>(descs, tprefix, nent, alpha, beta);
+}
+
+// 128 x 128 tiles (GBM_BIG x GBN_BIG)
+constexpr int GBM_BIG = 128, GBN_BIG = 128;
+template <class T, int ROLE>
+__global__ __launch_bounds__(256) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
+                                                       const int* __restrict__ tprefix, int nent, T alpha, T beta) {
+  gemm_tile<T, 4>(descs, tprefix, nent, alpha, beta);
 }
 
 // ---------------------------------------------------------------- BF16 x 3

@@ -41,7 +41,8 @@ class Opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("p_os", C.c_int32), ("l0", C.c_int32), ("max_attempts", C.c_int32),
                 ("seed", C.c_uint64), ("rank_model", C.c_void_p), ("kappa_h", C.c_double),
                 ("hip_stream", C.c_void_p), ("profile", C.c_int32), ("apply_graph", C.c_int32),
-                ("hss_leaf_elems", C.c_int32), ("rank_model_path", C.c_char_p), ("keep_box", C.c_int32)]
+                ("hss_leaf_elems", C.c_int32), ("rank_model_path", C.c_char_p), ("keep_box", C.c_int32),
+                ("ldu", C.c_int32)]
 
 
 class GmresInfo(C.Structure):
@@ -272,18 +273,18 @@ class Handle:
 
 def factor(op, tree, tol, prec="fp32", seed=1508, stream=None, l0=32, p_os=10, max_attempts=8,
            rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True, hss_leaf_elems=4,
-           rank_model_path=None, keep_box=0):
+           rank_model_path=None, keep_box=0, ldu=2):
     """hss_factor: build the preconditioner of one operator (see include/hss.h)."""
     return factor_batched([op], [tree], tol, prec=prec, seed=seed, stream=stream, l0=l0, p_os=p_os,
                           max_attempts=max_attempts, rank_model=rank_model, kappa_h=kappa_h,
                           profile=profile, vals_dev=None if vals_dev is None else [vals_dev],
                           apply_graph=apply_graph, hss_leaf_elems=hss_leaf_elems,
-                          rank_model_path=rank_model_path, keep_box=keep_box)
+                          rank_model_path=rank_model_path, keep_box=keep_box, ldu=ldu)
 
 
 def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, p_os=10, max_attempts=8,
                    rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True, hss_leaf_elems=4,
-                   rank_model_path=None, keep_box=0):
+                   rank_model_path=None, keep_box=0, ldu=2):
     keep = _Keep()
     n = len(ops)
     A = (BlockOp * n)(*[_op_struct(op, keep, None if vals_dev is None else vals_dev[i])
@@ -301,6 +302,7 @@ def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, 
     o.apply_graph = 1 if apply_graph else 0
     o.hss_leaf_elems = int(hss_leaf_elems)
     o.keep_box = int(keep_box)
+    o.ldu = int(ldu)
     if rank_model_path is not None:
         o.rank_model_path = os.fsencode(rank_model_path)
         keep.items.append(o.rank_model_path)
@@ -399,11 +401,11 @@ def _scalar_code(t):
     return _SCALAR[str(t.dtype).replace("torch.", "")]
 
 
-def debug_gemm(As, Bs, Cs, alpha=1.0, beta=0.0, stream=None, bf16x3=False):
+def debug_gemm(As, Bs, Cs, alpha=1.0, beta=0.0, stream=None, bf16x3=False, big=False):
     """C_b = alpha A_b B_b + beta C_b in place (column-major views of CUDA tensors:
     pass tensors shaped [cols, rows] in row-major storage, i.e. X.T of the matrix).
     bf16x3: float32 or complex64 operands on the BF16 matrix cores (hi / lo split, three
-    products per real product)."""
+    products per real product). big: float32 operands on the 128 x 128-tile kernel."""
     L = lib()
     L.hss_debug_gemm.restype = C.c_int
     n = len(As)
@@ -414,6 +416,10 @@ def debug_gemm(As, Bs, Cs, alpha=1.0, beta=0.0, stream=None, bf16x3=False):
         if code not in (0, 2):
             raise ValueError("bf16x3 takes float32 or complex64 operands")
         code = 4 if code == 0 else 5
+    elif big:
+        if code != 0:
+            raise ValueError("big tiles take float32 operands")
+        code = 6
     M = I(*[c.shape[1] for c in Cs])
     N = I(*[c.shape[0] for c in Cs])
     K = I(*[a.shape[0] for a in As])

@@ -50,6 +50,31 @@ def test_batched_gemm(name):
         assert np.abs(got - R).max() <= tol * scale * max(1.0, np.abs(R).max()), (m, n, k)
 
 
+@pytest.mark.parametrize("name", ["float32"])
+def test_batched_gemm_big_tiles(name):
+    """The 128 x 128-tile MFMA kernel (four waves of 4 x 4 blocks of 16 x 16) on
+    ragged and multi-tile shapes, against numpy."""
+    npdt, tdt, tol = DT[name]
+    print(f"big-tile gemm {name}", flush=True)
+    rng = np.random.default_rng(17)
+    shapes = [(1, 1, 1), (70, 45, 33), (128, 128, 8), (129, 257, 9), (300, 129, 200), (520, 700, 333)]
+    As, Bs, Cs, ref = [], [], [], []
+    alpha, beta = (-1.0, 1.0)
+    for (m, n, k) in shapes:
+        A = _rand(rng, (m, k), npdt)
+        B = _rand(rng, (k, n), npdt)
+        Cm = _rand(rng, (m, n), npdt)
+        ref.append(alpha * (A.astype(np.complex128) @ B.astype(np.complex128)) + beta * Cm)
+        As.append(_dev(A, tdt))
+        Bs.append(_dev(B, tdt))
+        Cs.append(_dev(Cm, tdt))
+    hss.debug_gemm(As, Bs, Cs, alpha=alpha, beta=beta, big=True)
+    for (m, n, k), Cd, R in zip(shapes, Cs, ref):
+        got = Cd.cpu().numpy().T
+        scale = np.sqrt(k) * 10 + 1
+        assert np.abs(got - R).max() <= tol * scale * max(1.0, np.abs(R).max()), (m, n, k)
+
+
 def test_batched_gemm_bf16x3():
     """FP32 operands on BF16 matrix cores (hi / lo split, three products): about 16
     significant bits per product, i.e. far better than plain BF16 (~4e-3)."""

@@ -46,14 +46,17 @@ def _check_p_bound(h):
     assert h.query("tmax").max() <= 2.0
 
 
-@pytest.mark.parametrize("pde,p,prec", [("poisson", 1, "fp64"), ("helmholtz", 2, "fp64"),
-                                        ("poisson", 2, "fp32"), ("helmholtz", 2, "fp32")])
-def test_exact_factorization(pde, p, prec):
+@pytest.mark.parametrize("pde,p,prec,ldu", [("poisson", 1, "fp64", 1), ("helmholtz", 2, "fp64", 1),
+                                            ("poisson", 2, "fp32", 1), ("helmholtz", 2, "fp32", 1),
+                                            ("helmholtz", 2, "fp64", 0), ("helmholtz", 2, "fp32", 2)])
+def test_exact_factorization(pde, p, prec, ldu):
+    """ldu = 1 keeps every interior of more than 128 rows and the root in the block
+    LDU form, 0 as explicit inverses, 2 chooses per batch."""
     n = 12
     op = sipg.assemble(n, p, pde, kappa=14.0)
     tree = partition.build_tree(n, n, 16)
-    print(f"exact: {pde} p={p} {prec}", flush=True)
-    h = hss.factor(op, tree, 0.0, prec=prec)
+    print(f"exact: {pde} p={p} {prec} ldu={ldu}", flush=True)
+    h = hss.factor(op, tree, 0.0, prec=prec, ldu=ldu)
     rng = np.random.default_rng(0)
     b = rng.standard_normal(op.ndof) + (1j * rng.standard_normal(op.ndof) if op.is_complex else 0)
     x = h.apply(_t(b)).cpu().numpy()
@@ -62,19 +65,21 @@ def test_exact_factorization(pde, p, prec):
     cond = np.linalg.cond(D)
     eps = 1e-16 if prec == "fp64" else 6e-8
     assert np.linalg.norm(x - xr) <= 50 * eps * cond * np.linalg.norm(xr)
-    # p = 1: a 96-row root kept as an explicit inverse; p = 2: a 216-row root in
-    # the block LDU form (several blocks: 128 columns, or the tuning table's width)
+    # p = 1: a 96-row root, unblocked, so an explicit inverse; p = 2: a 216-row root
+    # in the block LDU form when forced (several blocks: 128 columns, or the tuning
+    # table's width), an explicit inverse otherwise (too little work saved)
     rb = h.query("root_block")[0]
-    assert rb == 0 if p == 1 else 0 < rb < 216
+    assert rb == 0 if (p == 1 or ldu != 1) else 0 < rb < 216
     if prec == "fp64":
         _, info = h.gmres(_t(b), tol=1e-10)
         assert info[0]["iters"] == 1 and info[0]["true_relres"] <= 1e-10
     h.close()
 
 
-def test_poisson16_fp64_matches_oracle_elementwise():
+@pytest.mark.parametrize("ldu", [2, 1])
+def test_poisson16_fp64_matches_oracle_elementwise(ldu):
     P = configs.make("poisson_p1_16")
-    h = hss.factor(P.op, P.tree, P.tol, prec="fp64", seed=P.seed)
+    h = hss.factor(P.op, P.tree, P.tol, prec="fp64", seed=P.seed, ldu=ldu)
     F = OracleFactor(P.op, P.tree, P.tol, seed=P.seed)
     heap = h.query("node_heap").astype(int)
     ranks = dict(zip(heap, h.query("ranks").astype(int)))
