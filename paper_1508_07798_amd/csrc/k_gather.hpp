@@ -84,6 +84,86 @@ __global__ __launch_bounds__(256) void gather_kernel(OpDev A, const GatherDesc<T
   }
 }
 
+// The same formation over 64 x 32 tiles: the sources of a tile's rows and columns
+// (child side and position in its B, global element and local dof) are decoded
+// once into LDS, and each thread, which keeps one row, looks up the element block
+// of its coupling entries once per run of columns of the same element. grid:
+// (tiles of the largest box, boxes).
+constexpr int GT_R = 64, GT_C = 32;
+template <class T, class TA, class TS>
+__global__ __launch_bounds__(256) void gather_tile_kernel(OpDev A, const GatherDesc<TS>* __restrict__ descs,
+                                                          T* const* __restrict__ Mout,
+                                                          T* const* __restrict__ Abi_out,
+                                                          T* const* __restrict__ S_out) {
+  const GatherDesc<TS> g = descs[blockIdx.y];
+  const int n = g.ni + g.nb;
+  const int trows = (n + GT_R - 1) / GT_R, tcols = (n + GT_C - 1) / GT_C;
+  if ((int)blockIdx.x >= trows * tcols) return;  // the whole workgroup
+  const int r0 = ((int)blockIdx.x % trows) * GT_R, c0 = ((int)blockIdx.x / trows) * GT_C;
+  __shared__ int s_side[GT_R + GT_C], s_pos[GT_R + GT_C], s_loc[GT_R + GT_C];
+  __shared__ int64_t s_el[GT_R + GT_C];
+  const int tid = threadIdx.x, q = A.q;
+  if (tid < GT_R + GT_C) {
+    // slots 0 .. GT_R - 1: rows r0 + tid; then columns c0 + (tid - GT_R); past the
+    // box's end a slot repeats its last index (never used)
+    const int i = tid < GT_R ? min(r0 + tid, n - 1) : min(c0 + tid - GT_R, n - 1);
+    const int64_t l = g.gidx[i] - g.dof_off;
+    s_el[tid] = g.el_off + l / q;
+    s_loc[tid] = (int)(l % q);
+    if (g.src) {
+      const int32_t sv = g.src[i];
+      s_side[tid] = sv >> 30;
+      s_pos[tid] = sv & ((1 << 30) - 1);
+    } else {
+      s_side[tid] = -1;
+      s_pos[tid] = 0;
+    }
+  }
+  __syncthreads();
+  const int rl = tid % GT_R, cg = tid / GT_R;
+  const int r = r0 + rl;
+  if (r >= n) return;
+  T* M = Mout[blockIdx.y];
+  T* Abi = Abi_out ? Abi_out[blockIdx.y] : nullptr;
+  T* S = S_out ? S_out[blockIdx.y] : nullptr;
+  const int side_r = s_side[rl], pos_r = s_pos[rl], loc_r = s_loc[rl];
+  const int64_t er = s_el[rl];
+  int64_t last_ec = -1;
+  int blk = -1;
+  for (int cc = cg; cc < GT_C; cc += 256 / GT_R) {
+    const int c = c0 + cc;
+    if (c >= n) break;
+    const int sl = GT_R + cc;
+    T v;
+    if (side_r >= 0 && side_r == s_side[sl]) {
+      const TS* st = g.st[side_r];
+      const TS sv = st[pos_r + (size_t)s_pos[sl] * g.nbc[side_r]];
+      if constexpr (sizeof(T) == sizeof(TS)) v = sv;
+      else v = narrow<T>(to_wide(sv));
+    } else {
+      const int64_t ec = s_el[sl];
+      if (ec != last_ec) {
+        last_ec = ec;
+        blk = -1;
+        for (int b = A.row_ptr[er]; b < A.row_ptr[er + 1]; ++b)
+          if (A.col_idx[b] == ec) {
+            blk = b;
+            break;
+          }
+      }
+      v = blk >= 0 ? narrow<T>(((const TA*)A.vals)[(size_t)blk * q * q + (size_t)s_loc[sl] * q + loc_r])
+                   : traits<T>::zero();
+    }
+    if (r < g.ni) {
+      M[r + (size_t)c * g.ni] = v;  // [A_ii | A_ib]
+    } else if (c < g.ni) {
+      Abi[(r - g.ni) + (size_t)c * g.nb] = v;
+    } else {
+      S[(r - g.ni) + (size_t)(c - g.ni) * g.nb] = v;
+    }
+  }
+}
+
 // Check of the operator's values: out[0] = bits of max |a| over the finite
 // entries, out[1] = bits of max |A(e, f) - A(f, e)^T| (the symmetry the method
 // assumes: V = U in the compression), out[2] = number of non-finite entries.
