@@ -1123,7 +1123,8 @@ template <class T> struct Engine : EngineBase {
         g.nbc[1] = n.leaf ? 0 : (int)P.nodes[n.child[1]].bdof.size();
         g.el_off = pr.el_off;
         g.dof_off = pr.dof_off;
-        maxe = std::max<int64_t>(maxe, (int64_t)(g.ni + g.nb) * (g.ni + g.nb));
+        const int nt = g.ni + g.nb;
+        maxe = std::max<int64_t>(maxe, (int64_t)cdiv(nt, GT_R) * cdiv(nt, GT_C));
       }
       auto* dgd = up(gd, tmp);
       auto* dM = up(Mp, tmp);
@@ -1137,7 +1138,8 @@ template <class T> struct Engine : EngineBase {
       }
       int id = prof.start(C_GATHER, 0, gby);
       fl();
-      gather_kernel<X, W, T><<<dim3(grid1(maxe, 512), (unsigned)nw), 256, 0, st>>>(op, dgd, dM, dA, dS);
+      gather_tile_kernel<X, W, T><<<dim3((unsigned)std::max<int64_t>(maxe, 1), (unsigned)nw), 256, 0, st>>>(op, dgd, dM,
+                                                                                                    dA, dS);
       prof.stop(id);
       check_launch("gather");
     }
@@ -1380,7 +1382,7 @@ template <class T> struct Engine : EngineBase {
         rt[p].R = persist.get<W>((size_t)rt[p].n * rt[p].n);
         rt[p].rowperm = persist.get<int>(rt[p].n);
         max_nr = std::max(max_nr, rt[p].n);
-        maxe = std::max<int64_t>(maxe, (int64_t)rt[p].n * rt[p].n);
+        maxe = std::max<int64_t>(maxe, (int64_t)cdiv(rt[p].n, GT_R) * cdiv(rt[p].n, GT_C));
       }
       int64_t* dg = up(gall, persist);
       int32_t* ds = up(sall, persist);
@@ -1409,7 +1411,8 @@ template <class T> struct Engine : EngineBase {
       for (int p = 0; p < nprob; ++p) rby += (double)rt[p].n * rt[p].n * (sizeof(W) + sizeof(T));
       int id = prof.start(C_ROOT, 0, rby);
       fl();
-      gather_kernel<W, W, T><<<dim3(grid1(maxe, 512), (unsigned)nprob), 256, 0, st>>>(op, dgd, dR, nullptr, nullptr);
+      gather_tile_kernel<W, W, T><<<dim3((unsigned)std::max<int64_t>(maxe, 1), (unsigned)nprob), 256, 0, st>>>(
+          op, dgd, dR, nullptr, nullptr);
       prof.stop(id);
       check_launch("root gather");
       std::vector<GjDesc<W>> gj;

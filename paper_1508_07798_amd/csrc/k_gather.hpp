@@ -32,63 +32,12 @@ template <class TS> struct GatherDesc {
   int64_t el_off, dof_off; // problem offsets
 };
 
-template <class TA> __device__ inline TA op_entry(const OpDev& A, int64_t el_off, int64_t dof_off,
-                                                  int64_t gr, int64_t gc) {
-  const int q = A.q;
-  const int64_t lr = gr - dof_off, lc = gc - dof_off;
-  const int64_t er = el_off + lr / q, ec = el_off + lc / q;
-  const int ir = (int)(lr % q), ic = (int)(lc % q);
-  for (int b = A.row_ptr[er]; b < A.row_ptr[er + 1]; ++b)
-    if (A.col_idx[b] == ec) return ((const TA*)A.vals)[(size_t)b * q * q + (size_t)ic * q + ir];
-  return traits<TA>::zero();
-}
-
-// grid: (chunks over (ni+nb)^2, boxes)
-template <class T, class TA, class TS>
-__global__ __launch_bounds__(256) void gather_kernel(OpDev A, const GatherDesc<TS>* __restrict__ descs,
-                                                     T* const* __restrict__ Mout,
-                                                     T* const* __restrict__ Abi_out,
-                                                     T* const* __restrict__ S_out) {
-  const GatherDesc<TS> g = descs[blockIdx.y];
-  const int n = g.ni + g.nb;
-  const int64_t tot = (int64_t)n * n;
-  T* M = Mout[blockIdx.y];
-  T* Abi = Abi_out ? Abi_out[blockIdx.y] : nullptr;
-  T* S = S_out ? S_out[blockIdx.y] : nullptr;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
-    const int r = (int)(e % n), c = (int)(e / n);
-    T v;
-    bool same = false;
-    if (g.src) {
-      const int32_t sr = g.src[r], sc = g.src[c];
-      const int side_r = sr >> 30, side_c = sc >> 30;
-      if (side_r == side_c) {
-        const int pr = sr & ((1 << 30) - 1), pc = sc & ((1 << 30) - 1);
-        const TS* st = g.st[side_r];
-        if constexpr (sizeof(T) == sizeof(TS)) v = st[pr + (size_t)pc * g.nbc[side_r]];
-        else v = narrow<T>(to_wide(st[pr + (size_t)pc * g.nbc[side_r]]));
-        same = true;
-      }
-    }
-    if (!same) {
-      TA a = op_entry<TA>(A, g.el_off, g.dof_off, g.gidx[r], g.gidx[c]);
-      v = narrow<T>(a);
-    }
-    if (r < g.ni) {
-      M[r + (size_t)c * g.ni] = v;  // [A_ii | A_ib]
-    } else if (c < g.ni) {
-      Abi[(r - g.ni) + (size_t)c * g.nb] = v;
-    } else {
-      S[(r - g.ni) + (size_t)(c - g.ni) * g.nb] = v;
-    }
-  }
-}
-
-// The same formation over 64 x 32 tiles: the sources of a tile's rows and columns
-// (child side and position in its B, global element and local dof) are decoded
-// once into LDS, and each thread, which keeps one row, looks up the element block
-// of its coupling entries once per run of columns of the same element. grid:
-// (tiles of the largest box, boxes).
+// One workgroup per 64 x 32 tile of a box's (n_i + n_b)^2 entries: the sources of
+// the tile's rows and columns (child side and position in its B, global element
+// and local dof) are decoded once into LDS, and each thread, which keeps one row,
+// looks up the element block of its operator entries once per run of columns of
+// the same element (entry (r, c) of block (e, f) sits at c q + r, column-major).
+// grid: (tiles of the largest box, boxes).
 constexpr int GT_R = 64, GT_C = 32;
 template <class T, class TA, class TS>
 __global__ __launch_bounds__(256) void gather_tile_kernel(OpDev A, const GatherDesc<TS>* __restrict__ descs,
