@@ -114,6 +114,55 @@ def make(name: str, *, n: int | None = None, p: int | None = None, seed_offset: 
                    restart=30, prec=prec, kappa=kappa, coef=coef, seed=seed)
 
 
+# Problem families of the paper's Section 4 studies, for the h/p sweeps and the
+# partition studies (all real, homogeneous Dirichlet data, FP64):
+#   poisson   -lap u = f                                   (Poisson study)
+#   cavity    -lap u - kappa^2 u = f, the soft cavity        (Helmholtz study)
+#   aniso     -u_xx - a0 u_yy + c0 u = f (equation (60) normalized by a11)
+#   contrast  -div(rho^-1 grad u) - kappa^2 u = f, rho = rho_d in the rectangular
+#             enclosure D = [0.125, 0.875] x [0.375, 0.5] of the partition
+#             figure, 1 elsewhere (per element, by its centroid)
+# kappa keeps `dpw` DG nodes per wavelength along an axis as n and p vary: the
+# stand-in for the paper's constant dispersion error.
+STUDY_TOL = {"poisson": 1e-3, "cavity": 1e-3, "aniso": 1e-3, "contrast": 1e-3}
+
+
+def contrast_coef(n: int, rho_d: float) -> np.ndarray:
+    """rho^-1 per element ([ey, ex]) with rho = rho_d in the enclosure D."""
+    xc = (np.arange(n) + 0.5) / n
+    inside = ((xc[None, :] > 0.125) & (xc[None, :] < 0.875) & (xc[:, None] > 0.375) & (xc[:, None] < 0.5))
+    return np.where(inside, 1.0 / rho_d, 1.0)
+
+
+def study(kind: str, n: int, p: int, *, scheme: str = "boxes", a0: float = 1e-6, c0: float = 1.0,
+          rho_d: float = 1e3, dpw: float = 8.0, leaf_elems: int = 16, seed_offset: int = 0,
+          tol: float | None = None) -> Problem:
+    """One problem of a Section 4 study family (see above), rhs N(0, 1), ID tol
+    STUDY_TOL (or ``tol``), GMRES(30) to 1e-8, FP64."""
+    if kind not in STUDY_TOL:
+        raise KeyError(kind)
+    seed = BASE_SEED + 10 + ["poisson", "cavity", "aniso", "contrast"].index(kind) + 1000 * seed_offset
+    rng = np.random.default_rng(seed)
+    coef = np.ones((n, n))
+    kappa = 0.0
+    if kind == "poisson":
+        op = sipg.assemble(n, p, "poisson")
+    elif kind == "cavity":
+        kappa = dofs_per_wavelength_kappa(n, p, dpw)
+        op = sipg.assemble(n, p, "poisson", reaction=-kappa * kappa)
+    elif kind == "aniso":
+        op = sipg.assemble(n, p, "poisson", aniso=(1.0, a0), reaction=c0)
+    else:
+        kappa = dofs_per_wavelength_kappa(n, p, dpw)
+        coef = contrast_coef(n, rho_d)
+        op = sipg.assemble(n, p, "poisson", coef=coef, reaction=-kappa * kappa)
+    tree = partition.build_tree(n, n, leaf_elems=leaf_elems, scheme=scheme)
+    b = rng.standard_normal((op.ndof, 1))
+    return Problem(name=f"{kind}_p{p}_{n}_{scheme}", op=op, tree=tree, rhs=b,
+                   tol=STUDY_TOL[kind] if tol is None else tol,
+                   gmres_tol=1e-8, restart=30, prec="fp64", kappa=kappa, coef=coef, seed=seed)
+
+
 def make_batch(count: int = 64, n_lo: int = 32, n_hi: int = 96, p: int = 2,
                nrhs: int = 4, seed_offset: int = 0) -> list[Problem]:
     """The batched Helmholtz workload: ``count`` problems of uneven size."""
