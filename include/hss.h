@@ -96,7 +96,8 @@ typedef struct {
   const float* rank_model; /* NULL: plain adaptive ID; else HSS_MLP_NPARAMS host
                               floats (W1,b1,W2,b2,W3,b3, row-major [out][in]) of
                               the rank predictor that presizes l per box as
-                              32 * ceil((1.5 k^ + p_os) / 32), k^ its prediction */
+                              32 * ceil((m k^ + p_os) / 32), k^ its prediction and
+                              m = model_margin                                    */
   double kappa_h;          /* wavenumber * element size, a rank-model feature    */
   void* hip_stream;        /* hipStream_t for all work (NULL: null stream)       */
   int32_t profile;         /* 0: off; 1: time every kernel class with HIP events on
@@ -118,6 +119,8 @@ typedef struct {
                               per block in each apply), 2 (default) the LDU form for
                               the batches where the work saved outweighs the added
                               launches                                            */
+  double model_margin;     /* samples per predicted rank, m above (0: the default,
+                              3; otherwise at least 1)                            */
 } hss_opts_t;
 
 typedef struct {

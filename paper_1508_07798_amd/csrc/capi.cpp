@@ -160,6 +160,7 @@ void hss_default_opts(hss_opts_t* o) {
   o->rank_model_path = nullptr;
   o->keep_box = 0;
   o->ldu = 2;
+  o->model_margin = 0.0;
 }
 
 const char* hss_last_error(void) { return g_err.c_str(); }
@@ -174,7 +175,8 @@ hss_status_t hss_factor_batched(int32_t nprob, const hss_block_op_t* A, const hs
     hss_default_opts(&opts);
     if (o) opts = *o;
     if (opts.p_os < 1 || opts.l0 < 1 || opts.max_attempts < 1 || opts.hss_leaf_elems < 0 || opts.keep_box < 0 ||
-        opts.ldu < 0 || opts.ldu > 2)
+        opts.ldu < 0 || opts.ldu > 2 || !(opts.model_margin == 0.0 || opts.model_margin >= 1.0) ||
+        !std::isfinite(opts.model_margin))
       return fail(HSS_EINVAL, "bad options");
     const int leaf = opts.hss_leaf_elems > 0 ? opts.hss_leaf_elems : 4;
     if (opts.prec != HSS_PREC_FP64 && opts.prec != HSS_PREC_FP32 && opts.prec != HSS_PREC_BF16)

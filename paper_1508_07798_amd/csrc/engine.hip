@@ -336,6 +336,11 @@ template <class T> struct Engine : EngineBase {
   static constexpr double kLduLaunchFlops = 5e9;
   static constexpr int kGjLookaheadAbove = 2048;
   int la_above = kGjLookaheadAbove;
+  // samples above the rank model's prediction: l = 32 ceil((margin k^ + p_os) / 32)
+  // with margin = hss_opts_t.model_margin (0: kModelMargin). The margin sets the
+  // first attempt's oversampling: on the p = 4 Helmholtz workload 3 gave better
+  // skeletons than 1.5, which halved the GMRES iterations at fewer judge retries
+  static constexpr double kModelMargin = 3.0;
   // 128 x 128 GEMM tiles for large real FP32 products (HSS_GEMM_BIG=0: off)
   static constexpr int kGemmBigMinTiles = 256;
   bool gemm_big_on = true;
@@ -1537,11 +1542,12 @@ template <class T> struct Engine : EngineBase {
       for (int i = 0; i < 64; ++i) z += w[576 + j * 64 + i] * h1[i];
       out += w[4736 + j] * std::tanh(z);
     }
-    // l = 32 ceil((1.5 k^ + p_os) / 32): room above the predicted rank keeps the
+    // l = 32 ceil((margin k^ + p_os) / 32): room above the predicted rank keeps the
     // a-posteriori estimate on the samples reliable (few judge retries), and l in
     // steps of 32 matches the sampling and CPQR kernels' tiles
     const double k = std::max(0.0, std::exp2((double)out) - 1.0);
-    const int want = (int)std::ceil(1.5 * k) + o.p_os;
+    const double margin = o.model_margin > 0 ? o.model_margin : kModelMargin;
+    const int want = (int)std::ceil(margin * k) + o.p_os;
     return std::max(32, 32 * ((want + 31) / 32));
   }
 

@@ -42,7 +42,7 @@ class Opts(C.Structure):
                 ("seed", C.c_uint64), ("rank_model", C.c_void_p), ("kappa_h", C.c_double),
                 ("hip_stream", C.c_void_p), ("profile", C.c_int32), ("apply_graph", C.c_int32),
                 ("hss_leaf_elems", C.c_int32), ("rank_model_path", C.c_char_p), ("keep_box", C.c_int32),
-                ("ldu", C.c_int32)]
+                ("ldu", C.c_int32), ("model_margin", C.c_double)]
 
 
 class GmresInfo(C.Structure):
@@ -273,18 +273,19 @@ class Handle:
 
 def factor(op, tree, tol, prec="fp32", seed=1508, stream=None, l0=32, p_os=10, max_attempts=8,
            rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True, hss_leaf_elems=4,
-           rank_model_path=None, keep_box=0, ldu=2):
+           rank_model_path=None, keep_box=0, ldu=2, model_margin=0.0):
     """hss_factor: build the preconditioner of one operator (see include/hss.h)."""
     return factor_batched([op], [tree], tol, prec=prec, seed=seed, stream=stream, l0=l0, p_os=p_os,
                           max_attempts=max_attempts, rank_model=rank_model, kappa_h=kappa_h,
                           profile=profile, vals_dev=None if vals_dev is None else [vals_dev],
                           apply_graph=apply_graph, hss_leaf_elems=hss_leaf_elems,
-                          rank_model_path=rank_model_path, keep_box=keep_box, ldu=ldu)
+                          rank_model_path=rank_model_path, keep_box=keep_box, ldu=ldu,
+                          model_margin=model_margin)
 
 
 def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, p_os=10, max_attempts=8,
                    rank_model=None, kappa_h=0.0, profile=False, vals_dev=None, apply_graph=True, hss_leaf_elems=4,
-                   rank_model_path=None, keep_box=0, ldu=2):
+                   rank_model_path=None, keep_box=0, ldu=2, model_margin=0.0):
     keep = _Keep()
     n = len(ops)
     A = (BlockOp * n)(*[_op_struct(op, keep, None if vals_dev is None else vals_dev[i])
@@ -303,6 +304,7 @@ def factor_batched(ops, trees, tol, prec="fp32", seed=1508, stream=None, l0=32, 
     o.hss_leaf_elems = int(hss_leaf_elems)
     o.keep_box = int(keep_box)
     o.ldu = int(ldu)
+    o.model_margin = float(model_margin)
     if rank_model_path is not None:
         o.rank_model_path = os.fsencode(rank_model_path)
         keep.items.append(o.rank_model_path)

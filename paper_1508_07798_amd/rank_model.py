@@ -1,9 +1,10 @@
 """Rank-predictor MLP: training data from factorizations, training on the GPU.
 
 The library sizes each separator's randomized sampling from a predicted ID rank
-k^ as l = 32 ceil((1.5 k^ + p_os) / 32) (hss_opts_t.rank_model): samples well
+k^ as l = 32 ceil((m k^ + p_os) / 32), m = 3 by default (hss_opts_t.rank_model,
+model_margin): samples well
 above the rank keep the a-posteriori error estimate reliable, so few boxes need
-a second round. The paper chooses an
+a second round, and give better skeletons, so fewer GMRES iterations. The paper chooses an
 anticipated rank from observed rank laws (Section 4); here a small network
 8 -> 64 -> 64 -> 1 (tanh, tanh, linear) learns log2(1 + k) from the ranks the
 adaptive ID itself produced on other problems. The judge and the rank-growth

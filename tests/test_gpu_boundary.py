@@ -156,3 +156,6 @@ def test_kept_schur_complement_matches_oracle(name, prec, box, tol_s):
     with pytest.raises(hss.HssError) as ex:
         hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, ldu=3)
     assert ex.value.status == hss.HSS_EINVAL
+    with pytest.raises(hss.HssError) as ex:
+        hss.factor(P.op, P.tree, P.tol, prec=prec, seed=P.seed, model_margin=0.5)
+    assert ex.value.status == hss.HSS_EINVAL
