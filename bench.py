@@ -27,7 +27,7 @@ PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "mfma_bf16": 2500.0, "alu_fp32": 
         "hbm": 8000.0}
 # bound of each kernel class and whether its algorithmic work is counted in flops or bytes
 BOUND = {"gather": "hbm", "gj_panel": "alu", "gj_rows": "hbm", "gj_update": "mfma", "schur_gemm": "mfma",
-         "symm": "hbm", "omega": "hbm", "sample_gemm": "mfma", "sample": "alu", "id": "alu", "utall": "alu",
+         "symm": "hbm", "omega": "hbm", "sample_gemm": "mfma", "sample": "mfma", "id": "alu", "utall": "alu",
          "expand": "mfma", "judge": "hbm", "apply": "hbm", "spmv": "hbm", "root": "hbm", "gj_perm": "hbm",
          "gj_panel_wide": "alu", "gj_rows_wide": "hbm", "gj_update_wide": "mfma"}
 # the *_wide classes: Gauss-Jordan work that a single-precision factorization does in

@@ -18,6 +18,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "k_gemm.hpp"
 
 namespace hss {
 
@@ -161,20 +162,28 @@ struct HTile {
 
 // Samples of one HSS height, one workgroup per (HSS node, 64 x 64 output tile):
 // candidates, then Z = Y(R, :) - S(R, tau) Omega(tau, :) written transposed
-// (Zt, l x m). 4 x 4 outputs per thread; the product over tau runs in slabs of
-// 16 staged through LDS. Tiles beyond the candidate count exit.
+// (Zt, l x m). The product over tau runs in slabs of 16 staged through LDS as
+// split real / imaginary planes and is taken on the matrix cores as in the GEMM
+// kernel: four waves, each a 32 x 32 quadrant of 2 x 2 MFMA 16x16 blocks
+// (complex64 with three real products per complex product, complex128 with four).
+// Tiles beyond the candidate count exit.
 template <class T, int MCAP>
 __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restrict__ bx,
                                                      const HssDesc<T>* __restrict__ hs,
                                                      const HTile* __restrict__ tiles) {
-  constexpr int KC = 16;
+  using R = typename traits<T>::real;
+  using Acc = typename mfma_acc<R>::type;
+  constexpr bool CX = traits<T>::cplx;
+  constexpr bool G3 = CX && std::is_same<R, float>::value;
+  constexpr int NP = CX ? (G3 ? 3 : 2) : 1;
+  constexpr int KC = 16, LD = 64 + 4;
   const HTile tl = tiles[blockIdx.x];
   const HssDesc<T> h = hs[tl.hnode];
   const CompBox<T> b = bx[h.box];
   __shared__ int s_cand[MCAP];
   __shared__ int s_m;
-  __shared__ T Sg[64][KC + 1];
-  __shared__ T Og[KC][65];
+  __shared__ R Sg[NP][KC][LD];  // S(R, tau) slab: [plane][k][row]
+  __shared__ R Og[NP][KC][LD];  // Omega(tau, :) slab: [plane][k][col]
   const int tid = threadIdx.x;
   if (h.left < 0) {
     for (int i = tid; i < h.hi - h.lo; i += 256) s_cand[i] = h.lo + i;
@@ -193,12 +202,13 @@ __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restric
   const int l = b.l, n = b.n;
   const int r0 = tl.r0, c0 = tl.c0;
   if (r0 >= m) return;
-  const int tx = tid % 16, ty = tid / 16;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[a][q] = traits<T>::zero();
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  Acc acc[NP][2][2];
+  for (int p = 0; p < NP; ++p)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) acc[p][i][j] = Acc{0, 0, 0, 0};
   // slab j0 of S(R, tau) and Omega(tau, :) in registers (4 + 4 values per thread),
   // prefetched while the previous slab is consumed from LDS
   T sreg[4], oreg[4];
@@ -220,44 +230,89 @@ __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restric
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = tid + 256 * u;
-      Sg[e % 64][e / 64] = sreg[u];
-      Og[e % KC][e / KC] = oreg[u];
+      const R sr = traits<T>::re(sreg[u]), si = traits<T>::im(sreg[u]);
+      const R orr = traits<T>::re(oreg[u]), oi = traits<T>::im(oreg[u]);
+      Sg[0][e / 64][e % 64] = sr;
+      Og[0][e % KC][e / KC] = orr;
+      if constexpr (CX) {
+        Sg[1][e / 64][e % 64] = si;
+        Og[1][e % KC][e / KC] = oi;
+      }
+      if constexpr (G3) {
+        Sg[2][e / 64][e % 64] = sr + si;
+        Og[2][e % KC][e / KC] = orr + oi;
+      }
     }
     __syncthreads();
     if (j0 + KC < h.hi) load(j0 + KC);
-#pragma unroll 4
-    for (int kk = 0; kk < KC; ++kk) {
-      T sv[4], ov[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) sv[a] = Sg[ty * 4 + a][kk];
+    for (int ks = 0; ks < KC; ks += 4) {
+      const int kk = ks + lk;
+      R a[NP][2], bb[NP][2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) ov[q] = Og[kk][tx * 4 + q];
+      for (int p = 0; p < NP; ++p) {
+        a[p][0] = Sg[p][kk][wm + li];
+        a[p][1] = Sg[p][kk][wm + 16 + li];
+        bb[p][0] = Og[p][kk][wn + li];
+        bb[p][1] = Og[p][kk][wn + 16 + li];
+      }
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[a][q] = acc[a][q] + sc_mul(sv[a], ov[q]);
+        for (int j = 0; j < 2; ++j) {
+          if constexpr (G3) {
+            acc[0][i][j] = mfma_acc<R>::mac(a[0][i], bb[0][j], acc[0][i][j]);
+            acc[1][i][j] = mfma_acc<R>::mac(a[1][i], bb[1][j], acc[1][i][j]);
+            acc[2][i][j] = mfma_acc<R>::mac(a[2][i], bb[2][j], acc[2][i][j]);
+          } else if constexpr (CX) {
+            acc[0][i][j] = mfma_acc<R>::mac(a[0][i], bb[0][j], acc[0][i][j]);
+            acc[0][i][j] = mfma_acc<R>::mac(-a[1][i], bb[1][j], acc[0][i][j]);
+            acc[1][i][j] = mfma_acc<R>::mac(a[0][i], bb[1][j], acc[1][i][j]);
+            acc[1][i][j] = mfma_acc<R>::mac(a[1][i], bb[0][j], acc[1][i][j]);
+          } else {
+            acc[0][i][j] = mfma_acc<R>::mac(a[0][i], bb[0][j], acc[0][i][j]);
+          }
+        }
     }
   }
-  // Y first for all 16 outputs, then the stores (a store the compiler cannot
-  // separate from the next load would serialize the read-store pairs)
-  T yv[4][4];
-  static_for<0, 4>([&](auto aa) {
-    constexpr int a = decltype(aa)::value;
-    const int r = r0 + ty * 4 + a;
-    const int row = s_cand[r < m ? r : 0];
-    static_for<0, 4>([&](auto qq) {
-      constexpr int q = decltype(qq)::value;
-      const int c = c0 + tx * 4 + q;
-      yv[a][q] = (r < m && c < l) ? b.Y[row + (size_t)c * n] : traits<T>::zero();
+  // lane holds column li and four rows of each 16x16 block: Y first for all 16
+  // outputs, then the stores (a store the compiler cannot separate from the next
+  // load would serialize the read-store pairs)
+  T yv[2][2][4];
+  static_for<0, 2>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    static_for<0, 2>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      const int c = c0 + wn + 16 * j + li;
+      static_for<0, 4>([&](auto vv) {
+        constexpr int v = decltype(vv)::value;
+        const int r = r0 + wm + 16 * i + mfma_acc<R>::row(lk, v);
+        const int row = s_cand[r < m ? r : 0];
+        yv[i][j][v] = (r < m && c < l) ? b.Y[row + (size_t)c * n] : traits<T>::zero();
+      });
     });
   });
-  static_for<0, 4>([&](auto aa) {
-    constexpr int a = decltype(aa)::value;
-    const int r = r0 + ty * 4 + a;
-    static_for<0, 4>([&](auto qq) {
-      constexpr int q = decltype(qq)::value;
-      const int c = c0 + tx * 4 + q;
-      if (r < m && c < l) h.Zt[c + (size_t)r * l] = yv[a][q] - acc[a][q];
+  static_for<0, 2>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    static_for<0, 2>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      const int c = c0 + wn + 16 * j + li;
+      static_for<0, 4>([&](auto vv) {
+        constexpr int v = decltype(vv)::value;
+        const int r = r0 + wm + 16 * i + mfma_acc<R>::row(lk, v);
+        if (r < m && c < l) {
+          T val;
+          if constexpr (G3) {
+            const R t0 = acc[0][i][j][v], t1 = acc[1][i][j][v];
+            val = traits<T>::mk(t0 - t1, acc[2][i][j][v] - t0 - t1);
+          } else if constexpr (CX) {
+            val = traits<T>::mk(acc[0][i][j][v], acc[1][i][j][v]);
+          } else {
+            val = acc[0][i][j][v];
+          }
+          h.Zt[c + (size_t)r * l] = yv[i][j][v] - val;
+        }
+      });
     });
   });
   if (tid == 0 && r0 == 0 && c0 == 0) *h.k = m;  // provisional: number of candidates (read by cpqr)
