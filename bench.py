@@ -190,6 +190,8 @@ def main():
                     help="spin kernels around the timed steps, to cut a kernel trace to them")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS),
                     help="measured workload (default: the largest configuration, p=4 Helmholtz on 256x256)")
+    ap.add_argument("--mixed", default=None, choices=("fp32", "bf16"),
+                    help="precision of the mixed form's Schur products (default: the workload's)")
     ap.add_argument("--oracle-sample-n", type=int, default=16,
                     help="grid of the smaller same-family problem the oracle is timed on when the "
                          "workload itself is too large for the host")
@@ -206,7 +208,7 @@ def main():
     from workloads import configs
 
     W = WORKLOADS[args.workload]
-    MIX = W["mixed"]
+    MIX = args.mixed or W["mixed"]
     def note(msg):
         print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -387,7 +389,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": W["dtype"],
+        "dtype": W["dtype"] if MIX == W["mixed"] else f"{W['dtype']} ({MIX} Schur products)",
         "data": "synthetic",
         "config": {"workload": W["desc"], "global_batch": 1, "parallelism": "single GPU"},
         "fp64_ms_per_step": None if ms64 is None else round(ms64, 3),
