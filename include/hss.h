@@ -189,8 +189,10 @@ hss_status_t gmres_solve(hss_handle_t h, int32_t nrhs, const void* b, void* x, i
  * root, and the Schur products),
  * "bytes_apply", "bytes_spmv", "time_factor_ms", "host_wait_ms"
  * (time the factorization spent waiting for the device at its sync points),
- * "root_block" (block width of the roots' block LDU form; 0: the roots, of at
- * most 128 rows, are stored as explicit inverses),
+ * "root_block" (block width of the roots' block LDU form; 0: explicit inverses),
+ * "compress_host_ms" (4 values: host time of the compression attempts spent
+ * building and uploading their lists, launching, waiting for the judge, and
+ * deciding the next attempt),
  * "phase_ms" (8 values: host wall time of operator upload, features, gather,
  * Gauss-Jordan, Schur GEMM, compression, root, apply set-up),
  * "prof.<class>.ms|launches|flops|bytes" (HIP-event time, launch count and

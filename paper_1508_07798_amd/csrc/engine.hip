@@ -397,6 +397,9 @@ template <class T> struct Engine : EngineBase {
   // algorithmic work of the compression (all attempts), real flops
   double alg_sample = 0, alg_cpqr = 0;
   double phase_ms[8] = {};
+  // host time of the compression attempts: building and uploading the lists,
+  // launching, waiting for the judge, deciding the next attempt
+  double compress_host_ms[4] = {};
   std::vector<float> feat_v;
 
   // apply
@@ -1255,6 +1258,7 @@ template <class T> struct Engine : EngineBase {
     // host wall time per phase: 0 operator and index upload, 1 features, 2 gather,
     // 3 Gauss-Jordan, 4 Schur GEMM, 5 compression, 6 root, 7 apply set-up
     std::fill(std::begin(phase_ms), std::end(phase_ms), 0.0);
+    std::fill(std::begin(compress_host_ms), std::end(compress_host_ms), 0.0);
     auto tl = t0;
     auto lap = [&](int k) {
       const auto now = std::chrono::high_resolution_clock::now();
@@ -1631,7 +1635,12 @@ template <class T> struct Engine : EngineBase {
     const double* h_nrm = d2h_pinned(d_nrm, nb_boxes);
     bool have_nrm = false;
     std::vector<int> fallback_boxes;
+    using hclock = std::chrono::high_resolution_clock;
+    auto ms_since = [](hclock::time_point t) {
+      return std::chrono::duration<double, std::milli>(hclock::now() - t).count();
+    };
     while (!todo.empty()) {
+      auto t_att = hclock::now();
       Arena at;
       at.st = st;
       const int na = (int)todo.size();
@@ -1775,6 +1784,8 @@ template <class T> struct Engine : EngineBase {
         oby += (double)b.n * b.l * sizeof(T);
         jby += 2.0 * b.n * b.n * sizeof(T);
       }
+      compress_host_ms[0] += ms_since(t_att);
+      t_att = hclock::now();
       {
         int id = prof.start(C_OMEGA, 0, oby);
         fl();
@@ -1830,7 +1841,11 @@ template <class T> struct Engine : EngineBase {
       const double* h_err = d2h_pinned(d_err, na);
       const int* h_flh = d2h_pinned(d_flags, 3 * na);
       const int* h_k = d2h_pinned(d_kall, nhs_all);
+      compress_host_ms[1] += ms_since(t_att);
+      t_att = hclock::now();
       sync();
+      compress_host_ms[2] += ms_since(t_att);
+      t_att = hclock::now();
       // algorithmic work of this attempt from the ranks the IDs chose (real flops;
       // a complex multiply-add counts 8): samples Z of every HSS node, the truncated
       // Householder QR and T = R11^-1 R12, the tall bases, and the expansion
@@ -1909,6 +1924,7 @@ template <class T> struct Engine : EngineBase {
         }
       }
       todo.swap(next);
+      compress_host_ms[3] += ms_since(t_att);
     }
     for (int i : fallback_boxes) copy_boxes.push_back(i), ++fallbacks, err_v[wv[i]] = 0.0;
     if (!copy_boxes.empty()) {
@@ -2393,6 +2409,8 @@ template <class T> struct Engine : EngineBase {
     };
     if (key == "kept_n") out = {(double)kept_n_};
     else if (key == "root_block") out = {(double)root_wb_};
+    else if (key == "compress_host_ms")
+      out = {compress_host_ms[0], compress_host_ms[1], compress_host_ms[2], compress_host_ms[3]};
     else if (key == "kept_S" || key == "kept_St") {
       const size_t ne = (size_t)kept_n_ * kept_n_;
       std::vector<T> h(ne);
