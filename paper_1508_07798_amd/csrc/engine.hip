@@ -319,23 +319,26 @@ template <class T> struct Engine : EngineBase {
   // above which it is used
   static constexpr int kGjBlock = 128;
   static constexpr int kGjBlockMin = 128;
-  // boxes above this many rows take 256-column blocks: the depth-256 block products
-  // run about 15% faster than depth 128 (complex128, measured), and the extra work
-  // on the block copy is a few percent at these sizes
+  // width for boxes above kGjBlockWideAbove rows (HSS_GJ_BLOCK_WIDE overrides): with
+  // the complex128 panels on complex64 boxes and the lookahead, 128 measured as fast
+  // as 192 and 1% faster than 256 on the p = 4 Helmholtz workload
   static constexpr int kGjBlockWideAbove = 2048;
-  // complex64 boxes above kGjWidenAbove rows: complex128 panels on the block copy
-  // (else the whole box is eliminated in complex128)
+  static constexpr int kGjBlockWide = 128;
+  int block_wide = kGjBlockWide;
+  // complex64 boxes above kGjWidenAbove rows take complex128 panels on the block copy
+  // (kGjMixedPanels; else the whole box is widened and eliminated in complex128)
+  static constexpr int kGjWidenAbove = 2048;
   static constexpr bool kGjMixedPanels = true;
   // blocked Gauss-Jordan: the next block's panel sweep overlaps the block product
   // for batches whose largest box has more than la_above rows (HSS_GJ_LOOKAHEAD_ABOVE
   // overrides the default)
   static constexpr bool kGjLookahead = true;
+  static constexpr int kGjLookaheadAbove = 2048;
+  int la_above = kGjLookaheadAbove;
   // blocked interior boxes and roots in the block LDU form (hss_opts_t.ldu; mode 2
   // of gauss_jordan prices one extra GEMV launch per solve iteration as 5 us at 50
   // TFLOP/s over 20 iterations)
   static constexpr double kLduLaunchFlops = 5e9;
-  static constexpr int kGjLookaheadAbove = 2048;
-  int la_above = kGjLookaheadAbove;
   // samples above the rank model's prediction: l = 32 ceil((margin k^ + p_os) / 32)
   // with margin = hss_opts_t.model_margin (0: kModelMargin). The margin sets the
   // first attempt's oversampling: on the p = 4 Helmholtz workload 3 gave better
@@ -344,9 +347,6 @@ template <class T> struct Engine : EngineBase {
   // 128 x 128 GEMM tiles for large real FP32 products (HSS_GEMM_BIG=0: off)
   static constexpr int kGemmBigMinTiles = 256;
   bool gemm_big_on = true;
-  static constexpr int kGjBlockWide = 256;
-  // complex64 boxes above this many interior rows are eliminated in complex128
-  static constexpr int kGjWidenAbove = 2048;
   // largest sample count of the randomized ID (a box whose ID needs more rows keeps
   // its dense complement once its attempts are spent)
   static constexpr int kLcapMax = 512;
@@ -491,6 +491,8 @@ template <class T> struct Engine : EngineBase {
     prof.st = st;
     if (const char* e = std::getenv("HSS_GJ_LOOKAHEAD_ABOVE")) la_above = std::atoi(e);
     if (const char* e = std::getenv("HSS_GEMM_BIG")) gemm_big_on = std::atoi(e) != 0;
+    if (const char* e = std::getenv("HSS_GJ_BLOCK_WIDE"))
+      block_wide = std::max(16, std::min(GJ_BLOCK_MAX, std::atoi(e) / 16 * 16));
     int dev = 0;
     HIP_CHECK(hipGetDevice(&dev));
     int v = 0;
@@ -870,7 +872,7 @@ template <class T> struct Engine : EngineBase {
     if (c.tourn) c.cand = ar.get<int>(ds.size() * (size_t)c.nch * nb);
     int wo = block > 0 ? std::min(block, GJ_BLOCK_MAX)
                        : c.block >= 0 ? std::min(c.block, GJ_BLOCK_MAX)
-                       : (nmax > kGjBlockWideAbove ? kGjBlockWide : nmax > kGjBlockMin ? kGjBlock : 0);
+                       : (nmax > kGjBlockWideAbove ? block_wide : nmax > kGjBlockMin ? kGjBlock : 0);
     if (wo >= nmax) wo = 0;
     if (mixed && !wo) throw Error(HSS_EDEVICE, "panels in another precision need the blocked form");
     bool ldu = wo > 0 && ldu_mode == 1;
