@@ -816,19 +816,35 @@ __global__ __launch_bounds__(NT) void gj_tourn_final_kernel(const GjDesc<T>* __r
   const int w = min(nb, g.n - j0);
   const int base = g.poff + j0;
   __shared__ int s_cl[RPT * NT];  // the valid candidates, relative to base
-  __shared__ int s_m;
+  __shared__ int s_wn[NT / 64];
   __shared__ int s_pphys[NB];
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    int m = 0;
-    for (int i = 0; i < nch * NB; ++i) {
-      const int v = cand[(size_t)blockIdx.x * nch * NB + i];
-      if (v >= 0 && m < RPT * NT) s_cl[m++] = v;
-    }
-    s_m = m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // stable compaction of the valid candidates (chunk order, then local pivot
+  // order), NT entries per round: the position of an entry is the number of valid
+  // entries before it (ballots within a wave, wave counts through LDS)
+  const int nc = nch * NB;
+  const int* cb = cand + (size_t)blockIdx.x * nc;
+  int m = 0;
+  for (int c0 = 0; c0 < nc; c0 += NT) {
+    const int i = c0 + tid;
+    const int v = i < nc ? cb[i] : -1;
+    const bool ok = v >= 0;
+    const unsigned long long mask = __ballot(ok);
+    if (lane == 0) s_wn[wave] = __popcll(mask);
+    __syncthreads();
+    int before = m + __popcll(mask & ((1ull << lane) - 1));
+    int total = 0;
+    static_for<0, NT / 64>([&](auto ww) {
+      constexpr int q = decltype(ww)::value;
+      const int c = s_wn[q];
+      if (q < wave) before += c;
+      total += c;
+    });
+    if (ok && before < RPT * NT) s_cl[before] = v;
+    m += total;
+    __syncthreads();
   }
-  __syncthreads();
-  const int m = s_m;
+  m = min(m, RPT * NT);
   rot_search<T, NB, RPT, NT>(g, j0, w, m, [&](int r) { return base + s_cl[r]; }, s_pphys, g.flag);
   __syncthreads();
   const int p = tid < w ? s_cl[s_pphys[tid]] : 0;
