@@ -193,7 +193,8 @@ hss_status_t gmres_solve(hss_handle_t h, int32_t nrhs, const void* b, void* x, i
  * "compress_host_ms" (4 values: host time of the compression attempts spent
  * building and uploading their lists, launching, waiting for the judge, and
  * deciding the next attempt),
- * "phase_ms" (8 values: host wall time of operator upload, features, gather,
+ * "phase_ms" (8 values: host wall time of operator upload, features and the
+ * rank model's inference (one device launch for all boxes), gather,
  * Gauss-Jordan, Schur GEMM, compression, root, apply set-up),
  * "prof.<class>.ms|launches|flops|bytes" (HIP-event time, launch count and
  * algorithmic work of the timed launches) for the classes, in bit order:

@@ -303,6 +303,8 @@ template <class T> struct Flop {
 };
 
 // ------------------------------------------------------------------ engine
+void mlp_forward(const float* w, const float* x, int n, float* y, hipStream_t st);  // mlp.hip
+
 template <class T> struct Engine : EngineBase {
   using W = typename traits<T>::wide;
   static constexpr bool CX = traits<T>::cplx;
@@ -1330,6 +1332,7 @@ template <class T> struct Engine : EngineBase {
     lap(0);
     // features need the diagonal-block norms: computed on the host copy if available
     compute_features(A);
+    predict_ranks();
     lap(1);
 
     std::vector<Arena> wave_st(P.waves.size());
@@ -1531,23 +1534,32 @@ template <class T> struct Engine : EngineBase {
     }
   }
 
-  // sample count per box from the rank model (host evaluation of the same network
-  // the GPU trains; tiny), or l0 without a model
+  // the rank model's output log2(1 + k^) for every box, from one launch of the
+  // device inference kernel (the network the GPU trains) before the first wave
+  std::vector<float> pred_v;
+  void predict_ranks() {
+    pred_v.clear();
+    if (!o.rank_model) return;
+    const int nn = (int)P.nodes.size();
+    if (nn == 0) return;
+    Arena t;
+    t.st = st;
+    const std::vector<float> wts(o.rank_model, o.rank_model + HSS_MLP_NPARAMS);
+    const float* dw = up(wts, t);
+    const float* dx = up(feat_v, t);
+    float* dy = t.get<float>((size_t)nn);
+    fl();
+    mlp_forward(dw, dx, nn, dy, st);
+    check_launch("mlp_forward");
+    const float* h = d2h_pinned(dy, (size_t)nn);
+    sync();
+    pred_v.assign(h, h + nn);
+    drop(t);
+  }
+  // sample count per box from the rank model's prediction, or l0 without a model
   int predicted_l(int g) const {
     if (!o.rank_model) return o.l0;
-    const float* w = o.rank_model;
-    const float* x = &feat_v[(size_t)g * 8];
-    float h1[64], out = w[4800];
-    for (int j = 0; j < 64; ++j) {
-      float z = w[512 + j];
-      for (int i = 0; i < 8; ++i) z += w[j * 8 + i] * x[i];
-      h1[j] = std::tanh(z);
-    }
-    for (int j = 0; j < 64; ++j) {
-      float z = w[4672 + j];
-      for (int i = 0; i < 64; ++i) z += w[576 + j * 64 + i] * h1[i];
-      out += w[4736 + j] * std::tanh(z);
-    }
+    const float out = pred_v[(size_t)g];
     // l = 32 ceil((margin k^ + p_os) / 32): room above the predicted rank keeps the
     // a-posteriori estimate on the samples reliable (few judge retries), and l in
     // steps of 32 matches the sampling and CPQR kernels' tiles
