@@ -14,23 +14,25 @@
 
 namespace hss {
 
-// Panel shapes held in registers: 16 columns (8 for complex double, whose values
-// take four registers each), up to four rows per thread on 128, 256 or 512
-// threads, and for single precision up to eight rows per thread. The pivot search
-// runs in the matrix's own precision.
+// Panel shapes held in registers: 16 columns, up to four rows per thread on 128,
+// 256 or 512 threads, and for single precision up to eight rows per thread. Complex
+// double values take four registers each: 16 columns up to 1024 rows (two rows per
+// thread on 512 threads), 8 columns above, where 16 would spill or leave one wave
+// per SIMD. The pivot search runs in the matrix's own precision.
 template <class X>
 bool panel_rot_config(int rows, PanelShape& s) {
-  const int nb = std::is_same<X, cd>::value ? 8 : 16;
+  const bool zd = std::is_same<X, cd>::value;
+  const int nb = zd && rows > 1024 ? 8 : 16;
   if (rows <= 128) {
     s = {nb, 1, 128};
     return true;
   }
-  if (rows <= 256 * 4) {
+  if (rows <= 256 * (zd ? 2 : 4)) {
     s = {nb, (rows + 255) / 256, 256};
     return true;
   }
   if (rows <= 512 * 4) {
-    s = {nb, (rows + 511) / 512, 512};
+    s = {nb, zd && rows <= 1024 ? 2 : (rows + 511) / 512, 512};
     return true;
   }
   if (std::is_same<X, float>::value && rows <= 512 * 8) {
@@ -54,6 +56,8 @@ bool panel_rot_variant(const GjDesc<X>* dd, int nn, int j0, int nb, const PanelS
     HSS_ROT(8, 1, 128)
     HSS_ROT(8, 1, 256) HSS_ROT(8, 2, 256) HSS_ROT(8, 3, 256) HSS_ROT(8, 4, 256)
     HSS_ROT(8, 3, 512) HSS_ROT(8, 4, 512)
+    HSS_ROT(16, 1, 128) HSS_ROT(16, 1, 256) HSS_ROT(16, 2, 256) HSS_ROT(16, 3, 256) HSS_ROT(16, 4, 256)
+    HSS_ROT(16, 5, 256) HSS_ROT(16, 2, 512)
   } else {
     HSS_ROT(16, 1, 128)
     HSS_ROT(16, 1, 256) HSS_ROT(16, 2, 256) HSS_ROT(16, 3, 256) HSS_ROT(16, 4, 256)

@@ -132,7 +132,7 @@ GJ_CASES += [("float64", 0, ((600, 70), (530, 0), (40, 9))), ("complex64", 0, ((
              ("float32", 100, ((450, 30), (129, 1))),
              # tall double panels (beyond the register-resident kernel)
              ("float64", 0, ((2600, 10), (3900, 0))),
-             # complex double at root sizes (8-column panels, 256 and 512 threads)
+             # complex double at root sizes (8-column panels at 1,152 rows, 16 columns at 900)
              ("complex128", 0, ((1152, 20), (900, 0))),
              ("float32", 0, ((2000, 5), (1030, 3)))]
 
