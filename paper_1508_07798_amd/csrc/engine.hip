@@ -352,6 +352,8 @@ template <class T> struct Engine : EngineBase {
   // largest sample count of the randomized ID (a box whose ID needs more rows keeps
   // its dense complement once its attempts are spent)
   static constexpr int kLcapMax = 512;
+  // CPQR launches of at most this many nodes (one per compute unit) run wide workgroups
+  static constexpr int kCpqrWideMaxNodes = 256;
   int* d_sing_ = nullptr;  // per box (then per root): 1 if a pivot was exactly zero
   double tol = 0;
   Prof prof;
@@ -506,10 +508,12 @@ template <class T> struct Engine : EngineBase {
       if (pr.q != q) throw Error(HSS_EINVAL, "all problems of a batch must share q");
     ntot = P.ndof_total;
     if (lds_max > 65536) {
-      HIP_CHECK(hipFuncSetAttribute((const void*)cpqr_kernel<T, true, 8, 8, 512, 64>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
-      HIP_CHECK(hipFuncSetAttribute((const void*)cpqr_kernel<T, true, 16, 16, 512, 256>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
+      constexpr int NTW = sizeof(T) >= 16 ? 512 : 1024;
+      for (const void* f : {(const void*)cpqr_kernel<T, true, 8, 8, 512, 64>,
+                            (const void*)cpqr_kernel<T, true, 16, 16, 512, 256>,
+                            (const void*)cpqr_kernel<T, true, 8, 8, 512, 64, NTW>,
+                            (const void*)cpqr_kernel<T, true, 16, 16, 512, 256, NTW>})
+        HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
       for (const void* f : {(const void*)gj_panel_kernel<T, true, 16>, (const void*)gj_panel_kernel<T, true, 32>,
                             (const void*)gj_panel_kernel<W, true, 16>, (const void*)gj_panel_kernel<W, true, 32>})
         HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - kPanelStaticLds));
@@ -1576,16 +1580,29 @@ template <class T> struct Engine : EngineBase {
     const size_t cap = (size_t)(lds_max > 65536 ? 65536 : 32768);
     return lmax <= 256 && zmax <= 512 && (size_t)lmax * zmax * sizeof(T) <= cap;
   }
-  // the CPQR variant for sample counts up to lmax and candidate counts up to zmax
+  // the CPQR variant for sample counts up to lmax and candidate counts up to zmax.
+  // A launch of at most one node per compute unit takes wide workgroups (1,024
+  // threads; 512 for 16-byte scalars, whose reflector rows would spill at 1,024):
+  // every step's column updates then take a quarter (half) of the passes. The
+  // result does not depend on the width: each column is still updated and
+  // reduced by one group of GL lanes, and every wave takes the same pivots.
+  template <bool LDS_, int GL_, int RPL_, int MCAP_, int KCAP_>
+  void cpqr_go(const CompBox<T>* dbx, const HssDesc<T>* dhs, const int* dl, unsigned g, size_t shm, int p_os) {
+    constexpr int NTW = sizeof(T) >= 16 ? 512 : 1024;
+    if (g <= (unsigned)kCpqrWideMaxNodes)
+      cpqr_kernel<T, LDS_, GL_, RPL_, MCAP_, KCAP_, NTW><<<g, NTW, shm, st>>>(dbx, dhs, dl, p_os);
+    else
+      cpqr_kernel<T, LDS_, GL_, RPL_, MCAP_, KCAP_, 256><<<g, 256, shm, st>>>(dbx, dhs, dl, p_os);
+  }
   void cpqr_launch(const CompBox<T>* dbx, const HssDesc<T>* dhs, const int* dl, unsigned g, int lmax, int zmax,
                    bool in_lds, int p_os) {
     const size_t shm = (size_t)lmax * zmax * sizeof(T);
     if (lmax <= 64 && zmax <= 512) {
-      if (in_lds) cpqr_kernel<T, true, 8, 8, 512, 64><<<g, 256, shm, st>>>(dbx, dhs, dl, p_os);
-      else cpqr_kernel<T, false, 8, 8, 512, 64><<<g, 256, 0, st>>>(dbx, dhs, dl, p_os);
+      if (in_lds) cpqr_go<true, 8, 8, 512, 64>(dbx, dhs, dl, g, shm, p_os);
+      else cpqr_go<false, 8, 8, 512, 64>(dbx, dhs, dl, g, 0, p_os);
     } else if (lmax <= 256 && zmax <= 512) {
-      if (in_lds) cpqr_kernel<T, true, 16, 16, 512, 256><<<g, 256, shm, st>>>(dbx, dhs, dl, p_os);
-      else cpqr_kernel<T, false, 16, 16, 512, 256><<<g, 256, 0, st>>>(dbx, dhs, dl, p_os);
+      if (in_lds) cpqr_go<true, 16, 16, 512, 256>(dbx, dhs, dl, g, shm, p_os);
+      else cpqr_go<false, 16, 16, 512, 256>(dbx, dhs, dl, g, 0, p_os);
     } else {
       if (lmax > kLcapMax || zmax > 2 * kLcapMax) throw Error(HSS_EINVAL, "ID sample count above the supported maximum");
       constexpr int GLb = sizeof(T) >= 16 ? 32 : 16, RPLb = kLcapMax / GLb;

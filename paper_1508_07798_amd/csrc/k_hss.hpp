@@ -339,8 +339,8 @@ __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restric
 // of the column it updates in registers (GL * RPL >= l). MCAP bounds the number
 // of candidates m, KCAP the sample count l (and so the rank).
 constexpr int kMaxSwaps = 64;
-template <class T, bool LDS, int GL, int RPL, int MCAP, int KCAP>
-__global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict__ bx,
+template <class T, bool LDS, int GL, int RPL, int MCAP, int KCAP, int NT = 256>
+__global__ __launch_bounds__(NT) void cpqr_kernel(const CompBox<T>* __restrict__ bx,
                                                    const HssDesc<T>* __restrict__ hs,
                                                    const int* __restrict__ list, int p_os) {
   using R = typename traits<T>::real;
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
   const CompBox<T> b = bx[h.box];
   const int l = b.l;
   const int m = *h.k;
-  constexpr int NG = 256 / GL;
+  constexpr int NG = NT / GL;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* A = LDS ? (T*)smem_raw : h.Zw;  // l x m, ld = l
   __shared__ R s_nrm[2][MCAP];  // double buffered: read at step j, written for step j + 1
@@ -368,8 +368,8 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
   float tm = 0.f;
   for (int pass = 0, swaps = 0;; ++pass) {
     const bool forced = pass > 0;  // pivot order given by s_sel
-    for (int e = tid; e < l * m; e += 256) A[e] = h.Zt[e];
-    for (int c = tid; c < m; c += 256) s_pos[c] = -1;
+    for (int e = tid; e < l * m; e += NT) A[e] = h.Zt[e];
+    for (int c = tid; c < m; c += NT) s_pos[c] = -1;
     if (tid == 0) s_tm = 0u;
     __syncthreads();
     for (int c0 = 0; c0 < m; c0 += NG) {
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
     if (!(tm > 2.f) || swaps >= kMaxSwaps) break;
     // the swap: largest |T(i, c)|, then the lowest i, then the lowest c
     unsigned long long key = 0ull;
-    for (int e = tid; e < k * m; e += 256) {
+    for (int e = tid; e < k * m; e += NT) {
       const int i = e % k, c = e / k;
       if (s_pos[c] >= 0) continue;
       const float v = (float)sqrt((double)traits<T>::abs2(A[i + (size_t)c * l]));
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
     __syncthreads();
   }
   // U (m x k, ld zcap): row sel[i] = e_i, free row c = T(:, c)^T
-  for (int e = tid; e < m * k; e += 256) {
+  for (int e = tid; e < m * k; e += NT) {
     const int c = e % m, i = e / m;
     const int pos = s_pos[c];
     T v;
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(256) void cpqr_kernel(const CompBox<T>* __restrict_
     else v = A[i + (size_t)c * l];
     h.U[c + (size_t)i * h.zcap] = v;
   }
-  for (int i = tid; i < k; i += 256) h.skel[i] = h.cand[s_sel[i]];
+  for (int i = tid; i < k; i += NT) h.skel[i] = h.cand[s_sel[i]];
   if (tid == 0) atomicMax((int*)b.tmax, __float_as_int(tm));
   __syncthreads();
   if (tid == 0) {
