@@ -52,7 +52,7 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* _
   const int rl = tid & 63, part = tid >> 6;
   const int row = r0 + rl;
   __shared__ V xs[NR][256];
-  __shared__ V red[NR][NP][64];
+  __shared__ V red[NP][64];  // one right-hand side at a time: four workgroups fit a CU
   for (int rb = 0; rb < nrhs; rb += NR) {
     const int nr = min(NR, nrhs - rb);
     V acc[NR];
@@ -93,19 +93,20 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_kernel(const GemvDesc<T>* _
       }
     }
 #pragma unroll
-    for (int k = 0; k < NR; ++k) red[k][part][rl] = acc[k];
-    __syncthreads();
-    if (part == 0 && row < d.rows) {
-      const int64_t dst = d.out_off >= 0 ? d.out_off + row : d.out_idx[row];
-      for (int k = 0; k < nr; ++k) {
-        V s = red[k][0][rl];
-        for (int q = 1; q < NP; ++q) s = s + red[k][q][rl];
+    for (int k = 0; k < NR; ++k) {
+      if (k >= nr) break;  // nr is the same for the whole workgroup
+      red[part][rl] = acc[k];
+      __syncthreads();
+      if (part == 0 && row < d.rows) {
+        const int64_t dst = d.out_off >= 0 ? d.out_off + row : d.out_idx[row];
+        V s = red[0][rl];
+        for (int q = 1; q < NP; ++q) s = s + red[q][rl];
         V* yp = y + dst + (rb + k) * ld;
         if (tl.split) atomic_add_v(yp, sub == 1 ? -s : s);
         else *yp = sub == 1 ? (*yp - s) : sub == 2 ? (*yp + s) : s;
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
