@@ -133,6 +133,18 @@ struct Pinned {
   }
 };
 
+// Device copies of a plan's index arrays, in one block; the block goes back to
+// the process cache (as clean) when the plan goes, by which time every engine
+// that read it has synchronised its stream.
+struct PlanIndexDev {
+  void* base = nullptr;
+  size_t bytes = 0;
+  int32_t *row_ptr = nullptr, *col_idx = nullptr, *dof_elem = nullptr, *dof_prob = nullptr, *tblk = nullptr,
+          *src = nullptr;
+  int64_t *elem_dof = nullptr, *seg = nullptr, *perm = nullptr, *gidx = nullptr, *bpos = nullptr;
+  ~PlanIndexDev() { dev_free(base, bytes, nullptr); }
+};
+
 // Device memory of one phase: bump allocation from large chunks (few runtime
 // allocations), plus a staging region for host->device uploads of descriptor
 // arrays that are copied in one transfer per launch point.
@@ -1080,15 +1092,69 @@ template <class T> struct Engine : EngineBase {
     return ldu ? wo : 0;
   }
 
+  // The plan's index arrays on this device: uploaded by the first factorization
+  // on the device (one transfer, then a wait, so that engines on other streams
+  // may read them at once) and shared by every later one.
+  const PlanIndexDev& plan_index() {
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    Plan::DevCache& C = *P.dev_cache;
+    std::lock_guard<std::mutex> lk(C.mu);
+    for (const auto& sl : C.slots)
+      if (sl.dev == dev) return *static_cast<const PlanIndexDev*>(sl.data.get());
+    const PlanFlat& F = P.flat;
+    auto ix = std::make_shared<PlanIndexDev>();
+    struct Part {
+      const void* src;
+      size_t bytes, off;
+    };
+    std::vector<Part> parts;
+    size_t tot = 0;
+    auto place = [&](const auto& v) -> size_t {
+      const size_t b = v.size() * sizeof(v[0]);
+      parts.push_back({v.data(), b, tot});
+      const size_t o = tot;
+      tot += (b + 255) & ~size_t(255);
+      return b ? o : SIZE_MAX;
+    };
+    const size_t o_rp = place(F.row_ptr), o_ci = place(F.col_idx), o_ed = place(F.elem_dof), o_sg = place(F.seg),
+                 o_de = place(F.dof_elem), o_dp = place(F.dof_prob), o_pm = place(F.perm), o_tb = place(F.tblk),
+                 o_gi = place(F.gidx), o_sr = place(F.src), o_bp = place(F.bpos);
+    ix->bytes = std::max<size_t>(tot, 256);
+    ix->base = dev_alloc(ix->bytes, st);
+    char* b = (char*)ix->base;
+    auto at = [&](size_t o) -> char* { return o == SIZE_MAX ? nullptr : b + o; };
+    ix->row_ptr = (int32_t*)at(o_rp);
+    ix->col_idx = (int32_t*)at(o_ci);
+    ix->elem_dof = (int64_t*)at(o_ed);
+    ix->seg = (int64_t*)at(o_sg);
+    ix->dof_elem = (int32_t*)at(o_de);
+    ix->dof_prob = (int32_t*)at(o_dp);
+    ix->perm = (int64_t*)at(o_pm);
+    ix->tblk = (int32_t*)at(o_tb);
+    ix->gidx = (int64_t*)at(o_gi);
+    ix->src = (int32_t*)at(o_sr);
+    ix->bpos = (int64_t*)at(o_bp);
+    if (tot > 0) {
+      char* h = keep.get(tot);
+      for (const Part& pt : parts)
+        if (pt.bytes) std::memcpy(h + pt.off, pt.src, pt.bytes);
+      HIP_CHECK(hipMemcpyAsync(b, h, tot, hipMemcpyHostToDevice, st));
+    }
+    HIP_CHECK(hipStreamSynchronize(st));
+    C.slots.push_back({dev, std::shared_ptr<void>(ix, ix.get())});
+    return *ix;
+  }
+
+
   // ---------------------------------------------------------------- input check
   // Every value finite, and A(e, f) = A(f, e)^T to 1e-12 of the largest entry: the
   // compression takes the column bases equal to the row bases (V = U), which needs
   // symmetric (or complex-symmetric) complements. Checked on the device, so that
   // device-resident values are covered as well as host ones.
-  void validate_values(const PlanFlat& F) {
+  void validate_values(const int32_t* dt) {
     Arena t;
     t.st = st;
-    int32_t* dt = up(F.tblk, t);
     unsigned long long* dout = t.get<unsigned long long>(3);
     HIP_CHECK(hipMemsetAsync(dout, 0, 3 * sizeof(unsigned long long), st));
     fl();
@@ -1281,16 +1347,17 @@ template <class T> struct Engine : EngineBase {
       keep_g_ = P.find(0, o.keep_box);
       if (keep_g_ < 0) throw Error(HSS_EINVAL, "keep_box " + std::to_string(o.keep_box) + " is not a box of problem 0");
     }
-    // operator upload (FP64); the index arrays come precomputed with the plan
+    // operator upload (FP64); the index arrays are the plan's, on the device once
     const PlanFlat& F = P.flat;
+    const PlanIndexDev& ix = plan_index();
     {
-      d_row_ptr = up(F.row_ptr, persist);
-      d_col_idx = up(F.col_idx, persist);
+      d_row_ptr = ix.row_ptr;
+      d_col_idx = ix.col_idx;
       nnzb = (int64_t)F.col_idx.size();
-      d_elem_dof = up(F.elem_dof, persist);
-      d_seg_off = up(F.seg, persist);
-      d_dof_elem = up(F.dof_elem, persist);
-      d_dof_prob = up(F.dof_prob, persist);
+      d_elem_dof = ix.elem_dof;
+      d_seg_off = ix.seg;
+      d_dof_elem = ix.dof_elem;
+      d_dof_prob = ix.dof_prob;
       const size_t blk = (size_t)q * q;
       d_vals = persist.get<W>((size_t)nnzb * blk);
       for (int p = 0; p < nprob; ++p) {
@@ -1299,16 +1366,16 @@ template <class T> struct Engine : EngineBase {
         const hipMemcpyKind kind = A[p].vals_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
         HIP_CHECK(hipMemcpyAsync(d_vals + (size_t)pr.blk_off * blk, A[p].vals, nb_p * blk * sizeof(W), kind, st));
       }
-      d_perm = up(F.perm, persist);
-      validate_values(F);
+      d_perm = ix.perm;
+      validate_values(ix.tblk);
     }
     // per box index data and factor storage
     const int nn = (int)P.nodes.size();
     nd.assign(nn, NodeDev{});
     {
-      int64_t* dg = up(F.gidx, persist);
-      int32_t* ds = up(F.src, persist);
-      int64_t* db = up(F.bpos, persist);
+      int64_t* dg = ix.gidx;
+      int32_t* ds = ix.src;
+      int64_t* db = ix.bpos;
       T* fbase = persist.get<T>(std::max<size_t>(F.fsz, 1));
       int* pbase = persist.get<int>(std::max<size_t>(F.psz, 1));
       for (int g = 0; g < nn; ++g) {

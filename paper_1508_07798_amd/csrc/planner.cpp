@@ -339,6 +339,7 @@ Plan make_plan(int nprob, const hss_block_op_t* A, const hss_tree_t* T, int hss_
 }
 
 void flatten(Plan& P) {
+  P.dev_cache = std::make_shared<Plan::DevCache>();  // copies of older index arrays do not apply
   PlanFlat& F = P.flat;
   F = PlanFlat{};
   const int nprob = (int)P.probs.size();

@@ -22,6 +22,8 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -103,6 +105,18 @@ struct Plan {
   int64_t ndof_total = 0;
   int q_max = 0;
   PlanFlat flat;
+  // Device copies of flat's index arrays, one set per device, made by the first
+  // factorization on that device and shared by the later ones (the arrays depend
+  // on the structure only). The set's owner frees it when the plan goes.
+  struct DevSlot {
+    int dev;
+    std::shared_ptr<void> data;
+  };
+  struct DevCache {
+    std::mutex mu;
+    std::vector<DevSlot> slots;
+  };
+  std::shared_ptr<DevCache> dev_cache = std::make_shared<DevCache>();
   int find(int prob, int heap) const;
 };
 
