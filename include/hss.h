@@ -190,6 +190,9 @@ hss_status_t gmres_solve(hss_handle_t h, int32_t nrhs, const void* b, void* x, i
  * "bytes_apply", "bytes_spmv", "time_factor_ms", "host_wait_ms"
  * (time the factorization spent waiting for the device at its sync points),
  * "root_block" (block width of the roots' block LDU form; 0: explicit inverses),
+ * "cpqr_queue_launches" (truncated-QR launches that ran as a persistent work
+ * queue: HSS heights of more nodes than the device holds at once, when the
+ * environment sets HSS_CPQR_QUEUE=1; 0 otherwise),
  * "compress_host_ms" (4 values: host time of the compression attempts spent
  * building and uploading their lists, launching, waiting for the judge, and
  * deciding the next attempt),

@@ -55,22 +55,25 @@ void* dev_alloc(size_t n, hipStream_t st) {
   }
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, n);
-  if (e != hipSuccess) {
-    // release clean cached blocks and retry once
+  // the device is full: release clean cached blocks, the largest first, until the
+  // allocation fits (releasing all of them would make the next requests of the
+  // same factorization allocate and map their memory afresh)
+  while (e != hipSuccess) {
+    (void)hipGetLastError();
+    void* q = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_mu);
-      for (auto it = g_free.begin(); it != g_free.end();) {
-        if (it->st == nullptr) {
-          (void)hipFree(it->p);
-          it = g_free.erase(it);
-        } else {
-          ++it;
-        }
+      int big = -1;
+      for (size_t i = 0; i < g_free.size(); ++i)
+        if (g_free[i].st == nullptr && (big < 0 || g_free[i].n > g_free[big].n)) big = (int)i;
+      if (big >= 0) {
+        q = g_free[big].p;
+        g_free.erase(g_free.begin() + big);
       }
     }
-    (void)hipGetLastError();
+    if (!q) throw Error(HSS_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
+    (void)hipFree(q);
     e = hipMalloc(&p, n);
-    if (e != hipSuccess) throw Error(HSS_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
   }
   return p;
 }
@@ -366,6 +369,12 @@ template <class T> struct Engine : EngineBase {
   static constexpr int kLcapMax = 512;
   // CPQR launches of at most this many nodes (one per compute unit) run wide workgroups
   static constexpr int kCpqrWideMaxNodes = 256;
+  int n_cu = 256;              // compute units of the device
+  // HSS_CPQR_QUEUE=1: the work-queue form for heights of more nodes than the chip
+  // holds at once (off by default: the hardware dispatcher's own order measured as
+  // fast or faster on every workload here)
+  bool cpqr_queue_on = false;
+  int cpqr_queued_ = 0;        // CPQR launches of the last factorization in the work-queue form
   int* d_sing_ = nullptr;  // per box (then per root): 1 if a pivot was exactly zero
   double tol = 0;
   Prof prof;
@@ -507,6 +516,7 @@ template <class T> struct Engine : EngineBase {
     prof.st = st;
     if (const char* e = std::getenv("HSS_GJ_LOOKAHEAD_ABOVE")) la_above = std::atoi(e);
     if (const char* e = std::getenv("HSS_GEMM_BIG")) gemm_big_on = std::atoi(e) != 0;
+    if (const char* e = std::getenv("HSS_CPQR_QUEUE")) cpqr_queue_on = std::atoi(e) != 0;
     if (const char* e = std::getenv("HSS_GJ_BLOCK_WIDE"))
       block_wide = std::max(16, std::min(GJ_BLOCK_MAX, std::atoi(e) / 16 * 16));
     int dev = 0;
@@ -514,6 +524,7 @@ template <class T> struct Engine : EngineBase {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
       lds_max = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
     (void)hipGetLastError();
     q = P.probs[0].q;
     for (auto& pr : P.probs)
@@ -524,7 +535,9 @@ template <class T> struct Engine : EngineBase {
       for (const void* f : {(const void*)cpqr_kernel<T, true, 8, 8, 512, 64>,
                             (const void*)cpqr_kernel<T, true, 16, 16, 512, 256>,
                             (const void*)cpqr_kernel<T, true, 8, 8, 512, 64, NTW>,
-                            (const void*)cpqr_kernel<T, true, 16, 16, 512, 256, NTW>})
+                            (const void*)cpqr_kernel<T, true, 16, 16, 512, 256, NTW>,
+                            (const void*)cpqr_queue_kernel<T, true, 8, 8, 512, 64>,
+                            (const void*)cpqr_queue_kernel<T, true, 16, 16, 512, 256>})
         HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
       for (const void* f : {(const void*)gj_panel_kernel<T, true, 16>, (const void*)gj_panel_kernel<T, true, 32>,
                             (const void*)gj_panel_kernel<W, true, 16>, (const void*)gj_panel_kernel<W, true, 32>})
@@ -1394,6 +1407,7 @@ template <class T> struct Engine : EngineBase {
     err_v.assign(nn, 0.0);
     tmax_v.assign(nn, 0.f);
     fallbacks = retries = 0;
+    cpqr_queued_ = 0;
     flops_factor = 0;
     alg_sample = alg_cpqr = 0;
     host_wait_ms = 0;
@@ -1661,14 +1675,35 @@ template <class T> struct Engine : EngineBase {
     else
       cpqr_kernel<T, LDS_, GL_, RPL_, MCAP_, KCAP_, 256><<<g, 256, shm, st>>>(dbx, dhs, dl, p_os);
   }
+  // With cpqr_queue_on, launches of more nodes than the chip holds at once take
+  // the work-queue form: as many workgroups as fit, over the nodes in the order of
+  // dq (largest first), so that the largest start first and the short ones fill
+  // the tail. qnext: a zeroed counter of this launch's own.
+  template <bool LDS_, int GL_, int RPL_, int MCAP_, int KCAP_>
+  void cpqr_queue(const CompBox<T>* dbx, const HssDesc<T>* dhs, const int* dq, unsigned g, size_t shm, int* qnext,
+                  int p_os) {
+    auto* kf = cpqr_queue_kernel<T, LDS_, GL_, RPL_, MCAP_, KCAP_>;
+    int per_cu = 0;
+    HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, 256, shm));
+    const unsigned grid = std::min<unsigned>(g, (unsigned)std::max(1, per_cu) * (unsigned)n_cu);
+    kf<<<grid, 256, shm, st>>>(dbx, dhs, dq, (int)g, qnext, p_os);
+    ++cpqr_queued_;
+  }
   void cpqr_launch(const CompBox<T>* dbx, const HssDesc<T>* dhs, const int* dl, unsigned g, int lmax, int zmax,
-                   bool in_lds, int p_os) {
+                   bool in_lds, int p_os, const int* dq = nullptr, int* qnext = nullptr) {
     const size_t shm = (size_t)lmax * zmax * sizeof(T);
+    const bool queue = cpqr_queue_on && dq && qnext && g > (unsigned)kCpqrWideMaxNodes;
     if (lmax <= 64 && zmax <= 512) {
-      if (in_lds) cpqr_go<true, 8, 8, 512, 64>(dbx, dhs, dl, g, shm, p_os);
+      if (queue) {
+        if (in_lds) cpqr_queue<true, 8, 8, 512, 64>(dbx, dhs, dq, g, shm, qnext, p_os);
+        else cpqr_queue<false, 8, 8, 512, 64>(dbx, dhs, dq, g, 0, qnext, p_os);
+      } else if (in_lds) cpqr_go<true, 8, 8, 512, 64>(dbx, dhs, dl, g, shm, p_os);
       else cpqr_go<false, 8, 8, 512, 64>(dbx, dhs, dl, g, 0, p_os);
     } else if (lmax <= 256 && zmax <= 512) {
-      if (in_lds) cpqr_go<true, 16, 16, 512, 256>(dbx, dhs, dl, g, shm, p_os);
+      if (queue) {
+        if (in_lds) cpqr_queue<true, 16, 16, 512, 256>(dbx, dhs, dq, g, shm, qnext, p_os);
+        else cpqr_queue<false, 16, 16, 512, 256>(dbx, dhs, dq, g, 0, qnext, p_os);
+      } else if (in_lds) cpqr_go<true, 16, 16, 512, 256>(dbx, dhs, dl, g, shm, p_os);
       else cpqr_go<false, 16, 16, 512, 256>(dbx, dhs, dl, g, 0, p_os);
     } else {
       if (lmax > kLcapMax || zmax > 2 * kLcapMax) throw Error(HSS_EINVAL, "ID sample count above the supported maximum");
@@ -1871,6 +1906,20 @@ template <class T> struct Engine : EngineBase {
         n_stl[hh] = (unsigned)stl.size();
         n_utl[hh] = (unsigned)utl.size();
       }
+      // the CPQR's work queues (heights of more nodes than the chip holds at once):
+      // the nodes by decreasing l x zcap, and one zeroed counter per height
+      std::vector<int*> d_qlst(nh, nullptr);
+      int* qnext = nullptr;
+      for (int hh = 0; hh < nh; ++hh) {
+        if (!cpqr_queue_on || byh[hh].size() <= (size_t)kCpqrWideMaxNodes) continue;
+        std::vector<int> ql = byh[hh];
+        std::stable_sort(ql.begin(), ql.end(), [&](int a, int b) {
+          return (int64_t)bx[hs[a].box].l * hs[a].zcap > (int64_t)bx[hs[b].box].l * hs[b].zcap;
+        });
+        d_qlst[hh] = up(ql, at);
+        if (!qnext) qnext = at.get<int>(nh);
+      }
+      if (qnext) HIP_CHECK(hipMemsetAsync(qnext, 0, nh * sizeof(int), st));
       int* d_leaves = up(leaves, at);
       HTile* d_etl = etl.empty() ? nullptr : up(etl, at);
       HTile* d_mtl = mtl.empty() ? nullptr : up(mtl, at);
@@ -1903,7 +1952,8 @@ template <class T> struct Engine : EngineBase {
         check_launch("sample");
         id = prof.start(C_ID, 0, 0);
         rec_id[hh] = id;
-        cpqr_launch(dbx, dhs, d_lvl[hh], (unsigned)byh[hh].size(), lmax, zmax[hh], in_lds[hh], o.p_os);
+        cpqr_launch(dbx, dhs, d_lvl[hh], (unsigned)byh[hh].size(), lmax, zmax[hh], in_lds[hh], o.p_os, d_qlst[hh],
+                    qnext ? qnext + hh : nullptr);
         prof.stop(id);
       }
       for (int hh = 0; hh < nh; ++hh) {
@@ -2507,6 +2557,7 @@ template <class T> struct Engine : EngineBase {
     };
     if (key == "kept_n") out = {(double)kept_n_};
     else if (key == "root_block") out = {(double)root_wb_};
+    else if (key == "cpqr_queue_launches") out = {(double)cpqr_queued_};
     else if (key == "compress_host_ms")
       out = {compress_host_ms[0], compress_host_ms[1], compress_host_ms[2], compress_host_ms[3]};
     else if (key == "kept_S" || key == "kept_St") {

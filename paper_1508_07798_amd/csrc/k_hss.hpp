@@ -339,14 +339,13 @@ __global__ __launch_bounds__(256) void sample_kernel(const CompBox<T>* __restric
 // of the column it updates in registers (GL * RPL >= l). MCAP bounds the number
 // of candidates m, KCAP the sample count l (and so the rank).
 constexpr int kMaxSwaps = 64;
-template <class T, bool LDS, int GL, int RPL, int MCAP, int KCAP, int NT = 256>
-__global__ __launch_bounds__(NT) void cpqr_kernel(const CompBox<T>* __restrict__ bx,
-                                                   const HssDesc<T>* __restrict__ hs,
-                                                   const int* __restrict__ list, int p_os) {
+template <class T, bool LDS, int GL, int RPL, int MCAP, int KCAP, int NT>
+__device__ __forceinline__ void cpqr_node(const CompBox<T>* __restrict__ bx, const HssDesc<T>* __restrict__ hs,
+                                          int node, int p_os) {
   using R = typename traits<T>::real;
   static_assert(GL * RPL >= KCAP, "reflector rows per group");
   static_assert(MCAP <= 64 * 32, "pivot bit mask");
-  const HssDesc<T> h = hs[list[blockIdx.x]];
+  const HssDesc<T> h = hs[node];
   const CompBox<T> b = bx[h.box];
   const int l = b.l;
   const int m = *h.k;
@@ -534,6 +533,35 @@ __global__ __launch_bounds__(NT) void cpqr_kernel(const CompBox<T>* __restrict__
     *h.k = k;
     atomicMax(b.kmax, k);
     if (k < m && k + p_os > l) atomicOr(b.flags, 1);
+  }
+}
+
+// one workgroup per node of the list
+template <class T, bool LDS, int GL, int RPL, int MCAP, int KCAP, int NT = 256>
+__global__ __launch_bounds__(NT) void cpqr_kernel(const CompBox<T>* __restrict__ bx,
+                                                   const HssDesc<T>* __restrict__ hs,
+                                                   const int* __restrict__ list, int p_os) {
+  cpqr_node<T, LDS, GL, RPL, MCAP, KCAP, NT>(bx, hs, list[blockIdx.x], p_os);
+}
+
+// Persistent form over a work queue: a grid sized to what the chip holds at once
+// takes the n nodes of the list in its order (largest first), each workgroup
+// claiming the next one from *next (zero at launch) when it finishes the last.
+// Every workgroup leaves once the queue is drained.
+template <class T, bool LDS, int GL, int RPL, int MCAP, int KCAP>
+__global__ __launch_bounds__(256) void cpqr_queue_kernel(const CompBox<T>* __restrict__ bx,
+                                                         const HssDesc<T>* __restrict__ hs,
+                                                         const int* __restrict__ list, int n, int* __restrict__ next,
+                                                         int p_os) {
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(next, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();  // read by every thread before the next claim overwrites it
+    if (it >= n) break;
+    cpqr_node<T, LDS, GL, RPL, MCAP, KCAP, 256>(bx, hs, list[it], p_os);
+    __syncthreads();  // the node's LDS state is dead before the next node's set-up
   }
 }
 

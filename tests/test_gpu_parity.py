@@ -373,3 +373,28 @@ def test_plan_reuse_for_new_values():
     assert np.array_equal(y1, y2)
     # A -> 2A halves the preconditioner
     assert np.linalg.norm(2.0 * y2 - y0) <= 1e-10 * np.linalg.norm(y0)
+
+
+def test_cpqr_work_queue_matches_one_workgroup_per_node(monkeypatch):
+    """With HSS_CPQR_QUEUE=1 the truncated QR of HSS heights with more nodes than the
+    device holds at once runs as a persistent work queue (largest nodes first). Each node is still
+    factorized by one workgroup with the same arithmetic, so the ranks equal those
+    of the one-workgroup-per-node launch exactly and the applies agree to rounding
+    (the apply's split products add through atomics)."""
+    P = configs.make("helmholtz_p2_64")
+    vals = _t(P.op.vals)
+    kh = P.kappa / P.op.n if P.kappa else 0.0
+    hs = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("HSS_CPQR_QUEUE", mode)
+        hs[mode] = hss.factor(P.op, P.tree, P.tol, prec="fp32", seed=P.seed, vals_dev=vals, kappa_h=kh)
+    monkeypatch.delenv("HSS_CPQR_QUEUE")
+    print("queued launches", hs["1"].query("cpqr_queue_launches"), flush=True)
+    assert hs["0"].query("cpqr_queue_launches")[0] == 0
+    assert hs["1"].query("cpqr_queue_launches")[0] > 0
+    assert np.array_equal(hs["0"].query("ranks"), hs["1"].query("ranks"))
+    x = _t(np.random.default_rng(3).standard_normal(P.op.ndof) + 0j)
+    y0, y1 = hs["0"].apply(x).cpu().numpy(), hs["1"].apply(x).cpu().numpy()
+    assert np.linalg.norm(y1 - y0) <= 1e-12 * np.linalg.norm(y0)
+    for h in hs.values():
+        h.close()
