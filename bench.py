@@ -95,15 +95,16 @@ def sha256(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(cls):
+def measured_traffic(cls, workload):
     """HBM bytes per launch of `cls` from the committed counter summary, or None when
-    the summary covers another class or its kernel sources have changed since."""
+    the summary covers another class or workload, or its kernel sources have changed
+    since."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("class") != cls:
+    if t.get("class") != cls or t.get("workload") != workload:
         return None
     for rel, digest in t.get("sources", {}).items():
         if sha256(os.path.join(ROOT, rel)) != digest:
@@ -308,7 +309,7 @@ def main():
     tot = runs[-1]["table"][dom]
     roof = roofline_entry(dom, tot, fp64=False, bf16_schur=MIX == "bf16")
     roof["kernel"] = dom
-    roof["traffic"] = measured_traffic(dom)
+    roof["traffic"] = measured_traffic(dom, args.workload)
     flops_factor = runs[-1]["flops_factor"]
     t_factor = float(np.mean([r["t_factor"] for r in runs]))
     t_wait = float(np.mean([r["t_wait"] for r in runs]))

@@ -78,7 +78,7 @@ def main():
     out = {"class": a.cls, "kernel_regex": a.regex, "bytes_per_launch": fb + wb,
            "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "dispatches": nf,
            "copy_mib": a.copy_mib, "copy_fetch_kib": fref, "copy_write_kib": wref,
-           "fetch_scale": fscale, "write_scale": wscale, "sources": sources}
+           "fetch_scale": fscale, "write_scale": wscale, "sources": sources, "workload": a.workload}
     with open(a.json, "w") as f:
         json.dump(out, f, indent=1)
     with open(a.summary, "w") as f:
