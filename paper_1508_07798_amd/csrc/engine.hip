@@ -536,6 +536,8 @@ template <class T> struct Engine : EngineBase {
                             (const void*)cpqr_kernel<T, true, 16, 16, 512, 256>,
                             (const void*)cpqr_kernel<T, true, 8, 8, 512, 64, NTW>,
                             (const void*)cpqr_kernel<T, true, 16, 16, 512, 256, NTW>,
+                            (const void*)cpqr_kernel<T, true, 8, 8, 512, 64, 512>,
+                            (const void*)cpqr_kernel<T, true, 16, 16, 512, 256, 512>,
                             (const void*)cpqr_queue_kernel<T, true, 8, 8, 512, 64>,
                             (const void*)cpqr_queue_kernel<T, true, 16, 16, 512, 256>})
         HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
@@ -1664,14 +1666,17 @@ template <class T> struct Engine : EngineBase {
   // the CPQR variant for sample counts up to lmax and candidate counts up to zmax.
   // A launch of at most one node per compute unit takes wide workgroups (1,024
   // threads; 512 for 16-byte scalars, whose reflector rows would spill at 1,024):
-  // every step's column updates then take a quarter (half) of the passes. The
-  // result does not depend on the width: each column is still updated and
-  // reduced by one group of GL lanes, and every wave takes the same pivots.
+  // every step's column updates then take a quarter (half) of the passes; one of
+  // at most two nodes per compute unit takes 512 threads. The result does not
+  // depend on the width: each column is still updated and reduced by one group of
+  // GL lanes, and every wave takes the same pivots.
   template <bool LDS_, int GL_, int RPL_, int MCAP_, int KCAP_>
   void cpqr_go(const CompBox<T>* dbx, const HssDesc<T>* dhs, const int* dl, unsigned g, size_t shm, int p_os) {
     constexpr int NTW = sizeof(T) >= 16 ? 512 : 1024;
     if (g <= (unsigned)kCpqrWideMaxNodes)
       cpqr_kernel<T, LDS_, GL_, RPL_, MCAP_, KCAP_, NTW><<<g, NTW, shm, st>>>(dbx, dhs, dl, p_os);
+    else if (NTW > 512 && g <= 2u * kCpqrWideMaxNodes)  // two nodes per compute unit
+      cpqr_kernel<T, LDS_, GL_, RPL_, MCAP_, KCAP_, 512><<<g, 512, shm, st>>>(dbx, dhs, dl, p_os);
     else
       cpqr_kernel<T, LDS_, GL_, RPL_, MCAP_, KCAP_, 256><<<g, 256, shm, st>>>(dbx, dhs, dl, p_os);
   }
