@@ -58,8 +58,8 @@ template <class T> __device__ inline void split(T v, typename traits<T>::real& r
 constexpr int GBM = 64, GBN = 64;
 
 template <class T> struct gemm_cfg {
-  // K slab per LDS stage: 16 real or 8 complex values
-  static constexpr int BK = traits<T>::cplx ? 8 : 16;
+  // K slab per LDS stage: 16 real or complex64 values, 8 complex128 values
+  static constexpr int BK = traits<T>::cplx && sizeof(T) >= 16 ? 8 : 16;
 };
 
 // Role of a GEMM launch; it only separates the kernel symbols so that a profile
